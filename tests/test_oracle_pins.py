@@ -1,0 +1,552 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names the property it pins and the part of the oracle a plausible
+mistake would break.  Paper: arXiv:2604.25876; section / equation labels as
+in its source.  None of these tests touches the HIP library.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from skyr_inputs import random_unit_field
+import radial_reference as rr
+
+SQ3 = math.sqrt(3.0)
+
+
+def interior_mask(shape):
+    m = np.zeros(shape, dtype=bool)
+    m[2:-2, 2:-2, 2:-2] = True
+    return m
+
+
+def coords(n, h):
+    return (np.arange(n) - 0.5 * (n - 1)) * h
+
+
+# ----------------------------------------------------------------- stencils
+def test_first_difference_exact_on_quartics():
+    """Sec. 3 first-difference stencil: exact for polynomials of degree <= 4
+    along each axis (pins its coefficients and the 1/h placement)."""
+    n, h = 12, 0.3
+    x = coords(n, h)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    rng = np.random.default_rng(0)
+    c = rng.standard_normal((4, 5, 3))
+    phi = np.zeros((4, n, n, n))
+    dphi = np.zeros((3, 4, n, n, n))
+    for A in range(4):
+        for ax, V in enumerate((X, Y, Z)):
+            phi[A] += sum(c[A, k, ax] * V ** k for k in range(5))
+            dphi[ax, A] += sum(k * c[A, k, ax] * V ** (k - 1) for k in range(1, 5))
+    a = oracle.first_derivatives(phi, h)
+    I = interior_mask((n, n, n))
+    err = np.abs(a - dphi)[:, :, I].max()
+    assert err < 1e-11 * np.abs(dphi).max()
+    assert np.all(a[:, :, ~I] == 0.0)
+
+
+def test_second_difference_exact_on_quintics():
+    """Sec. 3 five-point second difference: exact for degree <= 5."""
+    n, h = 12, 0.25
+    x = coords(n, h)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    rng = np.random.default_rng(1)
+    c = rng.standard_normal((4, 6, 3))
+    phi = np.zeros((4, n, n, n))
+    lap = np.zeros((4, n, n, n))
+    for A in range(4):
+        for ax, V in enumerate((X, Y, Z)):
+            phi[A] += sum(c[A, k, ax] * V ** k for k in range(6))
+            lap[A] += sum(k * (k - 1) * c[A, k, ax] * V ** (k - 2) for k in range(2, 6))
+    L = oracle.laplacian(phi, h)
+    I = interior_mask((n, n, n))
+    assert np.abs(L - lap)[:, I].max() < 1e-10 * np.abs(lap).max()
+
+
+# ---------------------------------------------------------------- vacuum
+@pytest.mark.parametrize("m", [0.0, 0.7, 1.0])
+def test_vacuum(m):
+    """phi = (1,0,0,0): E = 0, B = 0, force 0; g = (-m^2, 0, 0, 0) on sites
+    whose stencils stay inside the interior (the mass term and signs)."""
+    n, h = 12, 0.3
+    phi = np.zeros((4, n, n, n))
+    phi[0] = 1.0
+    o = oracle.observables(phi, h, m)
+    assert o["E"] == 0.0 and o["B"] == 0.0 and o["max_force"] == 0.0
+    g = oracle.gradient(phi, h, m)
+    deep = np.zeros((n, n, n), dtype=bool)
+    deep[4:-4, 4:-4, 4:-4] = True
+    assert np.all(g[0][deep] == -m * m)
+    assert np.all(g[1:] == 0.0)
+    gT, r = oracle.project(phi, g)
+    assert r == 0.0
+
+
+def test_checkerboard_is_penalised_by_e2_only():
+    """The first-difference stencil is blind to the k = pi mode (its symbol
+    vanishes there), so the quartic term sees no gradient; the E2 term, built
+    with the five-point second difference, penalises it.  Pins the reading
+    that E2 uses the second-difference stencil."""
+    n, h = 14, 0.2
+    idx = np.arange(n)
+    par = (-1.0) ** (idx[:, None, None] + idx[None, :, None] + idx[None, None, :])
+    phi = np.zeros((4, n, n, n))
+    eps = 0.05
+    phi[0] = 1.0
+    phi[1] = eps * par
+    phi /= np.sqrt((phi ** 2).sum(0, keepdims=True))
+    I = interior_mask((n, n, n))
+    phi[:, ~I] = 0.0
+    phi[0, ~I] = 1.0
+    a = oracle.first_derivatives(phi, h)
+    inner = np.zeros((n, n, n), dtype=bool)
+    inner[4:-4, 4:-4, 4:-4] = True
+    assert np.abs(a[:, :, inner]).max() < 1e-15
+    E2, E4, E0 = oracle.energy_parts(phi, h, 0.0)
+    # per inner site: -1/2 phi.Lap phi = 1/2 (32/(6 h^2)) * 3 * (pion amplitude)^2 to leading order
+    assert E2 > 0.5 * 3 * (16.0 / 6.0) * (eps ** 2) / h ** 2 * h ** 3 * inner.sum()
+
+
+# ---------------------------------------------------------- h-homogeneity
+def test_h_homogeneity():
+    """At fixed lattice values E2 scales as h, E4 as 1/h, E0 as h^3, B as h^0
+    (pins where h enters each part)."""
+    n = 11
+    phi = random_unit_field((n, n, n), 7, 0.4)
+    h1, h2, m = 0.2, 0.35, 0.9
+    p1 = oracle.energy_parts(phi, h1, m)
+    p2 = oracle.energy_parts(phi, h2, m)
+    r = h2 / h1
+    assert p2[0] == pytest.approx(p1[0] * r, rel=1e-13)
+    assert p2[1] == pytest.approx(p1[1] / r, rel=1e-13)
+    assert p2[2] == pytest.approx(p1[2] * r ** 3, rel=1e-13)
+    assert oracle.baryon(phi, h2) == pytest.approx(oracle.baryon(phi, h1), rel=1e-12, abs=1e-14)
+
+
+# ------------------------------------------------------- exact gradient
+def _richardson_derivative(fun, eps):
+    d1 = (fun(eps) - fun(-eps)) / (2 * eps)
+    d2 = (fun(eps / 2) - fun(-eps / 2)) / eps
+    return (4 * d2 - d1) / 3
+
+
+def test_gradient_is_derivative_of_discrete_energy_bruteforce():
+    """The discrete gradient equals the finite-difference derivative of the
+    discrete energy, over every interior coordinate of a tiny lattice."""
+    n, h, m = 7, 0.33, 0.85
+    phi = random_unit_field((n, n, n), 11, 0.7)
+    g = oracle.gradient(phi, h, m)
+    I = interior_mask((n, n, n))
+    worst = 0.0
+    for x, y, z in zip(*np.nonzero(I)):
+        for A in range(4):
+            def fun(e, x=x, y=y, z=z, A=A):
+                p = phi.copy()
+                p[A, x, y, z] += e
+                return oracle.energy(p, h, m)
+            fd = _richardson_derivative(fun, 1e-3)
+            worst = max(worst, abs(fd - h ** 3 * g[A, x, y, z]) / (abs(fd) + 1e-3))
+    assert worst < 1e-8
+    assert np.all(g[:, ~I] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gradient_directional_and_tangent(seed):
+    """Random directions on a 10^3 lattice: dE/dt = h^3 sum g.xi; for tangent
+    directions (xi.phi = 0) the projected gradient gives the same rate."""
+    n = 10
+    rng = np.random.default_rng(seed)
+    h, m = 0.2 + 0.2 * rng.random(), rng.random()
+    phi = random_unit_field((n, n, n), 100 + seed, 0.5)
+    I = interior_mask((n, n, n))
+    g = oracle.gradient(phi, h, m)
+    gT, _ = oracle.project(phi, g)
+    xi = rng.standard_normal(phi.shape) * I
+    fun = lambda e: oracle.energy(phi + e * xi, h, m)
+    fd = _richardson_derivative(fun, 1e-4)
+    assert fd == pytest.approx(h ** 3 * np.sum(g * xi), rel=1e-9)
+    xt = xi - (xi * phi).sum(0, keepdims=True) * phi
+    assert np.sum(gT * xt) == pytest.approx(np.sum(g * xt), rel=1e-12)
+    fun_t = lambda e: oracle.energy(phi + e * xt, h, m)
+    assert _richardson_derivative(fun_t, 1e-4) == pytest.approx(h ** 3 * np.sum(gT * xt), rel=1e-9)
+
+
+def test_pointwise_gradient_matches_full():
+    n, h, m = 12, 0.27, 1.0
+    phi = random_unit_field((n, n, n), 5, 0.5)
+    g = oracle.gradient(phi, h, m)
+    for (x, y, z) in [(2, 2, 2), (2, 5, 9), (6, 6, 6), (9, 9, 9), (3, 8, 2)]:
+        np.testing.assert_allclose(oracle.gradient_at(phi, h, m, x, y, z), g[:, x, y, z], rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------- 1D reduction
+def test_one_dimensional_reduction():
+    """A field that depends on x only (also on the frozen y/z layers) has
+    S = G_xx, E4 = 0 and Q = 0, so the gradient reduces to the 1D five-point
+    Laplacian of the E2 term (with the half-weighted couplings to the frozen
+    x-layers) minus the mass term: a textbook 1D second difference."""
+    n, h, m = 16, 0.22, 0.6
+    x = coords(n, h)
+    theta = 1.2 * np.exp(-x ** 2)
+    phi = np.zeros((4, n, n, n))
+    phi[0] = np.cos(theta)[:, None, None]
+    phi[2] = np.sin(theta)[:, None, None]
+    E2, E4, E0 = oracle.energy_parts(phi, h, m)
+    assert abs(E4) < 1e-13 * E2
+    g = oracle.gradient(phi, h, m)
+    # 1D: L f(i) = sum_k c_k f(i+k) / h^2 with the five-point weights
+    c = np.array([-1 / 12, 4 / 3, -5 / 2, 4 / 3, -1 / 12]) / h ** 2
+    inside = np.zeros(n, dtype=bool)
+    inside[2:-2] = True
+    for A in range(4):
+        f = phi[A, :, 0, 0]
+        fI = np.where(inside, f, 0.0)
+        lap = np.convolve(f, c[::-1], mode="same")
+        lapI = np.convolve(fI, c[::-1], mode="same")
+        # y/z second differences of an x-only field: constant columns give 0
+        # (the full field); the masked field 1_I phi has y/z jumps at the faces
+        # that only the interior stencil rows near y/z faces see
+        ref = -0.5 * (lap + lapI) - (m * m if A == 0 else 0.0)
+        yz = 6  # a y/z position whose stencils stay inside the interior
+        np.testing.assert_allclose(g[A, 2:-2, yz, yz], ref[2:-2], rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------ symmetries
+def _random_rotation(rng, dim):
+    q, r = np.linalg.qr(rng.standard_normal((dim, dim)))
+    q *= np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def test_isospin_covariance():
+    """phi_pi -> R phi_pi with R in SO(3): E and B invariant, g covariant.
+    For m = 0 the full SO(4) acts."""
+    n, h = 10, 0.3
+    rng = np.random.default_rng(3)
+    phi = random_unit_field((n, n, n), 9, 0.6)
+    R = _random_rotation(rng, 3)
+    rot = phi.copy()
+    rot[1:] = np.einsum("ab,b...->a...", R, phi[1:])
+    for m in (0.0, 1.0):
+        assert oracle.energy(rot, h, m) == pytest.approx(oracle.energy(phi, h, m), rel=1e-13)
+        g, gr = oracle.gradient(phi, h, m), oracle.gradient(rot, h, m)
+        np.testing.assert_allclose(gr[1:], np.einsum("ab,b...->a...", R, g[1:]), atol=1e-11)
+        np.testing.assert_allclose(gr[0], g[0], atol=1e-11)
+    assert oracle.baryon(rot, h) == pytest.approx(oracle.baryon(phi, h), abs=1e-13)
+    Q = _random_rotation(rng, 4)
+    rot4 = np.einsum("ab,b...->a...", Q, phi)
+    # keep the frozen layers at the rotated vacuum: SO(4) moves the vacuum too
+    assert oracle.energy(rot4, h, 0.0) == pytest.approx(oracle.energy(phi, h, 0.0), rel=1e-12)
+    assert oracle.baryon(rot4, h) == pytest.approx(oracle.baryon(phi, h), abs=1e-12)
+
+
+def test_lattice_symmetries():
+    """Axis permutations and reflections i -> n-1-i leave E invariant; B
+    changes sign under a reflection or an odd permutation (axis independence
+    of the stencils, orientation of the determinant)."""
+    n, h, m = 11, 0.3, 1.0
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog(X=(0.1, -0.2, 0.05))])
+    E = oracle.energy(phi, h, m)
+    B = oracle.baryon(phi, h)
+    assert B > 0.3
+    swapped = np.ascontiguousarray(np.transpose(phi, (0, 2, 1, 3)))
+    flipped = np.ascontiguousarray(phi[:, ::-1])
+    cyc = np.ascontiguousarray(np.transpose(phi, (0, 2, 3, 1)))
+    for f, sgn in ((swapped, -1), (flipped, -1), (cyc, 1)):
+        assert oracle.energy(f, h, m) == pytest.approx(E, rel=1e-13)
+        assert oracle.baryon(f, h) == pytest.approx(sgn * B, rel=1e-12)
+    g = oracle.gradient(phi, h, m)
+    gs = oracle.gradient(swapped, h, m)
+    np.testing.assert_allclose(gs, np.transpose(g, (0, 2, 1, 3)), atol=1e-11)
+
+
+# ------------------------------------------------------ tangency and norm
+def test_flow_step_keeps_unit_norm_and_tangency():
+    """After each update |phi| = 1 to rounding, and the projected gradient is
+    orthogonal to phi."""
+    n, h, m = 16, 0.25, 1.0
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    g = oracle.gradient(phi, h, m)
+    gT, _ = oracle.project(phi, g)
+    dots = np.abs((gT * phi).sum(0))
+    assert dots.max() <= 8 * np.finfo(float).eps * np.abs(g).max()
+    out, vel, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, 0.02, 0.0, 5)
+    norm = np.sqrt((out ** 2).sum(0))
+    assert np.abs(norm - 1).max() <= 4 * np.finfo(float).eps
+    I = interior_mask((n, n, n))
+    assert np.all(out[:, ~I] == phi[:, ~I]) and np.all(vel[:, ~I] == 0)
+
+
+# ------------------------------------------------ hedgehog quadrature
+def test_hedgehog_energy_against_radial_quadrature():
+    """Unrelaxed hedgehog with the smooth profile f = pi (1 - tanh r): lattice
+    E2, E4, E0 and B converge to the radial integrals at fourth order."""
+    m = 1.0
+    f = lambda r: math.pi * (1 - math.tanh(r))
+    fp = lambda r: -math.pi / math.cosh(r) ** 2
+    ref = rr.hedgehog_parts(f, fp, m)
+    assert ref["B"] == pytest.approx(1.0, abs=1e-12)
+    errs = {}
+    for h in (0.3, 0.2, 0.15):
+        n = int(round(2 * 5.5 / h)) + 4
+        n += n % 2
+        x = coords(n, h)
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        fr = math.pi * (1 - np.tanh(r))
+        phi = np.stack([np.cos(fr), np.sin(fr) * X / r, np.sin(fr) * Y / r, np.sin(fr) * Z / r])
+        I = interior_mask((n, n, n))
+        phi[:, ~I] = 0.0
+        phi[0, ~I] = 1.0
+        o = oracle.observables(phi, h, m)
+        errs[h] = {k: o[k] - ref[k] for k in ("E2", "E4", "E0", "B")}
+    for k in ("E2", "E4", "B"):
+        order = math.log(abs(errs[0.2][k] / errs[0.15][k])) / math.log(0.2 / 0.15)
+        assert 3.3 < order < 4.7, (k, errs, order)
+        assert abs(errs[0.15][k]) < 2e-2 * max(abs(ref[k]), 1.0)
+    # no derivatives in E0: the lattice sum is a rectangle rule of a smooth,
+    # rapidly decaying integrand, exact up to the truncated tail
+    for h in errs:
+        assert abs(errs[h]["E0"]) < 1e-6 * ref["E0"]
+
+
+# -------------------------------------------- Newton flow (integrator)
+def test_plain_newton_flow_shadow_energy():
+    """Kick-drift order: with arrests off, E + K drifts at first order in dt,
+    and the shadow energy E + K - (dt/2) h^3 sum gT.v of the kick-drift map
+    drifts far less; swapping kick and drift would flip the sign that works."""
+    n, h, m = 20, 0.25, 1.0
+    phi0 = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    drift = {}
+    for dt in (0.01, 0.005):
+        phi, vel, st = phi0.copy(), np.zeros_like(phi0), oracle.AnfState.fresh()
+        H0, Hs = [], []
+        for k in range(int(round(0.2 / dt)) + 1):
+            E = oracle.energy(phi, h, m)
+            gT, _ = oracle.project(phi, oracle.gradient(phi, h, m))
+            K = 0.5 * h ** 3 * np.sum(vel * vel)
+            H0.append(E + K)
+            Hs.append(E + K - 0.5 * dt * h ** 3 * np.sum(gT * vel))
+            phi, vel, st, _, _ = oracle.anf(phi, vel, h, m, dt, 0.0, k + 1, st, arrest=False)
+        drift[dt] = (np.max(np.abs(np.array(H0) - H0[0])), np.max(np.abs(np.array(Hs) - Hs[0])))
+    assert 1.7 < drift[0.01][0] / drift[0.005][0] < 2.3
+    for dt in drift:
+        assert drift[dt][1] < drift[dt][0] / 30
+
+
+# --------------------------------------------------------- arrest trace
+def test_arrest_trace():
+    """Arrest fires exactly when E_n > E_{n-1}; after a reset the next
+    velocity is dt F (the reset happens before the kick)."""
+    n, h, m, dt = 20, 0.25, 1.0, 0.06
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    out, vel, st, Et, At = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, 80, trace=True)
+    assert st.steps == 80 and len(Et) == 80
+    assert At[0] == 0
+    for k in range(1, 80):
+        assert bool(At[k]) == bool(Et[k] > Et[k - 1])
+    assert st.arrests == At.sum() and st.arrests > 0
+    k = int(np.nonzero(At)[0][0])
+    st2 = oracle.AnfState.fresh()
+    p, v, st2, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, k, st2)
+    p2, v2, st2, _, _ = oracle.anf(p, v, h, m, dt, 0.0, k + 1, st2)
+    gT, _ = oracle.project(p, oracle.gradient(p, h, m))
+    np.testing.assert_allclose(v2, -dt * gT, atol=1e-15)
+
+
+def test_resume_equals_uninterrupted():
+    n, h, m, dt = 16, 0.25, 1.0, 0.04
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    a, va, sa, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, 30)
+    b, vb, sb, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, 13)
+    b, vb, sb, _, _ = oracle.anf(b, vb, h, m, dt, 0.0, 30, sb)
+    assert np.array_equal(a, b) and np.array_equal(va, vb)
+    assert sa.arrests == sb.arrests and sa.E_prev == sb.E_prev
+
+
+# --------------------------------------------------- initial data (Sec. 4)
+PAULI = [np.eye(2, dtype=complex), np.array([[0, 1], [1, 0]], dtype=complex),
+         np.array([[0, -1j], [1j, 0]], dtype=complex), np.array([[1, 0], [0, -1]], dtype=complex)]
+
+
+def _to_matrix(p):
+    """U = phi0 + i phi.tau as 2x2 complex matrices, p of shape (4, ...)."""
+    return (p[0][..., None, None] * PAULI[0]
+            + 1j * sum(p[k][..., None, None] * PAULI[k] for k in (1, 2, 3)))
+
+
+def test_hedgehog_is_rational_map_z():
+    """R(z) = z gives n_R = x/r (Sec. 4.1), so phi = (cos f, sin f x/r)."""
+    n, h = 10, 0.4
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog(prof_lambda=1.3)])
+    x = coords(n, h)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    f = math.pi * np.exp(-r / 1.3)
+    ref = np.stack([np.cos(f), np.sin(f) * X / r, np.sin(f) * Y / r, np.sin(f) * Z / r])
+    I = interior_mask((n, n, n))
+    np.testing.assert_allclose(phi[:, I], ref[:, I], atol=2e-15)
+    assert np.all(phi[0, ~I] == 1.0) and np.all(phi[1:, ~I] == 0.0)
+
+
+def test_product_and_isorotation_against_pauli_matrices():
+    """The quaternion product and D(A) used for the product ansatz agree with
+    explicit 2x2 matrix products U = U1 (A U2 A^dagger) (Sec. 4.2, Sec. 5.3)."""
+    n, h = 8, 0.5
+    rng = np.random.default_rng(4)
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    c1 = oracle.hedgehog(X=(0.4, -0.3, 0.2))
+    c2 = oracle.cube_b4(X=(-0.5, 0.1, 0.3), prof_lambda=0.8)
+    c2q = oracle.cube_b4(X=(-0.5, 0.1, 0.3), prof_lambda=0.8, quat=q)
+    U1 = _to_matrix(oracle.init_product((n, n, n), h, [c1]))
+    U2 = _to_matrix(oracle.init_product((n, n, n), h, [c2]))
+    A = q[0] * PAULI[0] + 1j * sum(q[k] * PAULI[k] for k in (1, 2, 3))
+    ref = U1 @ (A @ U2 @ A.conj().T)
+    got = _to_matrix(oracle.init_product((n, n, n), h, [c1, c2q]))
+    np.testing.assert_allclose(got, ref, atol=1e-14)
+
+
+def test_isorotation_matrix_is_half_trace_formula():
+    """D(A)_ij = 1/2 Tr(tau_i A tau_j A^dagger) (Sec. 5.3) equals the
+    rotation applied to the pion components of a rotated hedgehog."""
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    A = q[0] * PAULI[0] + 1j * sum(q[k] * PAULI[k] for k in (1, 2, 3))
+    D = np.array([[0.5 * np.trace(PAULI[i] @ A @ PAULI[j] @ A.conj().T).real for j in (1, 2, 3)]
+                  for i in (1, 2, 3)])
+    n, h = 8, 0.5
+    plain = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    rot = oracle.init_product((n, n, n), h, [oracle.hedgehog(quat=q)])
+    np.testing.assert_allclose(rot[1:], np.einsum("ij,j...->i...", D, plain[1:]), atol=1e-14)
+    np.testing.assert_allclose(rot[0], plain[0], atol=1e-15)
+
+
+def test_cube_rational_map_charge_and_symmetry():
+    """Table RMA: the B = 4 map has O_h symmetry and the lattice field carries
+    a charge that approaches 4 as h shrinks (the unrelaxed core is a cone, so
+    the approach is slow); its energy is invariant under axis permutations."""
+    n, h = 40, 0.15
+    phi = oracle.init_product((n, n, n), h, [oracle.cube_b4(prof_lambda=1.0)])
+    coarse = oracle.init_product((30, 30, 30), 0.2, [oracle.cube_b4(prof_lambda=1.0)])
+    B, Bc = oracle.baryon(phi, h), oracle.baryon(coarse, 0.2)
+    assert B == pytest.approx(4.0, abs=0.2)
+    assert abs(B - 4.0) < abs(Bc - 4.0)
+    E = oracle.energy(phi, h, 1.0)
+    for perm in ((0, 2, 1, 3), (0, 3, 2, 1), (0, 2, 3, 1)):
+        assert oracle.energy(np.ascontiguousarray(np.transpose(phi, perm)), h, 1.0) == pytest.approx(E, rel=1e-12)
+
+
+def test_product_ansatz_charge_is_additive():
+    """Sec. 4.2: the product of separated constituents carries the sum of
+    their charges (up to the lattice error of each core); a charge times an
+    anti-charge (profile running from -pi to 0) carries B = 0."""
+    n, h = 52, 0.2
+    a = oracle.hedgehog(X=(-2.6, 0.0, 0.0), prof_lambda=0.7)
+    b = oracle.hedgehog(X=(2.6, 0.0, 0.0), prof_lambda=0.7, quat=(0.0, 0.0, 1.0, 0.0))
+    anti = oracle.hedgehog(X=(2.6, 0.0, 0.0), prof_a=-math.pi, prof_lambda=0.7)
+    B = {k: oracle.baryon(oracle.init_product((n, n, n), h, cs), h)
+         for k, cs in (("a", [a]), ("b", [b]), ("anti", [anti]), ("ab", [a, b]), ("a_anti", [a, anti]))}
+    assert B["a"] == pytest.approx(1.0, abs=0.05) and B["anti"] == pytest.approx(-B["b"], abs=1e-12)
+    assert B["ab"] == pytest.approx(B["a"] + B["b"], abs=5e-3)
+    assert B["a_anti"] == pytest.approx(0.0, abs=5e-3)
+
+
+# ------------------------------------------------------------ random draws
+def test_splitmix64_known_answers():
+    """SplitMix64 (Steele, Lea, Flood 2014): the published outputs for seed 1234567."""
+    assert [oracle.splitmix64(1234567, k) for k in range(5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+        16408922859458223821]
+
+
+def test_random_constituents_properties():
+    """Centres lie in the ball, quaternions are unit, and over many draws the
+    Shoemake quaternions have E[q] = 0 and E[q_i^2] = 1/4 (Haar measure)."""
+    cs = oracle.random_constituents(42, 4000, radius=3.0)
+    X = np.array([list(c.X) for c in cs])
+    q = np.array([list(c.quat) for c in cs])
+    assert np.all(np.linalg.norm(X, axis=1) <= 3.0)
+    np.testing.assert_allclose(np.linalg.norm(q, axis=1), 1.0, atol=1e-15)
+    assert np.abs(q.mean(0)).max() < 0.03
+    np.testing.assert_allclose((q ** 2).mean(0), 0.25, atol=0.015)
+    # uniform in the ball: E|X|^2 = 3/5 R^2
+    assert (X ** 2).sum(1).mean() == pytest.approx(0.6 * 9.0, rel=0.03)
+    assert all(c.degree == 1 for c in cs)
+
+
+# ------------------------------------------------- the literal EL form
+def test_literal_euler_lagrange_agrees_to_fourth_order():
+    """The paper's printed field equation, halved and evaluated with the
+    five-point second difference and D_i D_j mixed derivatives, differs from
+    the exact discrete gradient by O(h^4) on a smooth field (the reading that
+    the flow uses the derivative of the discrete energy)."""
+    m = 1.0
+    diffs = {}
+    for h in (0.1, 0.05):
+        n = int(round(2 * 3.0 / h)) + 4
+        n += n % 2
+        x = coords(n, h)
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        f = math.pi * (1 - np.tanh(r / 1.5))
+        phi = np.stack([np.cos(f), np.sin(f) * X / r, np.sin(f) * Y / r, np.sin(f) * Z / r])
+        gx, _ = oracle.project(phi, oracle.gradient(phi, h, m))
+        gl, _ = oracle.project(phi, oracle.gradient_literal(phi, h, m))
+        core = r < 2.0
+        diffs[h] = np.abs(gx - gl)[:, core].max()
+    order = math.log(diffs[0.1] / diffs[0.05]) / math.log(2.0)
+    assert 3.5 < order < 4.5, diffs
+
+
+# ---------------------------------------------------- relaxed solutions
+def test_radial_reference_reproduces_massless_skyrmion():
+    """The radial minimiser gives the textbook massless B = 1 energy
+    E/(12 pi^2) = 1.2314 in the printed normalisation (6 pi^2 here)."""
+    assert rr.radial_minimum(0.0, R=60.0) / (6 * math.pi ** 2) == pytest.approx(1.23145, abs=2e-5)
+
+
+def test_relaxed_unit_skyrmion_small():
+    """Relaxing the hedgehog on a coarse lattice (h = 0.2) reaches the
+    tolerance, keeps B near 1 and lands within 2% of the radial minimum."""
+    n, h, m = 44, 0.2, 1.0
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    out, vel, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, 0.02, 1e-3, 3000)
+    assert st.converged == 1
+    o = oracle.observables(out, h, m)
+    assert o["B"] == pytest.approx(1.0, abs=0.03)
+    assert o["E"] == pytest.approx(rr.radial_minimum(m), rel=0.02)
+
+
+@pytest.mark.slow
+def test_relaxed_unit_skyrmion_converges_at_fourth_order():
+    """Relaxed B = 1 (m = 1) at h = 0.2, 0.15, 0.1: the energy approaches the
+    radial minimum, B approaches 1 and the Derrick virial E2 - E4 + 3 E0
+    approaches 0, each at about fourth order in h."""
+    m, L = 1.0, 6.0
+    res = {}
+    for h in (0.2, 0.15, 0.1):
+        n = int(round(2 * L / h)) + 4
+        n += n % 2
+        phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+        out, vel, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, 0.1 * h, 1e-4, 8000)
+        assert st.converged == 1
+        res[h] = oracle.observables(out, h, m)
+    Estar = rr.radial_minimum(m)
+    eE = {h: res[h]["E"] - Estar for h in res}
+    eB = {h: res[h]["B"] - 1.0 for h in res}
+    eV = {h: res[h]["virial"] for h in res}
+    for e in (eE, eB, eV):
+        order = math.log(abs(e[0.15] / e[0.1])) / math.log(1.5)
+        assert 3.0 < order < 5.0, (e, order)
+    assert abs(eB[0.1]) < 1e-3
+    assert abs(eV[0.1]) / res[0.1]["E"] < 3e-3
+    # Richardson extrapolation at fourth order agrees with the radial minimum
+    Ex = res[0.1]["E"] + (res[0.1]["E"] - res[0.15]["E"]) / (1.5 ** 4 - 1)
+    assert Ex == pytest.approx(Estar, rel=1e-4)
