@@ -1,0 +1,163 @@
+"""Throughput of the arrested Newton flow on one MI355X.
+
+Workload: the 256^3 lattice (h = 0.1, m = 1) holding the product ansatz of
+10 unit charges at seeded random centres in a radius-3 ball with Haar-random
+isorotations (seed 1), profile f = pi exp(-r); time step dt = 0.01.  One
+"step" is one accepted arrested-Newton-flow step over the whole lattice: the
+fused sweep (derivatives, energy, exact gradient, projection, kick-drift,
+renormalisation, FP64 partial sums) plus the device-side arrest decision.
+
+The JSON line reports the FP32-bulk flow as `value` (site-updates/s, one
+site-update = one interior site advanced by one accepted step) and the plain
+FP64 flow beside it, the roofline of the sweep kernel (HBM bytes per site from
+the algorithm, kernel time from HIP events around each sweep launch), and the
+FP64 CPU oracle timed on a bounded sample on the host cores.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "site-updates/s FP32-bulk vs FP64 flow at 256³; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per interior site and sweep: read phi and v, write phi' and v'
+BYTES_PER_SITE = {"f32": 4 * 4 * 4, "f64": 4 * 4 * 8}
+
+
+def run_flow(skyr, torch, w, prec_name, steps, warmup):
+    prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
+    n, h = w["n"], w["h"]
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(w["init"])
+    dev = torch.device("cuda:0")
+    phi = skyr.new_field(lat, prec, dev)
+    skyr.init_field(lat, prec, spec, phi)
+    alt, vel = skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
+    work = skyr.new_workspace(lat, prec, dev)
+    model = skyr.Model(w["m"])
+    # tolerance 0: every call runs exactly its steps
+    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, warmup, work)
+    torch.cuda.synchronize()
+    s0, sw0, ar0 = st.steps, st.sweeps, st.arrests
+    skyr.timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, steps, work)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms, sweep_n = skyr.timing_read()
+    skyr.timing_enable(False)
+    done = st.steps - s0
+    interior = (n - 4) ** 3
+    elapsed = ev0.elapsed_time(ev1) / 1e3
+    kernel_avg_s = sweep_ms / 1e3 / max(sweep_n, 1)
+    bytes_launch = BYTES_PER_SITE[prec_name] * interior
+    achieved = bytes_launch / kernel_avg_s / 1e9
+    obs = skyr.observables(lat, prec, model, phi, work)
+    return dict(
+        prec=prec_name, steps=done, sweeps=st.sweeps - sw0, arrests=st.arrests - ar0, wall_s=wall,
+        elapsed_s=elapsed, site_updates_per_s=done * interior / elapsed, ms_per_step=1e3 * elapsed / max(done, 1),
+        sweep_kernel_avg_us=kernel_avg_s * 1e6, sweep_launches=sweep_n, bytes_per_launch=bytes_launch,
+        achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"])
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle (as it stands) on the host cores: a few flow steps of the
+    same 256^3 initial field, scaled to site-updates/s."""
+    import math
+
+    import numpy as np
+
+    import oracle
+    n, h = w["n"], w["h"]
+    init = w["init"]
+    cs = oracle.random_constituents(init["seed"], init["B"], init["radius"], math.pi, init["prof_lambda"])
+    phi = oracle.init_product((n, n, n), h, cs)
+    vel = np.zeros_like(phi)
+    st = oracle.AnfState.fresh()
+    t0 = time.perf_counter()
+    phi, vel, st, _, _ = oracle.anf(phi, vel, h, w["m"], w["dt"], 0.0, 1, st)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(20, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    phi, vel, st, _, _ = oracle.anf(phi, vel, h, w["m"], w["dt"], 0.0, 1 + k, st)
+    tk = time.perf_counter() - t0
+    interior = (n - 4) ** 3
+    return {"value": k * interior / tk, "unit": "site-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} FP64 flow steps of the same {n}^3 random B=10 field after 1 untimed step "
+                      f"({tk:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the flow of one lattice is not sharded across GPUs here "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_25876_amd import skyr
+    from skyr_inputs import RANDOM_B10_256 as W
+
+    skyr.lib()
+    r32 = run_flow(skyr, torch, W, "f32", args.steps, args.warmup)
+    print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
+    r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup)
+    print(f"# f64: {r64}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(W)
+        print(f"# cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": r32["site_updates_per_s"],
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "n": W["n"], "h": W["h"], "m": W["m"], "dt": W["dt"],
+                   "init": W["init"], "precision": "f32-bulk (f64 sums, arrest test, renormalisation every 16)",
+                   "interior_sites": (W["n"] - 4) ** 3},
+        "f64_flow": {"value": r64["site_updates_per_s"], "ms_per_step": r64["ms_per_step"],
+                     "sweep_kernel_avg_us": r64["sweep_kernel_avg_us"], "achieved_GBs": r64["achieved_GBs"],
+                     "arrests": r64["arrests"], "sweeps": r64["sweeps"]},
+        "speedup_f32_over_f64": r32["site_updates_per_s"] / r64["site_updates_per_s"],
+        "sweeps": r32["sweeps"],
+        "arrests": r32["arrests"],
+        "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep_kernel<float> (step mode)",
+                     "kernel_avg_us": r32["sweep_kernel_avg_us"], "bytes_per_launch": r32["bytes_per_launch"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * skyr.h -- C ABI of the MI355X arrested-Newton-flow library for the 3D Skyrme
+ * model in the sigma-model (unit 4-vector) form, arXiv:2604.25876.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Field layout.  A field is four real components per lattice site stored as
+ *   structure of arrays  phi[A][x][y][z],  A = 0..3,  z fastest,
+ * n[0] x n[1] x n[2] sites per component, contiguous, in double (SKYR_F64) or
+ * float (SKYR_F32_BULK).  U = phi^0 + i phi^a tau^a (Sec. 2.1).
+ * Coordinates x_i = (i - (n-1)/2) h.  The two outer layers of every face are
+ * frozen boundary values (vacuum (1,0,0,0) after skyr_init_field) and are never
+ * written by the flow; the interior I = {2..n-3}^3 carries energy, charge and
+ * the update.
+ *
+ * Discrete energy (Sec. 2.1 energy density at one half of the printed
+ * normalisation, discretised with the two fourth-order stencils of Sec. 3):
+ *   E_h = h^3 sum_{x in I} [ -1/2 phi.Lap_h phi + 1/4 (S^2 - sum_ij G_ij^2)
+ *                            + m^2 (1 - phi^0) ]
+ * with a_i = D_i phi (first-difference stencil), G_ij = a_i.a_j, S = tr G and
+ * Lap_h the sum of the five-point second differences.  The gradient returned
+ * and used by the flow is the exact derivative of E_h, in density units
+ * (g = h^-3 dE_h/dphi).
+ *
+ * Memory.  Every field, velocity, gradient and workspace pointer is DEVICE
+ * memory owned by the caller; the library never allocates or frees it.  Host
+ * structs are borrowed for the duration of a call.  `stream` is a hipStream_t
+ * (NULL = the default stream); device work is enqueued on it, and calls with
+ * host outputs synchronise it before returning.
+ *
+ * Errors.  Every entry point returns a skyr_status.  Arguments are validated
+ * before any device work: null required pointers, any n < 5, h <= 0, dt <= 0,
+ * or a lattice whose component exceeds 2^31 sites give SKYR_E_INVAL with no
+ * side effect.  HIP failures give SKYR_E_DEVICE.  skyr_last_error() returns a
+ * thread-local message describing the last failure of the calling thread.
+ * Calls are re-entrant on distinct buffers, workspaces and streams.
+ */
+#ifndef SKYR_H
+#define SKYR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* exported symbols of libskyr.so */
+#define SKYR_API __attribute__((visibility("default")))
+
+typedef enum {
+    SKYR_OK = 0,
+    SKYR_E_INVAL = -1,     /* invalid argument; nothing was done            */
+    SKYR_E_NOMEM = -2,     /* workspace too small / host allocation failed  */
+    SKYR_E_DEVICE = -3,    /* a HIP call failed                              */
+    SKYR_E_NONFINITE = -4, /* energy or force stopped being finite           */
+    SKYR_E_BUSY = -5       /* batch slot table full                          */
+} skyr_status;
+
+typedef enum {
+    SKYR_F64 = 0,      /* fields, velocities and stencils in double                        */
+    SKYR_F32_BULK = 1  /* fields, velocities and stencils in float; energy and charge sums,
+                          the arrest comparison and a periodic renormalisation in double  */
+} skyr_precision;
+
+/* Uniform cubic lattice (Sec. 3): n sites per axis (frozen layers included), spacing h. */
+typedef struct {
+    int32_t n[3];
+    int32_t _pad;
+    double h;
+} skyr_lattice;
+
+/* Rescaled pion mass m (Sec. 2, m = 2 m_pi / (F_pi e)). */
+typedef struct {
+    double m;
+} skyr_model;
+
+/* Arrested Newton flow controls (Sec. 3).
+ *   dt             fictitious time step (kick-drift step)
+ *   tol            stop when max over I of |F| < tol, F the projected force
+ *   max_steps      total cap on accepted steps across calls
+ *   renorm64_every SKYR_F32_BULK only: every this many steps the renormalisation
+ *                  phi <- phi/|phi| is done in double (0 = never; default 16) */
+typedef struct {
+    double dt;
+    double tol;
+    int64_t max_steps;
+    int32_t renorm64_every;
+    int32_t _pad;
+} skyr_flow;
+
+/* Initial data (Sec. 4). */
+typedef enum {
+    SKYR_INIT_HEDGEHOG = 0,       /* B = 1 at the origin, R(z) = z                           */
+    SKYR_INIT_RATIONAL_MAP = 1,   /* c[0]: one rational map constituent                      */
+    SKYR_INIT_PRODUCT = 2,        /* c[0..count): product ansatz, left to right               */
+    SKYR_INIT_RANDOM_PRODUCT = 3  /* B unit charges drawn from `seed` (skyr_random_constituents) */
+} skyr_init_kind;
+
+/* One constituent of a product (Sec. 4.1, 4.2): the degree-`degree` rational
+ * map R = p/q (p(z) = sum_k p[k] z^k, complex coefficients as (re, im)),
+ * profile f(r) = prof_a exp(-r / prof_lambda), centre X, and isorotation by the
+ * unit quaternion quat = (a0, a1, a2, a3), A = a0 + i a.tau, U -> A U A^dagger. */
+typedef struct {
+    int32_t degree; /* 1..8 */
+    int32_t _pad;
+    double p[9][2];
+    double q[9][2];
+    double X[3];
+    double quat[4];
+    double prof_a;
+    double prof_lambda;
+} skyr_constituent;
+
+typedef struct {
+    int32_t kind;                /* skyr_init_kind                                          */
+    int32_t count;               /* SKYR_INIT_PRODUCT: number of constituents in c (1..64)  */
+    const skyr_constituent* c;   /* host array; RATIONAL_MAP uses c[0]                      */
+    int32_t B;                   /* SKYR_INIT_RANDOM_PRODUCT: number of unit charges (1..64) */
+    int32_t _pad;
+    uint64_t seed;               /* SKYR_INIT_RANDOM_PRODUCT                                */
+    double ball_radius;          /* SKYR_INIT_RANDOM_PRODUCT: centres uniform in this ball  */
+    double prof_a;               /* HEDGEHOG, RANDOM_PRODUCT profile amplitude (pi)         */
+    double prof_lambda;          /* HEDGEHOG, RANDOM_PRODUCT profile length                  */
+} skyr_init_spec;
+
+/* Observables (Sec. 2.1, 5.6): E = E2 + E4 + E0; B = h^3 sum_I b with
+ * b = -(1/2 pi^2) det[phi, a_1, a_2, a_3] (the sign that gives the hedgehog with
+ * f(0) = pi charge +1); virial = E2 - E4 + 3 E0 (zero for a Derrick-stationary
+ * field); max_force = max over I of |F|, F = -(g - (g.phi) phi). */
+typedef struct {
+    double E, E2, E4, E0, B, virial, max_force;
+} skyr_obs;
+
+/* State of an arrested Newton flow, carried across skyr_anf_step calls.
+ * Initialise with skyr_anf_state_init (E_prev = +inf, counters 0) and start
+ * from zero velocity. */
+typedef struct {
+    int64_t steps;        /* accepted updates                                        */
+    int64_t arrests;      /* velocity resets (E(phi_k) > E(phi_{k-1}))                */
+    int64_t redo_sweeps;  /* sweeps recomputed with zero velocity after an arrest     */
+    int64_t sweeps;       /* all sweeps run (accepted + redone + final check)         */
+    double E_prev;        /* E(phi_{steps-1}); +inf before the first update           */
+    double E;             /* energy of the field at the last evaluated sweep          */
+    double max_force;     /* max |F| at the last evaluated sweep                      */
+    int32_t converged;    /* 1 once max_force < tol; the returned field is that one   */
+    int32_t redo_pending; /* the next sweep re-runs the last field with zero velocity */
+    int32_t nonfinite;    /* 1 if E or max_force stopped being finite                  */
+    int32_t _pad;
+} skyr_anf_state;
+
+/* Library version string. */
+SKYR_API const char* skyr_version(void);
+
+/* Thread-local description of the last error of the calling thread ("" if none). */
+SKYR_API const char* skyr_last_error(void);
+
+/* Bytes of device workspace needed by skyr_energy_gradient, skyr_anf_step and
+ * skyr_observables for this lattice and precision (0 on invalid arguments).
+ * The workspace holds the flow's control block and one block of partial sums
+ * per thread block; it must be 256-byte aligned and not shared by calls that
+ * overlap in time. */
+SKYR_API size_t skyr_workspace_bytes(const skyr_lattice* lat, skyr_precision prec);
+
+/* The B unit-charge constituents of SKYR_INIT_RANDOM_PRODUCT, drawn on the
+ * host (smorgasbord-style data, Sec. 4.2): SplitMix64 (Steele, Lea, Flood 2014)
+ * seeded with `seed`; per constituent, centre by rejection from the cube
+ * [-R, R]^3 until |X| <= R (three uniforms per attempt), then a Haar-random
+ * quaternion by Shoemake's method from three more uniforms,
+ * (sqrt(1-u1) sin 2pi u2, sqrt(1-u1) cos 2pi u2, sqrt(u1) sin 2pi u3, sqrt(u1) cos 2pi u3);
+ * uniforms are the top 53 bits times 2^-53.  out: host array of B entries. */
+SKYR_API skyr_status skyr_random_constituents(uint64_t seed, int32_t B, double radius, double prof_a, double prof_lambda,
+                                     skyr_constituent* out);
+
+/* Fill phi (device, layout above) with initial data (Sec. 4): the product
+ * U = prod_k A_k U_k(x - X_k) A_k^dagger (eq. Product ansatz) of rational-map
+ * fields U_k = exp(i f(r) n_R . tau) (Sec. 4.1), evaluated in double and
+ * rounded to the field precision; frozen layers set to vacuum.  Enqueued on
+ * `stream`; returns without waiting. */
+SKYR_API skyr_status skyr_init_field(const skyr_lattice* lat, skyr_precision prec, const skyr_init_spec* spec, void* phi,
+                            void* stream);
+
+/* Discrete gradient of E_h at phi (Sec. 3, eq. Newton_flow and the
+ * Euler-Lagrange expression it projects; here the exact derivative of E_h).
+ *   grad       nullable device output, layout of phi: g (projected = 0) or the
+ *              tangential part g - (g.phi) phi (projected = 1); zero on the
+ *              frozen layers
+ *   parts      nullable host output: E, E2, E4, E0, virial and max_force
+ *              (B is not computed here and is set to 0)
+ *   work       device workspace of skyr_workspace_bytes(lat, prec) bytes
+ * Synchronises `stream` when parts is non-null. */
+SKYR_API skyr_status skyr_energy_gradient(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                 const void* phi, void* grad, int32_t projected, skyr_obs* parts, void* work,
+                                 void* stream);
+
+/* Reset a flow state: counters 0, E_prev = +inf, no redo pending. */
+SKYR_API void skyr_anf_state_init(skyr_anf_state* st);
+
+/* Advance the arrested Newton flow (Sec. 3) by up to nsteps accepted steps.
+ * Step k, from (phi_k, v_k):
+ *   E_k = E_h(phi_k); if E_k > E_{k-1} the velocity is reset (arrest, v_k := 0)
+ *   F_k = -(g - (g.phi) phi); stop if max over I of |F_k| < tol
+ *   v_{k+1} = v_k + dt F_k;  phi_{k+1} = (phi_k + dt v_{k+1}) / |phi_k + dt v_{k+1}|
+ * The device evaluates E_k in the same sweep that computes the speculative
+ * update; an arrest re-runs that sweep with v_k = 0, so the trajectory is the
+ * one above.  Runs until st->steps reaches min(st->steps + nsteps,
+ * flow->max_steps), convergence, or a non-finite value.
+ *   phi      in/out; holds the result on return
+ *   phi_alt  scratch field of the same size (its frozen layers are overwritten)
+ *   vel      in/out velocity, same layout; zero at the start of a flow
+ *   st       in/out state (skyr_anf_state_init before the first call)
+ * Returns SKYR_E_NONFINITE if the energy or force stops being finite (field
+ * contents then unspecified).  Synchronises `stream`. */
+SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                          const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                          int64_t nsteps, void* work, void* stream);
+
+/* Energy parts, baryon number, virial and largest projected force of phi
+ * (Sec. 2.1 eq. B0_components, Sec. 5.6 eq. Virial).  Synchronises `stream`. */
+SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                             const void* phi, skyr_obs* out, void* work, void* stream);
+
+/* Kernel timing for measurement tools.  skyr_timing_enable(1) resets and
+ * starts recording a pair of HIP events around every sweep-kernel launch made
+ * by skyr_anf_step on the calling thread (on the caller's stream); (0) stops.
+ * skyr_timing_read returns the summed event time of those launches in
+ * milliseconds and their count (either pointer may be null). */
+SKYR_API void skyr_timing_enable(int32_t on);
+SKYR_API skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKYR_H */

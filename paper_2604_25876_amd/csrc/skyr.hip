@@ -1,0 +1,713 @@
+// skyr.hip -- host side of the C ABI (include/skyr.h) and the small kernels
+// around the fused sweep: initial data, frozen-layer copy, gradient zeroing,
+// fixed-order reduction of the per-block partial sums and the flow's device
+// state machine (arrest / redo / convergence, Sec. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/skyr.h"
+#include "sweep.hpp"
+
+namespace skyr {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+static skyr_status fail(skyr_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define SKYR_HIP(call)                                                                                       \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            return fail(SKYR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+// ------------------------------------------------------------ tile choice
+// The tile shape is a function of the precision only (the lattice size only
+// changes the number of tiles).
+struct Launch {
+    int threads;
+    int oy, oz;    // output rows / lanes per tile
+    int xchunk;    // planes per chunk
+    int tiles_z, tiles_y, tiles_x;
+    int blocks() const { return tiles_z * tiles_y * tiles_x; }
+};
+
+// waves per block, lanes per row, flux rows per thread
+#ifndef SKYR_F64_TILE
+#define SKYR_F64_TILE 8, 32, 1
+#endif
+#ifndef SKYR_F32_TILE
+#define SKYR_F32_TILE 8, 64, 2
+#endif
+using TileF64 = Tile<double, SKYR_F64_TILE>;
+using TileF32 = Tile<float, SKYR_F32_TILE>;
+
+static Launch plan(const skyr_lattice* lat, skyr_precision prec)
+{
+    Launch L{};
+    if (prec == SKYR_F64) {
+        L.threads = TileF64::THREADS;
+        L.oy = TileF64::OY;
+        L.oz = TileF64::OZ;
+    } else {
+        L.threads = TileF32::THREADS;
+        L.oy = TileF32::OY;
+        L.oz = TileF32::OZ;
+    }
+    L.xchunk = 32;
+    const int ix = lat->n[0] - 4, iy = lat->n[1] - 4, iz = lat->n[2] - 4;
+    L.tiles_z = (iz + L.oz - 1) / L.oz;
+    L.tiles_y = (iy + L.oy - 1) / L.oy;
+    L.tiles_x = (ix + L.xchunk - 1) / L.xchunk;
+    return L;
+}
+
+constexpr size_t CTL_BYTES = 256;
+constexpr size_t OBS_BYTES = 256;
+
+static size_t workspace_bytes(const Launch& L) { return CTL_BYTES + OBS_BYTES + (size_t)L.blocks() * NPART * sizeof(double); }
+
+static skyr_status check_lattice(const skyr_lattice* lat, skyr_precision prec)
+{
+    if (!lat) return fail(SKYR_E_INVAL, "lattice is null");
+    if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return fail(SKYR_E_INVAL, "unknown precision");
+    for (int i = 0; i < 3; ++i)
+        if (lat->n[i] < 5) return fail(SKYR_E_INVAL, "every lattice dimension must be at least 5");
+    if (!(lat->h > 0.0) || !std::isfinite(lat->h)) return fail(SKYR_E_INVAL, "lattice spacing must be positive");
+    const long long n3 = (long long)lat->n[0] * lat->n[1] * lat->n[2];
+    if (n3 >= (1LL << 31) / 4) return fail(SKYR_E_INVAL, "lattice too large for 32-bit component offsets");
+    return SKYR_OK;
+}
+
+static size_t elem_bytes(skyr_precision prec) { return prec == SKYR_F64 ? sizeof(double) : sizeof(float); }
+
+static long long sites(const skyr_lattice* lat) { return (long long)lat->n[0] * lat->n[1] * lat->n[2]; }
+
+// ------------------------------------------------------------ initial data
+struct DevConstituent {
+    int degree;
+    double p[9][2], q[9][2];
+    double X[3], quat[4];
+    double prof_a, prof_lambda;
+};
+
+// n_R of R = p/q at direction d (Sec. 4.1) in homogeneous form: with
+// u = x1 + i x2 and w = r + x3 (z = u / w), P(u, w) = sum_k p_k u^k w^(B-k),
+// n_R = (2 Re(P conj Q), 2 Im(P conj Q), |Q|^2 - |P|^2) / (|P|^2 + |Q|^2).
+__device__ static void rm_direction(const DevConstituent& c, const double d[3], double nh[3])
+{
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double ur = d[0], ui = d[1], w = r + d[2];
+    double Pr = 0, Pi = 0, Qr = 0, Qi = 0;
+    // homogeneous Horner scheme: P <- P u + p_k w^(B-k), k = B .. 0
+    for (int k = c.degree; k >= 0; --k) {
+        const double nPr = Pr * ur - Pi * ui, nPi = Pr * ui + Pi * ur;
+        const double nQr = Qr * ur - Qi * ui, nQi = Qr * ui + Qi * ur;
+        double wp = 1.0;
+        for (int e = 0; e < c.degree - k; ++e) wp *= w;
+        Pr = nPr + c.p[k][0] * wp;
+        Pi = nPi + c.p[k][1] * wp;
+        Qr = nQr + c.q[k][0] * wp;
+        Qi = nQi + c.q[k][1] * wp;
+    }
+    const double cr = Pr * Qr + Pi * Qi, ci = Pi * Qr - Pr * Qi;
+    const double p2 = Pr * Pr + Pi * Pi, q2 = Qr * Qr + Qi * Qi;
+    const double den = p2 + q2;
+    nh[0] = 2.0 * cr / den;
+    nh[1] = 2.0 * ci / den;
+    nh[2] = (q2 - p2) / den;
+}
+
+template <typename T>
+__global__ void init_kernel(T* __restrict__ phi, int n0, int n1, int n2, double h, const DevConstituent* __restrict__ cs,
+                            int nc)
+{
+    const long long N3 = (long long)n0 * n1 * n2;
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N3) return;
+    const int iz = (int)(s % n2);
+    const int iy = (int)((s / n2) % n1);
+    const int ix = (int)(s / ((long long)n1 * n2));
+    double U[4] = {1.0, 0.0, 0.0, 0.0};
+    const bool in = ix >= 2 && ix <= n0 - 3 && iy >= 2 && iy <= n1 - 3 && iz >= 2 && iz <= n2 - 3;
+    if (in) {
+        const double x[3] = {(ix - 0.5 * (n0 - 1)) * h, (iy - 0.5 * (n1 - 1)) * h, (iz - 0.5 * (n2 - 1)) * h};
+        for (int k = 0; k < nc; ++k) {
+            const DevConstituent& c = cs[k];
+            const double d[3] = {x[0] - c.X[0], x[1] - c.X[1], x[2] - c.X[2]};
+            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double f = c.prof_a * exp(-r / c.prof_lambda);
+            double nh[3];
+            rm_direction(c, d, nh);
+            // isorotation A (n.tau) A^dagger = (D(A) n).tau, D(A) n = (a0^2 - |a|^2) n + 2 (a.n) a - 2 a0 a x n
+            const double a0 = c.quat[0], a1 = c.quat[1], a2 = c.quat[2], a3 = c.quat[3];
+            const double aa = a1 * a1 + a2 * a2 + a3 * a3;
+            const double an = a1 * nh[0] + a2 * nh[1] + a3 * nh[2];
+            const double cx = a2 * nh[2] - a3 * nh[1], cy = a3 * nh[0] - a1 * nh[2], cz = a1 * nh[1] - a2 * nh[0];
+            const double k0 = a0 * a0 - aa;
+            const double rx = k0 * nh[0] + 2.0 * an * a1 - 2.0 * a0 * cx;
+            const double ry = k0 * nh[1] + 2.0 * an * a2 - 2.0 * a0 * cy;
+            const double rz = k0 * nh[2] + 2.0 * an * a3 - 2.0 * a0 * cz;
+            const double sf = sin(f), cf = cos(f);
+            const double V[4] = {cf, sf * rx, sf * ry, sf * rz};
+            // U <- U V with (u0 + i u.tau)(v0 + i v.tau) = (u0 v0 - u.v) + i (u0 v + v0 u - u x v).tau
+            const double w0 = U[0] * V[0] - (U[1] * V[1] + U[2] * V[2] + U[3] * V[3]);
+            const double w1 = U[0] * V[1] + V[0] * U[1] - (U[2] * V[3] - U[3] * V[2]);
+            const double w2 = U[0] * V[2] + V[0] * U[2] - (U[3] * V[1] - U[1] * V[3]);
+            const double w3 = U[0] * V[3] + V[0] * U[3] - (U[1] * V[2] - U[2] * V[1]);
+            U[0] = w0;
+            U[1] = w1;
+            U[2] = w2;
+            U[3] = w3;
+        }
+    }
+    for (int A = 0; A < 4; ++A) phi[A * N3 + s] = T(U[A]);
+}
+
+// ---------------------------------------------------------- small kernels
+template <typename T> __global__ void fill_kernel(T* __restrict__ p, long long n, T v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// copy the frozen layers (everything outside the interior) of src to dst
+template <typename T>
+__global__ void copy_frozen_kernel(const T* __restrict__ src, T* __restrict__ dst, int n0, int n1, int n2)
+{
+    const long long N3 = (long long)n0 * n1 * n2;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < N3; s += (long long)gridDim.x * blockDim.x) {
+        const int iz = (int)(s % n2);
+        const int iy = (int)((s / n2) % n1);
+        const int ix = (int)(s / ((long long)n1 * n2));
+        const bool in = ix >= 2 && ix <= n0 - 3 && iy >= 2 && iy <= n1 - 3 && iz >= 2 && iz <= n2 - 3;
+        if (!in)
+            for (int A = 0; A < 4; ++A) dst[A * N3 + s] = src[A * N3 + s];
+    }
+}
+
+// Fixed-order reduction of the per-block partials: thread t sums blocks
+// t, t + 256, ... in order, then a fixed tree.  out = {E2, E4, E0, Bsum, maxF2}.
+__device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[5])
+{
+    __shared__ double red[256][5];
+    const int t = threadIdx.x;
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int b = t; b < nblocks; b += 256) {
+        const double* p = part + (size_t)b * NPART;
+        for (int i = 0; i < 4; ++i) s[i] += p[i];
+        s[4] = fmax(s[4], p[4]);
+    }
+    for (int i = 0; i < 5; ++i) red[t][i] = s[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            for (int i = 0; i < 4; ++i) red[t][i] += red[t + w][i];
+            red[t][4] = fmax(red[t][4], red[t + w][4]);
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 5; ++i) out[i] = red[0][i];
+}
+
+// obs = {E, E2, E4, E0, B, virial, max_force}
+__global__ void observe_kernel(const double* __restrict__ part, int nblocks, double h, double* __restrict__ obs)
+{
+    double s[5];
+    reduce_partials(part, nblocks, s);
+    if (threadIdx.x == 0) {
+        const double h3 = h * h * h;
+        const double E2 = h3 * s[0], E4 = h3 * s[1], E0 = h3 * s[2];
+        obs[0] = E2 + E4 + E0;
+        obs[1] = E2;
+        obs[2] = E4;
+        obs[3] = E0;
+        obs[4] = -h3 * s[3] / (2.0 * M_PI * M_PI);
+        obs[5] = E2 - E4 + 3.0 * E0;
+        obs[6] = sqrt(s[4]);
+    }
+}
+
+// The flow's decision after the sweep over phi_k (Sec. 3): arrest when
+// E_k > E_{k-1} (re-run the sweep with v_k = 0), stop when max|F_k| < tol,
+// otherwise accept the update (swap buffers).
+__global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl)
+{
+    if (ctl->done) return;  // uniform
+    double s[5];
+    reduce_partials(part, ctl->nblocks, s);
+    if (threadIdx.x != 0) return;
+    const double E2 = ctl->h3 * s[0], E4 = ctl->h3 * s[1], E0 = ctl->h3 * s[2];
+    const double E = E2 + E4 + E0;
+    const double r = sqrt(s[4]);
+    ctl->sweeps += 1;
+    ctl->E = E;
+    ctl->E2 = E2;
+    ctl->E4 = E4;
+    ctl->E0 = E0;
+    ctl->max_force = r;
+    if (!isfinite(E) || !isfinite(r)) {
+        ctl->done = 1;
+        ctl->status = 3;
+        return;
+    }
+    bool arrest = false;
+    if (!ctl->redo && E > ctl->E_prev) {
+        arrest = true;
+        ctl->arrests += 1;
+    }
+    if (r < ctl->tol) {
+        ctl->done = 1;
+        ctl->status = 1;
+        ctl->redo = 0;
+        return;
+    }
+    if (arrest) {
+        ctl->redo = 1;
+        ctl->redo_sweeps += 1;
+        return;
+    }
+    ctl->cur ^= 1;
+    ctl->redo = 0;
+    ctl->E_prev = E;
+    ctl->steps += 1;
+    if (ctl->steps >= ctl->target) {
+        ctl->done = 1;
+        ctl->status = 2;
+    }
+}
+
+// ------------------------------------------------------------- launches
+template <typename T, int MODE>
+static hipError_t launch_sweep(const Launch& L, const SweepArgs& args, hipStream_t s)
+{
+    if constexpr (std::is_same<T, double>::value)
+        hipLaunchKernelGGL((sweep_kernel<double, SKYR_F64_TILE, MODE>), dim3(L.blocks()), dim3(L.threads), 0, s, args);
+    else
+        hipLaunchKernelGGL((sweep_kernel<float, SKYR_F32_TILE, MODE>), dim3(L.blocks()), dim3(L.threads), 0, s, args);
+    return hipGetLastError();
+}
+
+static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
+{
+    if (prec == SKYR_F64)
+        return mode == MODE_STEP ? launch_sweep<double, MODE_STEP>(L, args, s) : launch_sweep<double, MODE_GRAD>(L, args, s);
+    return mode == MODE_STEP ? launch_sweep<float, MODE_STEP>(L, args, s) : launch_sweep<float, MODE_GRAD>(L, args, s);
+}
+
+static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, double m, double dt)
+{
+    SweepArgs a{};
+    a.n0 = lat->n[0];
+    a.n1 = lat->n[1];
+    a.n2 = lat->n[2];
+    a.xchunk = L.xchunk;
+    a.tiles_z = L.tiles_z;
+    a.tiles_y = L.tiles_y;
+    a.tiles_x = L.tiles_x;
+    a.h = lat->h;
+    a.m = m;
+    a.dt = dt;
+    return a;
+}
+
+static hipError_t fill(void* p, long long n, skyr_precision prec, double v, hipStream_t s)
+{
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    if (prec == SKYR_F64)
+        hipLaunchKernelGGL(fill_kernel<double>, dim3(blocks), dim3(256), 0, s, (double*)p, n, v);
+    else
+        hipLaunchKernelGGL(fill_kernel<float>, dim3(blocks), dim3(256), 0, s, (float*)p, n, (float)v);
+    return hipGetLastError();
+}
+
+static bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+// ------------------------------------------------------------- timing
+// Per-thread event pool around sweep launches (measurement only).
+struct Timing {
+    bool on = false;
+    double ms = 0.0;
+    int64_t launches = 0;
+    std::vector<hipEvent_t> ev;  // 2 per launch of the current group
+    int used = 0;
+    ~Timing()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+static thread_local Timing g_timing;
+
+static hipError_t timing_mark(hipStream_t s)
+{
+    Timing& t = g_timing;
+    if (!t.on) return hipSuccess;
+    if (t.used == (int)t.ev.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        t.ev.push_back(e);
+    }
+    return hipEventRecord(t.ev[t.used++], s);
+}
+
+// after the stream has been synchronised: add up the recorded pairs
+static hipError_t timing_collect()
+{
+    Timing& t = g_timing;
+    for (int i = 0; i + 1 < t.used; i += 2) {
+        float ms = 0.0f;
+        hipError_t r = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+        if (r != hipSuccess) return r;
+        t.ms += ms;
+        t.launches += 1;
+    }
+    t.used = 0;
+    return hipSuccess;
+}
+
+}  // namespace skyr
+
+using namespace skyr;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* skyr_version(void) { return "skyr 0.1 (gfx950)"; }
+
+const char* skyr_last_error(void) { return g_last_error.c_str(); }
+
+size_t skyr_workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
+{
+    if (check_lattice(lat, prec) != SKYR_OK) return 0;
+    return workspace_bytes(plan(lat, prec));
+}
+
+void skyr_anf_state_init(skyr_anf_state* st)
+{
+    if (!st) return;
+    std::memset(st, 0, sizeof *st);
+    st->E_prev = INFINITY;
+    st->E = NAN;
+    st->max_force = NAN;
+}
+
+skyr_status skyr_random_constituents(uint64_t seed, int32_t B, double radius, double prof_a, double prof_lambda,
+                                     skyr_constituent* out)
+{
+    if (!out) return fail(SKYR_E_INVAL, "output array is null");
+    if (B < 1 || B > 64) return fail(SKYR_E_INVAL, "B must be in 1..64");
+    if (!(radius >= 0.0) || !(prof_lambda > 0.0)) return fail(SKYR_E_INVAL, "radius must be >= 0, prof_lambda > 0");
+    // SplitMix64: state advances by the golden-ratio increment, output is the finaliser of the state
+    uint64_t state = seed;
+    auto next = [&]() {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    };
+    auto uniform = [&]() { return (double)(next() >> 11) * 0x1.0p-53; };
+    for (int k = 0; k < B; ++k) {
+        skyr_constituent& c = out[k];
+        std::memset(&c, 0, sizeof c);
+        c.degree = 1;
+        c.p[1][0] = 1.0;  // p = z
+        c.q[0][0] = 1.0;  // q = 1
+        for (;;) {
+            const double x = radius * (2.0 * uniform() - 1.0);
+            const double y = radius * (2.0 * uniform() - 1.0);
+            const double z = radius * (2.0 * uniform() - 1.0);
+            if (x * x + y * y + z * z <= radius * radius) {
+                c.X[0] = x;
+                c.X[1] = y;
+                c.X[2] = z;
+                break;
+            }
+        }
+        const double u1 = uniform(), u2 = uniform(), u3 = uniform();
+        const double s1 = std::sqrt(1.0 - u1), s2 = std::sqrt(u1);
+        c.quat[0] = s1 * std::sin(2.0 * M_PI * u2);
+        c.quat[1] = s1 * std::cos(2.0 * M_PI * u2);
+        c.quat[2] = s2 * std::sin(2.0 * M_PI * u3);
+        c.quat[3] = s2 * std::cos(2.0 * M_PI * u3);
+        c.prof_a = prof_a;
+        c.prof_lambda = prof_lambda;
+    }
+    return SKYR_OK;
+}
+
+skyr_status skyr_init_field(const skyr_lattice* lat, skyr_precision prec, const skyr_init_spec* spec, void* phi,
+                            void* stream)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!spec || !phi) return fail(SKYR_E_INVAL, "spec and phi must be non-null");
+    hipStream_t s = (hipStream_t)stream;
+    DevConstituent host[64];
+    int nc = 0;
+    auto convert = [&](const skyr_constituent& c) -> bool {
+        if (c.degree < 1 || c.degree > 8 || !(c.prof_lambda > 0.0)) return false;
+        DevConstituent& d = host[nc++];
+        std::memset(&d, 0, sizeof d);
+        d.degree = c.degree;
+        std::memcpy(d.p, c.p, sizeof d.p);
+        std::memcpy(d.q, c.q, sizeof d.q);
+        std::memcpy(d.X, c.X, sizeof d.X);
+        std::memcpy(d.quat, c.quat, sizeof d.quat);
+        d.prof_a = c.prof_a;
+        d.prof_lambda = c.prof_lambda;
+        return true;
+    };
+    switch (spec->kind) {
+    case SKYR_INIT_HEDGEHOG: {
+        if (!(spec->prof_lambda > 0.0)) return fail(SKYR_E_INVAL, "prof_lambda must be positive");
+        skyr_constituent c;
+        std::memset(&c, 0, sizeof c);
+        c.degree = 1;
+        c.p[1][0] = 1.0;
+        c.q[0][0] = 1.0;
+        c.quat[0] = 1.0;
+        c.prof_a = spec->prof_a;
+        c.prof_lambda = spec->prof_lambda;
+        convert(c);
+        break;
+    }
+    case SKYR_INIT_RATIONAL_MAP:
+        if (!spec->c) return fail(SKYR_E_INVAL, "rational map needs c[0]");
+        if (!convert(spec->c[0])) return fail(SKYR_E_INVAL, "constituent degree must be 1..8, prof_lambda > 0");
+        break;
+    case SKYR_INIT_PRODUCT:
+        if (!spec->c || spec->count < 1 || spec->count > 64) return fail(SKYR_E_INVAL, "product needs 1..64 constituents");
+        for (int k = 0; k < spec->count; ++k)
+            if (!convert(spec->c[k])) return fail(SKYR_E_INVAL, "constituent degree must be 1..8, prof_lambda > 0");
+        break;
+    case SKYR_INIT_RANDOM_PRODUCT: {
+        skyr_constituent cs[64];
+        st = skyr_random_constituents(spec->seed, spec->B, spec->ball_radius, spec->prof_a, spec->prof_lambda, cs);
+        if (st != SKYR_OK) return st;
+        for (int k = 0; k < spec->B; ++k) convert(cs[k]);
+        break;
+    }
+    default:
+        return fail(SKYR_E_INVAL, "unknown initial-data kind");
+    }
+    DevConstituent* dev = nullptr;
+    SKYR_HIP(hipMalloc((void**)&dev, sizeof(DevConstituent) * nc));
+    hipError_t e = hipMemcpyAsync(dev, host, sizeof(DevConstituent) * nc, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return fail(SKYR_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    }
+    const long long N3 = sites(lat);
+    const int blocks = (int)((N3 + 255) / 256);
+    if (prec == SKYR_F64)
+        hipLaunchKernelGGL(init_kernel<double>, dim3(blocks), dim3(256), 0, s, (double*)phi, lat->n[0], lat->n[1],
+                           lat->n[2], lat->h, dev, nc);
+    else
+        hipLaunchKernelGGL(init_kernel<float>, dim3(blocks), dim3(256), 0, s, (float*)phi, lat->n[0], lat->n[1],
+                           lat->n[2], lat->h, dev, nc);
+    e = hipGetLastError();
+    // the copy from the host stack array and the kernel must finish before the table is freed
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return fail(SKYR_E_DEVICE, std::string("init_kernel: ") + hipGetErrorString(e));
+    return SKYR_OK;
+}
+
+static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
+                                void* grad, int projected, int baryon, double obs_out[7], void* work, hipStream_t s)
+{
+    const Launch L = plan(lat, prec);
+    SweepArgs a = make_args(lat, L, model->m, 0.0);
+    a.phi0 = phi;
+    a.grad = grad;
+    a.projected = projected;
+    a.baryon = baryon;
+    char* w = (char*)work;
+    a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+    double* obs = (double*)(w + CTL_BYTES);
+    if (grad) SKYR_HIP(fill(grad, 4 * sites(lat), prec, 0.0, s));
+    SKYR_HIP(sweep(prec, MODE_GRAD, L, a, s));
+    if (obs_out) {
+        hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, L.blocks(), lat->h, obs);
+        SKYR_HIP(hipGetLastError());
+        SKYR_HIP(hipMemcpyAsync(obs_out, obs, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+    }
+    return SKYR_OK;
+}
+
+static skyr_status check_common(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
+                                void* work)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!model || !phi || !work) return fail(SKYR_E_INVAL, "model, phi and work must be non-null");
+    if (!std::isfinite(model->m)) return fail(SKYR_E_INVAL, "mass must be finite");
+    if (!aligned256(work)) return fail(SKYR_E_INVAL, "workspace must be 256-byte aligned");
+    return SKYR_OK;
+}
+
+skyr_status skyr_energy_gradient(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                 const void* phi, void* grad, int32_t projected, skyr_obs* parts, void* work,
+                                 void* stream)
+{
+    skyr_status st = check_common(lat, prec, model, phi, work);
+    if (st != SKYR_OK) return st;
+    double o[7];
+    st = run_gradient(lat, prec, model, phi, grad, projected ? 1 : 0, 0, parts ? o : nullptr, work, (hipStream_t)stream);
+    if (st != SKYR_OK) return st;
+    if (parts) {
+        parts->E = o[0];
+        parts->E2 = o[1];
+        parts->E4 = o[2];
+        parts->E0 = o[3];
+        parts->B = 0.0;
+        parts->virial = o[5];
+        parts->max_force = o[6];
+    }
+    return SKYR_OK;
+}
+
+skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
+                             skyr_obs* out, void* work, void* stream)
+{
+    skyr_status st = check_common(lat, prec, model, phi, work);
+    if (st != SKYR_OK) return st;
+    if (!out) return fail(SKYR_E_INVAL, "out must be non-null");
+    double o[7];
+    st = run_gradient(lat, prec, model, phi, nullptr, 0, 1, o, work, (hipStream_t)stream);
+    if (st != SKYR_OK) return st;
+    out->E = o[0];
+    out->E2 = o[1];
+    out->E4 = o[2];
+    out->E0 = o[3];
+    out->B = o[4];
+    out->virial = o[5];
+    out->max_force = o[6];
+    return SKYR_OK;
+}
+
+skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                          const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                          int64_t nsteps, void* work, void* stream)
+{
+    skyr_status rc = check_common(lat, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (!flow || !phi_alt || !vel || !st) return fail(SKYR_E_INVAL, "flow, phi_alt, vel and st must be non-null");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (!(flow->tol >= 0.0)) return fail(SKYR_E_INVAL, "tol must be >= 0");
+    if (nsteps < 0 || flow->max_steps < 0 || flow->renorm64_every < 0) return fail(SKYR_E_INVAL, "negative step count");
+    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
+    if (st->converged || target <= st->steps) return SKYR_OK;
+
+    const Launch L = plan(lat, prec);
+    char* w = (char*)work;
+    Ctl* ctl = (Ctl*)w;
+    SweepArgs a = make_args(lat, L, model->m, flow->dt);
+    a.phi0 = phi;
+    a.phi1 = phi_alt;
+    a.vel = vel;
+    a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+    a.ctl = ctl;
+
+    Ctl h{};
+    h.cur = 0;
+    h.redo = st->redo_pending;
+    h.steps = st->steps;
+    h.target = target;
+    h.arrests = st->arrests;
+    h.redo_sweeps = st->redo_sweeps;
+    h.sweeps = st->sweeps;
+    h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
+    h.nblocks = L.blocks();
+    h.E_prev = st->E_prev;
+    h.E = st->E;
+    h.max_force = st->max_force;
+    h.tol = flow->tol;
+    h.h3 = lat->h * lat->h * lat->h;
+    SKYR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
+    // the frozen layers of phi_alt must match those of phi
+    {
+        const long long N3 = sites(lat);
+        const int blocks = (int)std::min<long long>((N3 + 255) / 256, 8192);
+        if (prec == SKYR_F64)
+            hipLaunchKernelGGL(copy_frozen_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)phi,
+                               (double*)phi_alt, lat->n[0], lat->n[1], lat->n[2]);
+        else
+            hipLaunchKernelGGL(copy_frozen_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)phi,
+                               (float*)phi_alt, lat->n[0], lat->n[1], lat->n[2]);
+        SKYR_HIP(hipGetLastError());
+    }
+    // sweeps are enqueued in groups; the host looks at the control block between groups
+    const int64_t remaining = target - st->steps;
+    int64_t group = std::min<int64_t>(std::max<int64_t>(remaining, 1), 32);
+    int64_t budget = 2 * remaining + 2;  // every step takes at most one redo sweep
+    for (;;) {
+        for (int64_t i = 0; i < group; ++i) {
+            SKYR_HIP(timing_mark(s));
+            SKYR_HIP(sweep(prec, MODE_STEP, L, a, s));
+            SKYR_HIP(timing_mark(s));
+            hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
+            SKYR_HIP(hipGetLastError());
+        }
+        budget -= group;
+        SKYR_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+        SKYR_HIP(timing_collect());
+        if (h.done || budget <= 0) break;
+        group = std::min<int64_t>(std::max<int64_t>(h.target - h.steps, 1), 32);
+    }
+    if (h.cur == 1) {
+        SKYR_HIP(hipMemcpyAsync(phi, phi_alt, 4 * sites(lat) * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+    }
+    st->steps = h.steps;
+    st->arrests = h.arrests;
+    st->redo_sweeps = h.redo_sweeps;
+    st->sweeps = h.sweeps;
+    st->E_prev = h.E_prev;
+    st->E = h.E;
+    st->max_force = h.max_force;
+    st->converged = h.status == 1;
+    st->redo_pending = h.redo;
+    st->nonfinite = h.status == 3;
+    if (st->nonfinite) return fail(SKYR_E_NONFINITE, "energy or force is not finite");
+    if (!h.done) return fail(SKYR_E_DEVICE, "flow did not reach its target within the sweep budget");
+    return SKYR_OK;
+}
+
+void skyr_timing_enable(int32_t on)
+{
+    Timing& t = g_timing;
+    t.on = on != 0;
+    t.used = 0;
+    if (t.on) {
+        t.ms = 0.0;
+        t.launches = 0;
+    }
+}
+
+skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches)
+{
+    if (sweep_ms) *sweep_ms = g_timing.ms;
+    if (sweep_launches) *sweep_launches = g_timing.launches;
+    return SKYR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,502 @@
+// sweep.hpp -- fused per-step sweep of the arrested Newton flow for gfx950.
+//
+// One launch evaluates, for every interior site of one field, the discrete
+// energy density, the exact gradient of the discrete energy E_h (Sec. 2.1
+// energy, Sec. 3 stencils), its tangent projection (Sec. 3, eq. Newton_flow)
+// and either the kick-drift-renormalise update (Sec. 3) or a gradient output,
+// plus FP64 per-block partial sums of E2, E4, E0, B and the largest |F|^2.
+//
+// Work decomposition (2.5D march):
+//   * a thread block owns an output tile of (PY-4) rows (y) x (LW-8) lanes (z)
+//     and a chunk of planes [xb, xe) along x, and marches through x;
+//   * every thread owns RY "flux positions" (rows r_k, lane zl); the flux
+//     region is PY x LW and overlaps neighbouring tiles by two rows/lanes;
+//   * x-neighbours live in registers: a ring of five phi planes per position
+//     and a ring of five gradient accumulators (planes j-2..j+2);
+//   * y-neighbours go through LDS (one phi plane with a 2-row halo and one plane
+//     of the y-flux), z-neighbours are exchanged across lanes (ds_bpermute);
+//   * the x-flux of plane j is pushed into the accumulators of planes j+-1, j+-2;
+//     output plane j-2 is complete after plane j and is written at once.
+// Energy, charge and force sums are accumulated in double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace skyr {
+
+// partial-sum slots per thread block (doubles)
+constexpr int NPART = 8;
+enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4 };
+
+// Control block of one flow, in device memory at the start of the workspace.
+struct Ctl {
+    int32_t cur;          // field buffer holding phi_k: 0 = phi, 1 = phi_alt
+    int32_t redo;         // this sweep re-runs phi_k with v_k = 0
+    int32_t done;         // 1: no further sweep does any work
+    int32_t status;       // 0 running, 1 converged, 2 step target reached, 3 non-finite
+    int64_t steps;        // accepted steps
+    int64_t target;       // stop when steps reaches this
+    int64_t arrests;
+    int64_t redo_sweeps;
+    int64_t sweeps;
+    int32_t renorm64_every;
+    int32_t nblocks;      // number of partial-sum blocks of the sweep
+    double E_prev;
+    double E, E2, E4, E0;
+    double max_force;
+    double tol;
+    double h3;
+    double pad[4];
+};
+static_assert(sizeof(Ctl) <= 256, "control block must fit its 256-byte slot");
+
+enum : int { MODE_STEP = 0, MODE_GRAD = 1 };
+
+struct SweepArgs {
+    const void* phi0;  // field buffer 0 (phi)
+    void* phi1;        // field buffer 1 (phi_alt); MODE_GRAD: unused
+    void* vel;         // MODE_STEP: velocity, updated in place
+    void* grad;        // MODE_GRAD: nullable gradient output
+    double* partials;  // [nblocks][NPART]
+    Ctl* ctl;          // MODE_STEP: control block
+    int n0, n1, n2;
+    int xchunk;        // planes per chunk
+    int tiles_z, tiles_y, tiles_x;
+    int projected;     // MODE_GRAD: write g - (g.phi) phi instead of g
+    int baryon;        // accumulate the baryon density
+    double h, m, dt;
+};
+
+// stencil coefficients (Sec. 3)
+//   D f  = ( 2/3 (f[+1] - f[-1]) - 1/12 (f[+2] - f[-2]) ) / h
+//   L f  = ( 4/3 (f[+1] + f[-1]) - 1/12 (f[+2] + f[-2]) - 5/2 f ) / h^2
+//        = ( 4/3 ((f[+1] - f) + (f[-1] - f)) - 1/12 ((f[+2] - f) + (f[-2] - f)) ) / h^2
+template <typename T> struct Coef {
+    static constexpr T c1 = T(2.0 / 3.0);
+    static constexpr T c2 = T(-1.0 / 12.0);
+    static constexpr T d1 = T(4.0 / 3.0);
+    static constexpr T d2 = T(-1.0 / 12.0);
+    static constexpr T d0 = T(-5.0 / 2.0);
+};
+
+__device__ __forceinline__ float lane_shift(float v, int lane, int d)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + d) & 63) << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ double lane_shift(double v, int lane, int d)
+{
+    const int addr = ((lane + d) & 63) << 2;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ float rnorm(float s) { return rsqrtf(s); }
+__device__ __forceinline__ double rnorm(double s) { return 1.0 / sqrt(s); }
+
+template <typename T> __device__ __forceinline__ T dot4(const T* a, const T* b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+// det[c0 c1 c2 c3] of four column 4-vectors (expansion by 2x2 minors)
+template <typename T> __device__ __forceinline__ T det4(const T* c0, const T* c1, const T* c2, const T* c3)
+{
+    // minors of columns (c0, c1) and (c2, c3) over row pairs
+    const T m01 = c0[0] * c1[1] - c0[1] * c1[0];
+    const T m02 = c0[0] * c1[2] - c0[2] * c1[0];
+    const T m03 = c0[0] * c1[3] - c0[3] * c1[0];
+    const T m12 = c0[1] * c1[2] - c0[2] * c1[1];
+    const T m13 = c0[1] * c1[3] - c0[3] * c1[1];
+    const T m23 = c0[2] * c1[3] - c0[3] * c1[2];
+    const T n01 = c2[0] * c3[1] - c2[1] * c3[0];
+    const T n02 = c2[0] * c3[2] - c2[2] * c3[0];
+    const T n03 = c2[0] * c3[3] - c2[3] * c3[0];
+    const T n12 = c2[1] * c3[2] - c2[2] * c3[1];
+    const T n13 = c2[1] * c3[3] - c2[3] * c3[1];
+    const T n23 = c2[2] * c3[3] - c2[3] * c3[2];
+    return m01 * n23 - m02 * n13 + m03 * n12 + m12 * n03 - m13 * n02 + m23 * n01;
+}
+
+template <typename T, int NW, int LW, int RY> struct Tile {
+    static constexpr int RPW = 64 / LW;     // rows per wave
+    static constexpr int R0 = NW * RPW;     // rows per row group
+    static constexpr int PY = R0 * RY;      // flux rows per tile
+    static constexpr int OY = PY - 4;       // output rows per tile
+    static constexpr int OZ = LW - 8;       // output lanes per tile
+    static constexpr int THREADS = NW * 64;
+    static_assert(THREADS >= 4 * LW, "halo rows are loaded by the first 4*LW threads");
+};
+
+template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
+    using TL = Tile<T, NW, LW, RY>;
+    static constexpr int PY = TL::PY;
+    static constexpr int R0 = TL::R0;
+    using C = Coef<T>;
+
+    struct Smem {
+        T phi[4][PY + 4][LW];  // phi of the current plane, rows y0-4 .. y0+PY-1
+        T qy[4][PY][LW];       // y-flux of the current plane, rows y0-2 .. y0+PY-3
+        T qz[4][PY][LW];       // z-flux of the current plane
+        double red[NW][NPART];
+    };
+
+    Smem& sm;
+    const T* __restrict__ pin;
+    T* __restrict__ pout;
+    T* __restrict__ vel;
+    T* __restrict__ gout;
+    long long N3;
+    int n0, n1, n2, plane;
+    int xb, xe;
+    int lane, zl, rg, z, hrow, hz, hoff;
+    bool halo_loader, lane_flux, redo, renorm64, projected, baryon;
+    int yk[RY], offk[RY];
+    bool row_out[RY], yz_in[RY], yz_near[RY];
+    T ih, ih2, dt, m2;
+
+    // registers carried along the march
+    T ring[5][4][RY];  // phi at planes j-2 .. j+2 (slot = plane mod 5 relative to the start)
+    T acc[5][4][RY];   // gradient accumulators of planes j-2 .. j+2
+    T nxt[4][RY];      // prefetched phi(j+3)
+    T hnxt[4];         // prefetched halo rows of phi(j+1)
+
+    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb = 0.0;
+    T pf2 = T(0);
+
+    __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
+
+    __device__ __forceinline__ void load_plane(int x, T (&dst)[4][RY]) const
+    {
+        const long long base = (long long)clampi(x, 0, n0 - 1) * plane;
+#pragma unroll
+        for (int A = 0; A < 4; ++A)
+#pragma unroll
+            for (int k = 0; k < RY; ++k) dst[A][k] = pin[A * N3 + base + offk[k]];
+    }
+
+    __device__ __forceinline__ void load_halo(int x, T (&dst)[4]) const
+    {
+        if (halo_loader) {
+            const long long base = (long long)clampi(x, 0, n0 - 1) * plane;
+#pragma unroll
+            for (int A = 0; A < 4; ++A) dst[A] = pin[A * N3 + base + hoff];
+        }
+    }
+
+    // one plane of the march: flux at plane j, output at plane j-2.  Ring and
+    // accumulator slots 0..4 hold planes j-2 .. j+2 and are shifted by one
+    // plane at the end of the step.
+    __device__ __forceinline__ void step(int j)
+    {
+        constexpr int S_M2 = 0, S_M1 = 1, S_0 = 2, S_P1 = 3, S_P2 = 4;
+
+        // commit the prefetched plane j+2 and the halo of plane j; prefetch j+3 and the halo of j+1
+        T hcur[4];
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) ring[S_P2][A][k] = nxt[A][k];
+            hcur[A] = hnxt[A];
+        }
+        load_plane(j + 3, nxt);
+        load_halo(j + 1, hnxt);
+        // velocity of the output plane j-2, used at the end of this step
+        T vcur[4][RY];
+        if constexpr (MODE == MODE_STEP) {
+            const long long vb = (long long)clampi(j - 2, 0, n0 - 1) * plane;
+#pragma unroll
+            for (int A = 0; A < 4; ++A)
+#pragma unroll
+                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : vel[A * N3 + vb + offk[k]];
+        }
+
+        // stage phi(j) for the y-stencils
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) sm.phi[A][rg + k * R0 + 2][zl] = ring[S_0][A][k];
+            if (halo_loader) sm.phi[A][hrow][hz] = hcur[A];
+        }
+        __syncthreads();
+
+        const bool j_in = (j >= 2) && (j <= n0 - 3);
+        const bool j_out = (j >= xb) && (j < xe);
+        const bool j_near = (j <= 3) || (j >= n0 - 4);
+
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int r = rg + k * R0 + 2;  // LDS row of this position in sm.phi
+            T c[4], ax[4], ay[4], az[4];
+            T cl = T(0);  // phi . Lap phi
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+                c[A] = ring[S_0][A][k];
+                const T xm2 = ring[S_M2][A][k], xm1 = ring[S_M1][A][k];
+                const T xp1 = ring[S_P1][A][k], xp2 = ring[S_P2][A][k];
+                const T ym2 = sm.phi[A][r - 2][zl], ym1 = sm.phi[A][r - 1][zl];
+                const T yp1 = sm.phi[A][r + 1][zl], yp2 = sm.phi[A][r + 2][zl];
+                const T zm2 = lane_shift(c[A], lane, -2), zm1 = lane_shift(c[A], lane, -1);
+                const T zp1 = lane_shift(c[A], lane, 1), zp2 = lane_shift(c[A], lane, 2);
+                ax[A] = (C::c1 * (xp1 - xm1) + C::c2 * (xp2 - xm2)) * ih;
+                ay[A] = (C::c1 * (yp1 - ym1) + C::c2 * (yp2 - ym2)) * ih;
+                az[A] = (C::c1 * (zp1 - zm1) + C::c2 * (zp2 - zm2)) * ih;
+                // the five-point weights sum to zero, so the Laplacian is a weighted sum of
+                // differences from the centre: no cancellation of O(1) terms in single precision
+                const T lap = (C::d1 * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
+                                        ((zp1 - c[A]) + (zm1 - c[A]))) +
+                               C::d2 * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
+                                        ((zp2 - c[A]) + (zm2 - c[A])))) *
+                              ih2;
+                cl += c[A] * lap;
+                // E2 part of the gradient: -1/2 (Lap phi + Lap(1_I phi)); neighbours outside I
+                // carry weight zero in the second Laplacian
+                T corr = T(0);
+                if (j_near || yz_near[k]) {
+                    const int y = yk[k];
+                    const bool ox1 = (j + 1 > n0 - 3), ox_1 = (j - 1 < 2), ox2 = (j + 2 > n0 - 3), ox_2 = (j - 2 < 2);
+                    const bool oy1 = (y + 1 > n1 - 3), oy_1 = (y - 1 < 2), oy2 = (y + 2 > n1 - 3), oy_2 = (y - 2 < 2);
+                    const bool oz1 = (z + 1 > n2 - 3), oz_1 = (z - 1 < 2), oz2 = (z + 2 > n2 - 3), oz_2 = (z - 2 < 2);
+                    corr = C::d1 * ((ox1 ? xp1 : T(0)) + (ox_1 ? xm1 : T(0)) + (oy1 ? yp1 : T(0)) +
+                                    (oy_1 ? ym1 : T(0)) + (oz1 ? zp1 : T(0)) + (oz_1 ? zm1 : T(0))) +
+                           C::d2 * ((ox2 ? xp2 : T(0)) + (ox_2 ? xm2 : T(0)) + (oy2 ? yp2 : T(0)) +
+                                    (oy_2 ? ym2 : T(0)) + (oz2 ? zp2 : T(0)) + (oz_2 ? zm2 : T(0)));
+                }
+                acc[S_0][A][k] += T(0.5) * corr * ih2 - lap;
+            }
+
+            const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
+            const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
+            const bool valid = lane_flux && yz_in[k] && j_in;
+            const T w = valid ? T(1) : T(0);  // flux vanishes outside I
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+                const T qx = w * ((gyy + gzz) * ax[A] - gxy * ay[A] - gxz * az[A]);
+                sm.qy[A][r - 2][zl] = w * ((gxx + gzz) * ay[A] - gxy * ax[A] - gyz * az[A]);
+                sm.qz[A][r - 2][zl] = w * ((gxx + gyy) * az[A] - gxz * ax[A] - gyz * ay[A]);
+                // push the x-flux: g(j-1) -= c1 q, g(j+1) += c1 q, g(j-2) -= c2 q, g(j+2) += c2 q
+                const T q = qx * ih;
+                acc[S_M1][A][k] -= C::c1 * q;
+                acc[S_P1][A][k] += C::c1 * q;
+                acc[S_M2][A][k] -= C::c2 * q;
+                acc[S_P2][A][k] += C::c2 * q;
+            }
+            if (row_out[k] && j_out) {
+                pe2 += (double)(T(-0.5) * cl);
+                pe4 += (double)(T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz));
+                pe0 += (double)(m2 * (T(1) - c[0]));
+                if (baryon) pb += (double)det4(c, ax, ay, az);
+            }
+        }
+
+        // output plane j-2 is complete
+        if (j - 2 >= xb && j - 2 < xe) {
+            const long long base = (long long)(j - 2) * plane;
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                if (row_out[k]) {
+                    T g[4], p[4], f[4];
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        g[A] = acc[S_M2][A][k];
+                        p[A] = ring[S_M2][A][k];
+                    }
+                    g[0] -= m2;
+                    const T gp = dot4(g, p);
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) f[A] = gp * p[A] - g[A];  // F = -(g - (g.phi) phi)
+                    pf2 = fmax(pf2, dot4(f, f));
+                    if constexpr (MODE == MODE_STEP) {
+                        T v[4], q[4], pn[4];
+#pragma unroll
+                        for (int A = 0; A < 4; ++A) {
+                            v[A] = vcur[A][k] + dt * f[A];
+                            q[A] = p[A] + dt * v[A];
+                        }
+                        if (renorm64) {
+                            const double s2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
+                                              (double)q[3] * q[3];
+                            const double inv = 1.0 / sqrt(s2);
+#pragma unroll
+                            for (int A = 0; A < 4; ++A) pn[A] = T((double)q[A] * inv);
+                        } else {
+                            const T inv = rnorm(dot4(q, q));
+#pragma unroll
+                            for (int A = 0; A < 4; ++A) pn[A] = q[A] * inv;
+                        }
+#pragma unroll
+                        for (int A = 0; A < 4; ++A) {
+                            pout[A * N3 + base + offk[k]] = pn[A];
+                            vel[A * N3 + base + offk[k]] = v[A];
+                        }
+                    } else {
+                        if (gout) {
+#pragma unroll
+                            for (int A = 0; A < 4; ++A) gout[A * N3 + base + offk[k]] = projected ? -f[A] : g[A];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // y- and z-divergence of the flux into g(j)
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int r = rg + k * R0;
+            const int rm2 = max(r - 2, 0), rm1 = max(r - 1, 0), rp1 = min(r + 1, PY - 1), rp2 = min(r + 2, PY - 1);
+            const int zm2 = max(zl - 2, 0), zm1 = max(zl - 1, 0), zp1 = min(zl + 1, LW - 1), zp2 = min(zl + 2, LW - 1);
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+                const T dy = C::c1 * (sm.qy[A][rp1][zl] - sm.qy[A][rm1][zl]) + C::c2 * (sm.qy[A][rp2][zl] - sm.qy[A][rm2][zl]);
+                const T dz = C::c1 * (sm.qz[A][r][zp1] - sm.qz[A][r][zm1]) + C::c2 * (sm.qz[A][r][zp2] - sm.qz[A][r][zm2]);
+                acc[S_0][A][k] -= (dy + dz) * ih;
+            }
+        }
+
+        // advance the rings by one plane; the freed accumulator starts plane j+3
+#pragma unroll
+        for (int A = 0; A < 4; ++A)
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+#pragma unroll
+                for (int sl = 0; sl < 4; ++sl) {
+                    ring[sl][A][k] = ring[sl + 1][A][k];
+                    acc[sl][A][k] = acc[sl + 1][A][k];
+                }
+                acc[4][A][k] = T(0);
+            }
+    }
+};
+
+template <typename T, int NW, int LW, int RY, int MODE>
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+{
+    using SW = Sweeper<T, NW, LW, RY, MODE>;
+    using TL = typename SW::TL;
+    constexpr int PY = TL::PY;
+    constexpr int R0 = TL::R0;
+    __shared__ typename SW::Smem smem;
+
+    const Ctl* ctl = a.ctl;
+    int cur = 0;
+    SW sw(smem);
+    sw.redo = false;
+    sw.renorm64 = false;
+    if constexpr (MODE == MODE_STEP) {
+        if (ctl->done) return;  // uniform: the flow has stopped
+        cur = ctl->cur;
+        sw.redo = ctl->redo != 0;
+        const int kr = ctl->renorm64_every;
+        sw.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
+    }
+    sw.n0 = a.n0;
+    sw.n1 = a.n1;
+    sw.n2 = a.n2;
+    const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
+    sw.plane = n1 * n2;
+    sw.N3 = (long long)n0 * sw.plane;
+    sw.pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
+    sw.pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
+    sw.vel = (T*)a.vel;
+    sw.gout = (T*)a.grad;
+    sw.projected = a.projected != 0;
+    sw.baryon = a.baryon != 0;
+
+    // tile coordinates
+    const int b = blockIdx.x;
+    const int tz = b % a.tiles_z;
+    const int ty = (b / a.tiles_z) % a.tiles_y;
+    const int tx = b / (a.tiles_z * a.tiles_y);
+    const int z0 = 2 + tz * TL::OZ;
+    const int y0 = 2 + ty * TL::OY;
+    sw.xb = 2 + tx * a.xchunk;
+    sw.xe = min(sw.xb + a.xchunk, n0 - 2);
+
+    const int tid = threadIdx.x;
+    sw.lane = tid & 63;
+    const int wave = tid >> 6;
+    sw.zl = sw.lane % LW;
+    sw.rg = wave * TL::RPW + sw.lane / LW;
+    sw.z = z0 - 4 + sw.zl;
+    const int zc = clampi(sw.z, 0, n2 - 1);
+    sw.lane_flux = (sw.zl >= 2) && (sw.zl < LW - 2);
+    const bool lane_out = (sw.zl >= 4) && (sw.zl < LW - 4) && (sw.z <= n2 - 3);
+    const bool z_in = (sw.z >= 2) && (sw.z <= n2 - 3);
+    const bool z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
+#pragma unroll
+    for (int k = 0; k < RY; ++k) {
+        const int r = sw.rg + k * R0;
+        const int y = y0 - 2 + r;
+        sw.yk[k] = y;
+        sw.offk[k] = clampi(y, 0, n1 - 1) * n2 + zc;
+        sw.row_out[k] = (r >= 2) && (r < PY - 2) && (y <= n1 - 3) && lane_out;
+        sw.yz_in[k] = z_in && (y >= 2) && (y <= n1 - 3);
+        sw.yz_near[k] = z_near || (y <= 3) || (y >= n1 - 4);
+    }
+    // halo rows of the phi plane: LDS rows 0, 1, PY+2, PY+3
+    sw.halo_loader = tid < 4 * LW;
+    sw.hrow = sw.halo_loader ? (tid / LW < 2 ? tid / LW : PY + tid / LW) : 0;
+    sw.hz = tid % LW;
+    sw.hoff = clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hz, 0, n2 - 1);
+
+    sw.ih = T(1.0 / a.h);
+    sw.ih2 = T(1.0 / (a.h * a.h));
+    sw.dt = T(a.dt);
+    sw.m2 = T(a.m * a.m);
+
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int A = 0; A < 4; ++A)
+#pragma unroll
+            for (int k = 0; k < RY; ++k) sw.acc[s][A][k] = T(0);
+
+    // prologue: ring slots 0..3 hold planes jstart-2 .. jstart+1; nxt holds jstart+2
+    const int jstart = sw.xb - 2;
+    const int nst = (sw.xe - sw.xb) + 4;
+    sw.load_plane(jstart - 2, sw.ring[0]);
+    sw.load_plane(jstart - 1, sw.ring[1]);
+    sw.load_plane(jstart, sw.ring[2]);
+    sw.load_plane(jstart + 1, sw.ring[3]);
+    sw.load_plane(jstart + 2, sw.nxt);
+    sw.load_halo(jstart, sw.hnxt);
+
+    for (int s = 0; s < nst; ++s) sw.step(jstart + s);
+
+    // block reduction of the partial sums (fixed order)
+    double vals[5] = {sw.pe2, sw.pe4, sw.pe0, sw.pb, (double)sw.pf2};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double v = vals[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off);
+            v = (i == 4) ? fmax(v, o) : v + o;
+        }
+        vals[i] = v;
+    }
+    if (sw.lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) smem.red[wave][i] = vals[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s[5] = {0, 0, 0, 0, 0};
+        for (int w = 0; w < NW; ++w) {
+            for (int i = 0; i < 4; ++i) s[i] += smem.red[w][i];
+            s[4] = fmax(s[4], smem.red[w][4]);
+        }
+        double* out = a.partials + (size_t)b * NPART;
+        for (int i = 0; i < 5; ++i) out[i] = s[i];
+    }
+}
+
+}  // namespace skyr

@@ -1,0 +1,349 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Every test builds identical seeded inputs for both sides, runs the library on
+cuda:0 and the oracle on the host, and compares element by element (or on
+sampled sites, for the full-size lattices).  Tolerances:
+  * FP64 gradients / projected gradients: max-abs relative to max |g| <= 1e-12
+  * FP64 energies, charge, virial: <= 1e-12 relative (1e-11 for the virial,
+    a difference of parts)
+  * FP32-bulk: inputs are the FP32 rounding of the same field; the gradient
+    is compared at 2e-4 of max |g| (single-precision stencil cancellation
+    ~ eps32 * 16/h^2), energies at 2e-6 relative
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from skyr_inputs import random_unit_field, HEDGEHOG_40_SMALLDT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def skyr():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2604_25876_amd import skyr as s
+    s.lib()
+    return s
+
+
+DEV = "cuda:0"
+
+
+def _tensor(a, prec, skyr):
+    return torch.tensor(np.ascontiguousarray(a), dtype=skyr.field_dtype(prec), device=DEV)
+
+
+def _lat(skyr, shape, h):
+    lat = skyr.Lattice()
+    lat.n[0], lat.n[1], lat.n[2] = shape
+    lat.h = h
+    return lat
+
+
+def _rel_inf(got, ref):
+    return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+# ----------------------------------------------------------- initial data
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("desc", [
+    {"kind": "hedgehog", "prof_lambda": 1.0},
+    {"kind": "cube_b4", "prof_lambda": 1.5},
+    {"kind": "random_product", "B": 10, "seed": 1, "radius": 3.0, "prof_lambda": 1.0},
+])
+def test_init_matches_oracle(skyr, prec, desc):
+    n, h = 40, 0.2
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(desc)
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    if desc["kind"] == "hedgehog":
+        cs = [oracle.hedgehog(prof_lambda=desc["prof_lambda"])]
+    elif desc["kind"] == "cube_b4":
+        cs = [oracle.cube_b4(prof_lambda=desc["prof_lambda"])]
+    else:
+        cs = oracle.random_constituents(desc["seed"], desc["B"], desc["radius"], math.pi, desc["prof_lambda"])
+    ref = oracle.init_product((n, n, n), h, cs)
+    got = phi.double().cpu().numpy()
+    tol = 1e-13 if prec == 0 else 1e-7
+    assert np.abs(got - ref).max() < tol
+
+
+def test_random_constituents_match_oracle(skyr):
+    for seed, B in ((1, 10), (2**63 + 12345, 12), (7, 1)):
+        a = skyr.random_constituents(seed, B, 3.0)
+        b = oracle.random_constituents(seed, B, 3.0)
+        for ca, cb in zip(a, b):
+            assert list(ca.X) == list(cb.X)
+            assert np.allclose(list(ca.quat), list(cb.quat), rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------- gradient
+SHAPES = [(9, 9, 9), (40, 40, 40), (37, 53, 70), (5, 6, 7), (64, 20, 131)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("projected", [False, True])
+def test_gradient_f64_matches_oracle(skyr, shape, projected):
+    h, m = 0.21, 0.9
+    phi = random_unit_field(shape, 17 + sum(shape), 0.5)
+    lat = _lat(skyr, shape, h)
+    t = _tensor(phi, 0, skyr)
+    g = skyr.new_field(lat, 0, DEV)
+    work = skyr.new_workspace(lat, 0, DEV)
+    parts = skyr.energy_gradient(lat, 0, skyr.Model(m), t, work, grad=g, projected=projected)
+    ref = oracle.gradient(phi, h, m)
+    if projected:
+        ref, _ = oracle.project(phi, ref)
+    got = g.cpu().numpy()
+    assert _rel_inf(got, ref) <= 1e-12
+    E2, E4, E0 = oracle.energy_parts(phi, h, m)
+    assert parts["E2"] == pytest.approx(E2, rel=1e-12)
+    assert parts["E4"] == pytest.approx(E4, rel=1e-12)
+    assert parts["E0"] == pytest.approx(E0, rel=1e-12)
+    _, r = oracle.project(phi, oracle.gradient(phi, h, m))
+    assert parts["max_force"] == pytest.approx(r, rel=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(40, 40, 40), (37, 53, 70)])
+def test_gradient_f32_matches_oracle(skyr, shape):
+    h, m = 0.2, 1.0
+    phi = random_unit_field(shape, 3, 0.3).astype(np.float32).astype(np.float64)
+    lat = _lat(skyr, shape, h)
+    t = _tensor(phi, 1, skyr)
+    g = skyr.new_field(lat, 1, DEV)
+    work = skyr.new_workspace(lat, 1, DEV)
+    parts = skyr.energy_gradient(lat, 1, skyr.Model(m), t, work, grad=g, projected=False)
+    ref = oracle.gradient(phi, h, m)
+    assert _rel_inf(g.double().cpu().numpy(), ref) <= 2e-4
+    E = sum(oracle.energy_parts(phi, h, m))
+    assert parts["E"] == pytest.approx(E, rel=2e-6)
+
+
+def test_gradient_is_deterministic(skyr):
+    """Two launches on the same input give bitwise identical outputs (a check
+    for missing barriers and LDS races)."""
+    shape, h, m = (48, 40, 100), 0.2, 1.0
+    phi = random_unit_field(shape, 5, 0.5)
+    lat = _lat(skyr, shape, h)
+    for prec in (0, 1):
+        t = _tensor(phi, prec, skyr)
+        work = skyr.new_workspace(lat, prec, DEV)
+        outs = []
+        for _ in range(2):
+            g = skyr.new_field(lat, prec, DEV)
+            p = skyr.energy_gradient(lat, prec, skyr.Model(m), t, work, grad=g)
+            outs.append((g.cpu().numpy(), p))
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert outs[0][1] == outs[1][1]
+
+
+# ------------------------------------------------------------ observables
+@pytest.mark.parametrize("desc", [
+    {"kind": "hedgehog", "prof_lambda": 1.0},
+    {"kind": "random_product", "B": 4, "seed": 3, "radius": 2.0, "prof_lambda": 1.0},
+])
+def test_observables_match_oracle(skyr, desc):
+    n, h, m = 44, 0.2, 1.0
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(desc)
+    phi = skyr.new_field(lat, 0, DEV)
+    skyr.init_field(lat, 0, spec, phi)
+    work = skyr.new_workspace(lat, 0, DEV)
+    got = skyr.observables(lat, 0, skyr.Model(m), phi, work)
+    ref = oracle.observables(phi.cpu().numpy(), h, m)
+    for k in ("E", "E2", "E4", "E0", "B", "max_force"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-13), k
+    assert got["virial"] == pytest.approx(ref["virial"], rel=1e-11, abs=1e-12)
+
+
+# ------------------------------------------------------------------- flow
+def _flow_pair(skyr, n, h, m, dt, prec=0, desc=None):
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(desc or {"kind": "hedgehog", "prof_lambda": 1.0})
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    return lat, phi, alt, vel, work
+
+
+def test_flow_trajectory_matches_oracle_step_by_step(skyr):
+    """Small-dt hedgehog (40^3, h = 0.2, dt = 0.025): fields and energies agree
+    after every one of the first 30 steps."""
+    w = HEDGEHOG_40_SMALLDT
+    n, h, m, dt = w["n"], w["h"], w["m"], w["dt"]
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+    ref = phi.cpu().numpy()
+    rvel = np.zeros_like(ref)
+    st, rst = skyr.anf_state(), oracle.AnfState.fresh()
+    flow = skyr.Flow(dt, 0.0, 10 ** 9, 0, 0)
+    for k in range(30):
+        skyr.anf_step(lat, 0, skyr.Model(m), flow, phi, alt, vel, st, 1, work)
+        ref, rvel, rst, Et, _ = oracle.anf(ref, rvel, h, m, dt, 0.0, k + 1, rst, trace=True)
+        assert st.steps == rst.steps == k + 1
+        assert st.arrests == rst.arrests
+        assert st.E_prev == pytest.approx(Et[-1], rel=1e-13)
+        assert np.abs(phi.cpu().numpy() - ref).max() < 1e-12
+        assert np.abs(vel.cpu().numpy() - rvel).max() < 1e-11
+
+
+def test_flow_with_arrests_matches_oracle(skyr):
+    """A step large enough to overshoot: the arrests fire on the same steps
+    and the fields agree after 80 steps run in one call."""
+    n, h, m, dt = 24, 0.25, 1.0, 0.06
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+    ref0 = phi.cpu().numpy()
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 0, skyr.Model(m), skyr.Flow(dt, 0.0, 10 ** 9, 0, 0), phi, alt, vel, st, 80, work)
+    ref, rvel, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, 0.0, 80)
+    assert rst.arrests > 0
+    assert st.steps == 80 and st.arrests == rst.arrests and st.redo_sweeps == rst.arrests
+    assert np.abs(phi.cpu().numpy() - ref).max() < 1e-10
+
+
+def test_flow_resume_across_calls(skyr):
+    """Chained calls (7 + 13 + 20 steps) equal one call of 40 steps, bitwise."""
+    n, h, m, dt = 28, 0.25, 1.0, 0.05
+    res = []
+    for chunks in ((40,), (7, 13, 20)):
+        lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+        st = skyr.anf_state()
+        for c in chunks:
+            skyr.anf_step(lat, 0, skyr.Model(m), skyr.Flow(dt, 0.0, 10 ** 9, 0, 0), phi, alt, vel, st, c, work)
+        res.append((phi.cpu().numpy(), vel.cpu().numpy(), st.arrests))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+
+
+def test_converged_energy_matches_oracle(skyr):
+    """Relax the hedgehog to max|F| < 1e-5 on both sides: energies agree to
+    1e-8 relative, B and virial to the same."""
+    n, h, m, dt, tol = 40, 0.2, 1.0, 0.02, 1e-5
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+    ref0 = phi.cpu().numpy()
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 0, skyr.Model(m), skyr.Flow(dt, tol, 20000, 0, 0), phi, alt, vel, st, 20000, work)
+    assert st.converged == 1
+    ref, _, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, tol, 20000)
+    assert rst.converged == 1
+    got = skyr.observables(lat, 0, skyr.Model(m), phi, work)
+    ro = oracle.observables(ref, h, m)
+    assert got["E"] == pytest.approx(ro["E"], rel=1e-8)
+    assert got["B"] == pytest.approx(ro["B"], rel=1e-8)
+
+
+def test_converged_f32_bulk_against_oracle(skyr):
+    """FP32-bulk relaxation of the same hedgehog: converged energy within 1e-6
+    of the FP64 oracle's converged energy, B within 1e-3; the FP64 energy of
+    the FP32 result (evaluated by the oracle) agrees even more closely."""
+    n, h, m, dt, tol = 40, 0.2, 1.0, 0.02, 1e-4
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt, prec=1)
+    ref0 = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 1, skyr.Model(m), skyr.Flow(dt, tol, 20000, 16, 0), phi, alt, vel, st, 20000, work)
+    assert st.converged == 1
+    ref, _, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, 1e-5, 20000)
+    got = skyr.observables(lat, 1, skyr.Model(m), phi, work)
+    ro = oracle.observables(ref, h, m)
+    e64 = oracle.energy(phi.double().cpu().numpy(), h, m)
+    print(f"FP32-bulk: steps {st.steps} arrests {st.arrests} E32 {got['E']:.10f} E64(phi32) {e64:.10f} "
+          f"oracle {ro['E']:.10f} B32 {got['B']:.8f} oracle B {ro['B']:.8f}")
+    assert e64 == pytest.approx(ro["E"], rel=1e-6)
+    assert got["E"] == pytest.approx(ro["E"], rel=1e-6)
+    assert got["B"] == pytest.approx(ro["B"], abs=1e-3)
+
+
+# ---------------------------------------------------------- edge cases
+def test_smallest_lattice(skyr):
+    """n = 5: a single interior site."""
+    shape, h, m = (5, 5, 5), 0.3, 0.7
+    phi = random_unit_field(shape, 2, 0.8)
+    lat = _lat(skyr, shape, h)
+    g = skyr.new_field(lat, 0, DEV)
+    work = skyr.new_workspace(lat, 0, DEV)
+    parts = skyr.energy_gradient(lat, 0, skyr.Model(m), _tensor(phi, 0, skyr), work, grad=g)
+    ref = oracle.gradient(phi, h, m)
+    assert _rel_inf(g.cpu().numpy(), ref) <= 1e-12
+    assert parts["E"] == pytest.approx(oracle.energy(phi, h, m), rel=1e-12)
+
+
+def test_vacuum_does_not_move(skyr):
+    n, h = 20, 0.2
+    lat = skyr.Lattice.cube(n, h)
+    phi = skyr.new_field(lat, 0, DEV)
+    phi[0] = 1.0
+    alt, vel = skyr.new_field(lat, 0, DEV), skyr.new_field(lat, 0, DEV)
+    work = skyr.new_workspace(lat, 0, DEV)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 0, skyr.Model(1.0), skyr.Flow(0.05, 1e-12, 100, 0, 0), phi, alt, vel, st, 100, work)
+    assert st.converged == 1 and st.steps == 0 and st.E == 0.0
+    assert bool((phi[0] == 1).all()) and bool((phi[1:] == 0).all())
+
+
+def test_nonfinite_input_reports_error(skyr):
+    n, h = 16, 0.2
+    lat = skyr.Lattice.cube(n, h)
+    phi = skyr.new_field(lat, 0, DEV)
+    phi[0] = 1.0
+    phi[2, 8, 8, 8] = float("nan")
+    alt, vel = skyr.new_field(lat, 0, DEV), skyr.new_field(lat, 0, DEV)
+    work = skyr.new_workspace(lat, 0, DEV)
+    st = skyr.anf_state()
+    with pytest.raises(skyr.SkyrError) as e:
+        skyr.anf_step(lat, 0, skyr.Model(1.0), skyr.Flow(0.05, 0.0, 10, 0, 0), phi, alt, vel, st, 10, work)
+    assert e.value.status == skyr.E_NONFINITE and st.nonfinite == 1
+
+
+# ------------------------------------------------- full-size sampled checks
+def _sample_sites(shape, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = [tuple(rng.integers(2, s - 2) for s in shape) for _ in range(count)]
+    # faces and corners of the interior
+    n0, n1, n2 = shape
+    pts += [(2, 2, 2), (n0 - 3, n1 - 3, n2 - 3), (2, n1 - 3, 2), (n0 // 2, 2, n2 - 3), (3, 3, 3)]
+    return pts
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_random_b10_sampled(skyr, prec):
+    """The 256^3 lattice, h = 0.1, random product of 10 unit charges (seed 1),
+    in the launch configuration the benchmark times: gradient and one flow
+    step on 400 sampled sites, and the total energy, against the oracle."""
+    n, h, m, dt = 256, 0.1, 1.0, 0.01
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description({"kind": "random_product", "B": 10, "seed": 1, "radius": 3.0,
+                                              "prof_lambda": 1.0})
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    host = phi.double().cpu().numpy()
+    work = skyr.new_workspace(lat, prec, DEV)
+    g = skyr.new_field(lat, prec, DEV)
+    parts = skyr.energy_gradient(lat, prec, skyr.Model(m), phi, work, grad=g)
+    gh = g.double().cpu().numpy()
+    pts = _sample_sites((n, n, n), 400, 11)
+    ref_g = np.array([oracle.gradient_at(host, h, m, *p) for p in pts])
+    got_g = np.array([gh[:, p[0], p[1], p[2]] for p in pts])
+    scale = np.abs(ref_g).max()
+    tol = 1e-12 if prec == 0 else 2e-4
+    assert np.abs(got_g - ref_g).max() <= tol * scale
+    E = oracle.energy(host, h, m)
+    assert parts["E"] == pytest.approx(E, rel=1e-12 if prec == 0 else 2e-6)
+    # one flow step from rest
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(m), skyr.Flow(dt, 0.0, 10 ** 9, 16, 0), phi, alt, vel, st, 1, work)
+    ph = phi.double().cpu().numpy()
+    vh = vel.double().cpu().numpy()
+    gerr = tol * scale  # bound on the gradient error at a site
+    for p, gr in zip(pts, ref_g):
+        po, vo = oracle.update_at(host[:, p[0], p[1], p[2]], np.zeros(4), gr, dt)
+        rnd = 1e-15 if prec == 0 else 2e-7
+        assert np.abs(vh[:, p[0], p[1], p[2]] - vo).max() <= 2 * dt * gerr + rnd * (1 + np.abs(vo).max())
+        assert np.abs(ph[:, p[0], p[1], p[2]] - po).max() <= 2 * dt * dt * gerr + 4 * rnd
+    assert st.E_prev == pytest.approx(E, rel=1e-12 if prec == 0 else 2e-6)
