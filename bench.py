@@ -45,6 +45,8 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup):
     model = skyr.Model(w["m"])
     # tolerance 0: every call runs exactly its steps
     flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
+    # tile shape for this lattice and precision: measured once, before the timed region
+    tile = skyr.autotune_cached(lat, prec, model, flow, phi, alt, vel, work)
     st = skyr.anf_state()
     skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, warmup, work)
     torch.cuda.synchronize()
@@ -71,7 +73,41 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup):
         prec=prec_name, steps=done, sweeps=st.sweeps - sw0, arrests=st.arrests - ar0, wall_s=wall,
         elapsed_s=elapsed, site_updates_per_s=done * interior / elapsed, ms_per_step=1e3 * elapsed / max(done, 1),
         sweep_kernel_avg_us=kernel_avg_s * 1e6, sweep_launches=sweep_n, bytes_per_launch=bytes_launch,
-        achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"])
+        achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"],
+        tile={"shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]})
+
+
+def sweep_tiles(skyr, torch, w, prec_name, steps=20):
+    """Time every compiled shape and slab length on the workload (flow steps
+    from the initial field); one line per candidate."""
+    prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
+    n, h = w["n"], w["h"]
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(w["init"])
+    dev = torch.device("cuda:0")
+    phi0 = skyr.new_field(lat, prec, dev)
+    skyr.init_field(lat, prec, spec, phi0)
+    phi, alt, vel = phi0.clone(), skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
+    work = skyr.new_workspace(lat, prec, dev)
+    model = skyr.Model(w["m"])
+    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
+    rows = []
+    for v, shape in enumerate(skyr.tile_variants(prec)):
+        for xc in (32, 64, 84, 128, 256):
+            skyr.set_tile(lat, prec, v, xc)
+            phi.copy_(phi0)
+            vel.zero_()
+            st = skyr.anf_state()
+            skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, 2, work)
+            skyr.timing_enable(True)
+            skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, steps, work)
+            ms, cnt = skyr.timing_read()
+            skyr.timing_enable(False)
+            us = 1e3 * ms / max(cnt, 1)
+            rows.append({"prec": prec_name, "shape": shape, "xchunk": xc, "sweep_us": us,
+                         "GBs": BYTES_PER_SITE[prec_name] * (n - 4) ** 3 / us / 1e3})
+            print(json.dumps(rows[-1]), flush=True)
+    return rows
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -107,7 +143,23 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["f32", "f64"], default=None,
+                    help="time one precision only (profiling runs)")
+    ap.add_argument("--sweep-tiles", action="store_true",
+                    help="print the sweep time of every compiled tile shape and x-chunk, then exit")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="instead of the flow, copy a 1 GiB device buffer 5 times (reference for the HBM "
+                         "byte counters: 1 GiB read + 1 GiB written per copy)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 2 ** 30, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the flow of one lattice is not sharded across GPUs here "
               "(--gpus must be 1)", file=sys.stderr)
@@ -119,6 +171,14 @@ def main():
     from skyr_inputs import RANDOM_B10_256 as W
 
     skyr.lib()
+    if args.sweep_tiles:
+        for p in ([args.only] if args.only else ["f32", "f64"]):
+            sweep_tiles(skyr, torch, W, p)
+        return
+    if args.only:
+        r = run_flow(skyr, torch, W, args.only, args.steps, args.warmup)
+        print(json.dumps(r), flush=True)
+        return
     r32 = run_flow(skyr, torch, W, "f32", args.steps, args.warmup)
     print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
     r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup)
@@ -143,7 +203,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["name"], "n": W["n"], "h": W["h"], "m": W["m"], "dt": W["dt"],
                    "init": W["init"], "precision": "f32-bulk (f64 sums, arrest test, renormalisation every 16)",
-                   "interior_sites": (W["n"] - 4) ** 3},
+                   "interior_sites": (W["n"] - 4) ** 3, "tile_f32": r32["tile"], "tile_f64": r64["tile"]},
         "f64_flow": {"value": r64["site_updates_per_s"], "ms_per_step": r64["ms_per_step"],
                      "sweep_kernel_avg_us": r64["sweep_kernel_avg_us"], "achieved_GBs": r64["achieved_GBs"],
                      "arrests": r64["arrests"], "sweeps": r64["sweeps"]},

@@ -220,6 +220,26 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                              const void* phi, skyr_obs* out, void* work, void* stream);
 
+/* Tile shapes of the fused sweep.  A few shapes (waves per block, lanes per
+ * row, flux rows per thread) are compiled per precision; x is cut into slabs
+ * of `xchunk` (>= 16) planes and one block marches one (y, z) tile of one
+ * slab.  The choice is kept per (lattice dimensions, precision) for the whole
+ * process and applies to every later sweep on such a lattice; results are
+ * deterministic for a given choice.  Default: shape 0, 128-plane slabs. */
+SKYR_API int32_t skyr_tile_variants(skyr_precision prec);
+SKYR_API skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant, int32_t info[3]);
+SKYR_API skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant, int32_t xchunk);
+SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk);
+
+/* Autotuner: time every compiled shape with slab lengths 16..256 on this
+ * lattice (three flow sweeps each, phi read, phi_alt and vel written), keep
+ * the fastest with skyr_set_tile and return it (outputs nullable; best_us is
+ * the sweep time in microseconds).  phi is unchanged; phi_alt is scratch and
+ * vel is zero on return.  Synchronises `stream`. */
+SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                   const skyr_flow* flow, const void* phi, void* phi_alt, void* vel, void* work,
+                                   void* stream, int32_t* variant, int32_t* xchunk, double* best_us);
+
 /* Kernel timing for measurement tools.  skyr_timing_enable(1) resets and
  * starts recording a pair of HIP events around every sweep-kernel launch made
  * by skyr_anf_step on the calling thread (on the caller's stream); (0) stops.

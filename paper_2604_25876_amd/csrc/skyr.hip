@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,50 +37,94 @@ static skyr_status fail(skyr_status s, const std::string& msg)
     } while (0)
 
 // ------------------------------------------------------------ tile choice
-// The tile shape is a function of the precision only (the lattice size only
-// changes the number of tiles).
-struct Launch {
-    int threads;
-    int oy, oz;    // output rows / lanes per tile
-    int xchunk;    // planes per chunk
-    int tiles_z, tiles_y, tiles_x;
-    int blocks() const { return tiles_z * tiles_y * tiles_x; }
+// A tile shape is (waves per block, lanes per row, flux rows per thread); a
+// few shapes are compiled per precision.  x is cut into slabs of `xchunk`
+// planes and one block marches one (y, z) tile of one slab.  The choice for a
+// (lattice, precision) pair is a process-wide setting (skyr_set_tile /
+// skyr_autotune); the default is shape 0 with 128-plane slabs.
+struct Shape {
+    int nw, lw, ry;
+    int threads() const { return nw * 64; }
+    int oy() const { return (64 / lw) * nw * ry - 4; }
+    int oz() const { return lw - 8; }
 };
 
-// waves per block, lanes per row, flux rows per thread
-#ifndef SKYR_F64_TILE
-#define SKYR_F64_TILE 8, 32, 1
+#ifndef SKYR_SHAPES_F64
+#define SKYR_SHAPES_F64(X) X(8, 32, 1) X(4, 32, 2)
 #endif
-#ifndef SKYR_F32_TILE
-#define SKYR_F32_TILE 8, 64, 2
+#ifndef SKYR_SHAPES_F32
+#define SKYR_SHAPES_F32(X) X(16, 64, 1) X(16, 32, 1) X(8, 64, 2)
 #endif
-using TileF64 = Tile<double, SKYR_F64_TILE>;
-using TileF32 = Tile<float, SKYR_F32_TILE>;
+#define SKYR_SHAPE_ENTRY(a, b, c) Shape{a, b, c},
+static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
+static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
+static const int kChunks[] = {16, 24, 32, 48, 64, 96, 128, 256};  // planes per slab
+constexpr int kMinChunk = 16;
+constexpr int kDefaultChunk = 128;
+
+static int shape_count(skyr_precision prec)
+{
+    return prec == SKYR_F64 ? (int)(sizeof kShapesF64 / sizeof kShapesF64[0])
+                            : (int)(sizeof kShapesF32 / sizeof kShapesF32[0]);
+}
+static const Shape& shape_of(skyr_precision prec, int v) { return prec == SKYR_F64 ? kShapesF64[v] : kShapesF32[v]; }
+
+struct Launch {
+    int variant;
+    Shape shape;
+    int xchunk;  // planes per slab
+    int tiles_z, tiles_y, slabs;
+    int blocks() const { return tiles_z * tiles_y * slabs; }
+    int threads() const { return shape.threads(); }
+};
+
+struct TileKey {
+    int n0, n1, n2, prec;
+    bool operator<(const TileKey& o) const
+    {
+        return std::tie(n0, n1, n2, prec) < std::tie(o.n0, o.n1, o.n2, o.prec);
+    }
+};
+static std::mutex g_tile_mu;
+static std::map<TileKey, std::pair<int, int>> g_tiles;  // (variant, planes per slab)
+
+static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int variant, int xchunk)
+{
+    Launch L{};
+    L.variant = variant;
+    L.shape = shape_of(prec, variant);
+    L.xchunk = xchunk;
+    const int ix = lat->n[0] - 4, iy = lat->n[1] - 4, iz = lat->n[2] - 4;
+    L.tiles_z = (iz + L.shape.oz() - 1) / L.shape.oz();
+    L.tiles_y = (iy + L.shape.oy() - 1) / L.shape.oy();
+    L.slabs = (ix + xchunk - 1) / xchunk;
+    return L;
+}
 
 static Launch plan(const skyr_lattice* lat, skyr_precision prec)
 {
-    Launch L{};
-    if (prec == SKYR_F64) {
-        L.threads = TileF64::THREADS;
-        L.oy = TileF64::OY;
-        L.oz = TileF64::OZ;
-    } else {
-        L.threads = TileF32::THREADS;
-        L.oy = TileF32::OY;
-        L.oz = TileF32::OZ;
+    int v = 0, xc = kDefaultChunk;
+    {
+        std::lock_guard<std::mutex> g(g_tile_mu);
+        auto it = g_tiles.find(TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec});
+        if (it != g_tiles.end()) {
+            v = it->second.first;
+            xc = it->second.second;
+        }
     }
-    L.xchunk = 32;
-    const int ix = lat->n[0] - 4, iy = lat->n[1] - 4, iz = lat->n[2] - 4;
-    L.tiles_z = (iz + L.oz - 1) / L.oz;
-    L.tiles_y = (iy + L.oy - 1) / L.oy;
-    L.tiles_x = (ix + L.xchunk - 1) / L.xchunk;
-    return L;
+    return plan_with(lat, prec, v, xc);
 }
 
 constexpr size_t CTL_BYTES = 256;
 constexpr size_t OBS_BYTES = 256;
 
-static size_t workspace_bytes(const Launch& L) { return CTL_BYTES + OBS_BYTES + (size_t)L.blocks() * NPART * sizeof(double); }
+// enough partial-sum slots for every shape and slab length >= the shortest supported
+static size_t workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
+{
+    int most = 0;
+    for (int v = 0; v < shape_count(prec); ++v) most = std::max(most, plan_with(lat, prec, v, kMinChunk).blocks());
+    return CTL_BYTES + OBS_BYTES + (size_t)most * NPART * sizeof(double);
+}
 
 static skyr_status check_lattice(const skyr_lattice* lat, skyr_precision prec)
 {
@@ -290,21 +337,33 @@ __global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict
 }
 
 // ------------------------------------------------------------- launches
-template <typename T, int MODE>
-static hipError_t launch_sweep(const Launch& L, const SweepArgs& args, hipStream_t s)
+template <typename T, int NW, int LW, int RY>
+static hipError_t launch_shape(int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
 {
-    if constexpr (std::is_same<T, double>::value)
-        hipLaunchKernelGGL((sweep_kernel<double, SKYR_F64_TILE, MODE>), dim3(L.blocks()), dim3(L.threads), 0, s, args);
+    if (mode == MODE_STEP)
+        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP>), dim3(L.blocks()), dim3(NW * 64), 0, s, args);
     else
-        hipLaunchKernelGGL((sweep_kernel<float, SKYR_F32_TILE, MODE>), dim3(L.blocks()), dim3(L.threads), 0, s, args);
+        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD>), dim3(L.blocks()), dim3(NW * 64), 0, s, args);
     return hipGetLastError();
 }
 
 static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
 {
-    if (prec == SKYR_F64)
-        return mode == MODE_STEP ? launch_sweep<double, MODE_STEP>(L, args, s) : launch_sweep<double, MODE_GRAD>(L, args, s);
-    return mode == MODE_STEP ? launch_sweep<float, MODE_STEP>(L, args, s) : launch_sweep<float, MODE_GRAD>(L, args, s);
+    int v = 0;
+    if (prec == SKYR_F64) {
+#define SKYR_CASE64(a, b, c)                                                                                \
+    if (L.variant == v) return launch_shape<double, a, b, c>(mode, L, args, s);                              \
+    ++v;
+        SKYR_SHAPES_F64(SKYR_CASE64)
+#undef SKYR_CASE64
+    } else {
+#define SKYR_CASE32(a, b, c)                                                                                \
+    if (L.variant == v) return launch_shape<float, a, b, c>(mode, L, args, s);                               \
+    ++v;
+        SKYR_SHAPES_F32(SKYR_CASE32)
+#undef SKYR_CASE32
+    }
+    return hipErrorInvalidValue;
 }
 
 static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, double m, double dt)
@@ -313,10 +372,9 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, double m, d
     a.n0 = lat->n[0];
     a.n1 = lat->n[1];
     a.n2 = lat->n[2];
-    a.xchunk = L.xchunk;
     a.tiles_z = L.tiles_z;
     a.tiles_y = L.tiles_y;
-    a.tiles_x = L.tiles_x;
+    a.xchunk = L.xchunk;
     a.h = lat->h;
     a.m = m;
     a.dt = dt;
@@ -392,7 +450,7 @@ const char* skyr_last_error(void) { return g_last_error.c_str(); }
 size_t skyr_workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
 {
     if (check_lattice(lat, prec) != SKYR_OK) return 0;
-    return workspace_bytes(plan(lat, prec));
+    return workspace_bytes(lat, prec);
 }
 
 void skyr_anf_state_init(skyr_anf_state* st)
@@ -689,6 +747,116 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     st->nonfinite = h.status == 3;
     if (st->nonfinite) return fail(SKYR_E_NONFINITE, "energy or force is not finite");
     if (!h.done) return fail(SKYR_E_DEVICE, "flow did not reach its target within the sweep budget");
+    return SKYR_OK;
+}
+
+int32_t skyr_tile_variants(skyr_precision prec)
+{
+    if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return 0;
+    return shape_count(prec);
+}
+
+skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant, int32_t info[3])
+{
+    if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return fail(SKYR_E_INVAL, "unknown precision");
+    if (!info || variant < 0 || variant >= shape_count(prec)) return fail(SKYR_E_INVAL, "no such tile variant");
+    const Shape& sh = shape_of(prec, variant);
+    info[0] = sh.nw;
+    info[1] = sh.lw;
+    info[2] = sh.ry;
+    return SKYR_OK;
+}
+
+skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant, int32_t xchunk)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (variant < 0 || variant >= shape_count(prec)) return fail(SKYR_E_INVAL, "no such tile variant");
+    if (xchunk < kMinChunk) return fail(SKYR_E_INVAL, "slabs must have at least 16 planes");
+    std::lock_guard<std::mutex> g(g_tile_mu);
+    g_tiles[TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec}] = {variant, xchunk};
+    return SKYR_OK;
+}
+
+skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    const Launch L = plan(lat, prec);
+    if (variant) *variant = L.variant;
+    if (xchunk) *xchunk = L.xchunk;
+    return SKYR_OK;
+}
+
+skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const skyr_flow* flow,
+                          const void* phi, void* phi_alt, void* vel, void* work, void* stream, int32_t* variant_out,
+                          int32_t* xchunk_out, double* best_us_out)
+{
+    skyr_status rc = check_common(lat, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)work;
+    Ctl* ctl = (Ctl*)w;
+    // every candidate runs the same sweep: phi -> phi_alt with zero incoming velocity
+    Ctl h{};
+    h.redo = 1;
+    h.target = INT64_MAX;
+    h.E_prev = INFINITY;
+    SKYR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    SKYR_HIP(hipEventCreate(&e0));
+    SKYR_HIP(hipEventCreate(&e1));
+    auto cleanup = [&]() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    };
+    double best = INFINITY;
+    int bv = 0, bx = kDefaultChunk;
+    for (int v = 0; v < shape_count(prec); ++v) {
+        int prev_slabs = -1;
+        for (int c = 0; c < (int)(sizeof kChunks / sizeof kChunks[0]); ++c) {
+            const int xc = kChunks[c];
+            const Launch L = plan_with(lat, prec, v, xc);
+            if (L.slabs == prev_slabs) continue;  // same split as a shorter slab length
+            prev_slabs = L.slabs;
+            SweepArgs a = make_args(lat, L, model->m, flow->dt);
+            a.phi0 = phi;
+            a.phi1 = phi_alt;
+            a.vel = vel;
+            a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+            a.ctl = ctl;
+            hipError_t e = sweep(prec, MODE_STEP, L, a, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = sweep(prec, MODE_STEP, L, a, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            }
+            const double us = 1e3 * ms / 3.0;
+            if (us < best) {
+                best = us;
+                bv = v;
+                bx = xc;
+            }
+        }
+    }
+    cleanup();
+    SKYR_HIP(fill(vel, 4 * sites(lat), prec, 0.0, s));
+    SKYR_HIP(hipStreamSynchronize(s));
+    {
+        std::lock_guard<std::mutex> g(g_tile_mu);
+        g_tiles[TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec}] = {bv, bx};
+    }
+    if (variant_out) *variant_out = bv;
+    if (xchunk_out) *xchunk_out = bx;
+    if (best_us_out) *best_us_out = best;
     return SKYR_OK;
 }
 

@@ -63,8 +63,8 @@ struct SweepArgs {
     double* partials;  // [nblocks][NPART]
     Ctl* ctl;          // MODE_STEP: control block
     int n0, n1, n2;
-    int xchunk;        // planes per chunk
-    int tiles_z, tiles_y, tiles_x;
+    int tiles_z, tiles_y;  // output tiles of the (y, z) plane
+    int xchunk;            // planes per slab
     int projected;     // MODE_GRAD: write g - (g.phi) phi instead of g
     int baryon;        // accumulate the baryon density
     double h, m, dt;
@@ -140,6 +140,10 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     static constexpr int PY = TL::PY;
     static constexpr int R0 = TL::R0;
     using C = Coef<T>;
+    // Waves made only of y-halo flux rows take a short path (y-flux only).  Enabled in
+    // double precision; in single precision the extra code path costs the register that
+    // keeps the 1024-thread shape at four waves per SIMD.
+    static constexpr bool kHaloFast = sizeof(T) == 8;
 
     struct Smem {
         T phi[4][PY + 4][LW];  // phi of the current plane, rows y0-4 .. y0+PY-1
@@ -149,18 +153,21 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     };
 
     Smem& sm;
-    const T* __restrict__ pin;
-    T* __restrict__ pout;
-    T* __restrict__ vel;
-    T* __restrict__ gout;
-    long long N3;
+    // per-component base pointers (uniform); element offsets within a component fit 32 bits
+    const T* pin[4];
+    T* pout[4];
+    T* vel[4];
+    T* gout[4];
     int n0, n1, n2, plane;
     int xb, xe;
-    int lane, zl, rg, z, hrow, hz, hoff;
-    bool halo_loader, lane_flux, redo, renorm64, projected, baryon;
-    int yk[RY], offk[RY];
+    int lane, zl, rg, z, hrow, hz;
+    unsigned hoff;
+    bool halo_loader, lane_flux, redo, renorm64, projected, baryon, has_grad, tile_near;
+    bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
+    int yk[RY];
+    unsigned offk[RY];
     bool row_out[RY], yz_in[RY], yz_near[RY];
-    T ih, ih2, dt, m2;
+    T c1h, c2h, d1h, d2h, ih2, dt, m2;  // stencil weights with 1/h, 1/h^2 folded in
 
     // registers carried along the march
     T ring[5][4][RY];  // phi at planes j-2 .. j+2 (slot = plane mod 5 relative to the start)
@@ -175,19 +182,19 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 
     __device__ __forceinline__ void load_plane(int x, T (&dst)[4][RY]) const
     {
-        const long long base = (long long)clampi(x, 0, n0 - 1) * plane;
+        const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * (unsigned)plane;
 #pragma unroll
         for (int A = 0; A < 4; ++A)
 #pragma unroll
-            for (int k = 0; k < RY; ++k) dst[A][k] = pin[A * N3 + base + offk[k]];
+            for (int k = 0; k < RY; ++k) dst[A][k] = pin[A][base + offk[k]];
     }
 
     __device__ __forceinline__ void load_halo(int x, T (&dst)[4]) const
     {
         if (halo_loader) {
-            const long long base = (long long)clampi(x, 0, n0 - 1) * plane;
+            const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * (unsigned)plane;
 #pragma unroll
-            for (int A = 0; A < 4; ++A) dst[A] = pin[A * N3 + base + hoff];
+            for (int A = 0; A < 4; ++A) dst[A] = pin[A][base + hoff];
         }
     }
 
@@ -211,11 +218,11 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
         // velocity of the output plane j-2, used at the end of this step
         T vcur[4][RY];
         if constexpr (MODE == MODE_STEP) {
-            const long long vb = (long long)clampi(j - 2, 0, n0 - 1) * plane;
+            const unsigned vb = (unsigned)clampi(j - 2, 0, n0 - 1) * (unsigned)plane;
 #pragma unroll
             for (int A = 0; A < 4; ++A)
 #pragma unroll
-                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : vel[A * N3 + vb + offk[k]];
+                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : vel[A][vb + offk[k]];
         }
 
         // stage phi(j) for the y-stencils
@@ -231,6 +238,38 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
         const bool j_out = (j >= xb) && (j < xe);
         const bool j_near = (j <= 3) || (j >= n0 - 4);
 
+        if (kHaloFast && halo_wave) {
+            // y-halo rows: only the y-flux of this plane is needed (by the rows next to them)
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int r = rg + k * R0 + 2;
+                T ax[4], ay[4], az[4];
+#pragma unroll
+                for (int A = 0; A < 4; ++A) {
+                    const T c = ring[S_0][A][k];
+                    ax[A] = c1h * (ring[S_P1][A][k] - ring[S_M1][A][k]) + c2h * (ring[S_P2][A][k] - ring[S_M2][A][k]);
+                    ay[A] = c1h * (sm.phi[A][r + 1][zl] - sm.phi[A][r - 1][zl]) +
+                            c2h * (sm.phi[A][r + 2][zl] - sm.phi[A][r - 2][zl]);
+                    az[A] = c1h * (lane_shift(c, lane, 1) - lane_shift(c, lane, -1)) +
+                            c2h * (lane_shift(c, lane, 2) - lane_shift(c, lane, -2));
+                }
+                const T gxx = dot4(ax, ax), gzz = dot4(az, az);
+                const T gxy = dot4(ax, ay), gyz = dot4(ay, az);
+                const bool valid = lane_flux && yz_in[k] && j_in;
+#pragma unroll
+                for (int A = 0; A < 4; ++A)
+                    sm.qy[A][r - 2][zl] = valid ? (gxx + gzz) * ay[A] - gxy * ax[A] - gyz * az[A] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int A = 0; A < 4; ++A)
+#pragma unroll
+                for (int k = 0; k < RY; ++k)
+#pragma unroll
+                    for (int sl = 0; sl < 4; ++sl) ring[sl][A][k] = ring[sl + 1][A][k];
+            return;
+        }
+
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int r = rg + k * R0 + 2;  // LDS row of this position in sm.phi
@@ -245,21 +284,20 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                 const T yp1 = sm.phi[A][r + 1][zl], yp2 = sm.phi[A][r + 2][zl];
                 const T zm2 = lane_shift(c[A], lane, -2), zm1 = lane_shift(c[A], lane, -1);
                 const T zp1 = lane_shift(c[A], lane, 1), zp2 = lane_shift(c[A], lane, 2);
-                ax[A] = (C::c1 * (xp1 - xm1) + C::c2 * (xp2 - xm2)) * ih;
-                ay[A] = (C::c1 * (yp1 - ym1) + C::c2 * (yp2 - ym2)) * ih;
-                az[A] = (C::c1 * (zp1 - zm1) + C::c2 * (zp2 - zm2)) * ih;
+                ax[A] = c1h * (xp1 - xm1) + c2h * (xp2 - xm2);
+                ay[A] = c1h * (yp1 - ym1) + c2h * (yp2 - ym2);
+                az[A] = c1h * (zp1 - zm1) + c2h * (zp2 - zm2);
                 // the five-point weights sum to zero, so the Laplacian is a weighted sum of
                 // differences from the centre: no cancellation of O(1) terms in single precision
-                const T lap = (C::d1 * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
-                                        ((zp1 - c[A]) + (zm1 - c[A]))) +
-                               C::d2 * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
-                                        ((zp2 - c[A]) + (zm2 - c[A])))) *
-                              ih2;
+                const T lap = d1h * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
+                                     ((zp1 - c[A]) + (zm1 - c[A]))) +
+                              d2h * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
+                                     ((zp2 - c[A]) + (zm2 - c[A])));
                 cl += c[A] * lap;
                 // E2 part of the gradient: -1/2 (Lap phi + Lap(1_I phi)); neighbours outside I
                 // carry weight zero in the second Laplacian
                 T corr = T(0);
-                if (j_near || yz_near[k]) {
+                if ((j_near || tile_near) && (j_near || yz_near[k])) {
                     const int y = yk[k];
                     const bool ox1 = (j + 1 > n0 - 3), ox_1 = (j - 1 < 2), ox2 = (j + 2 > n0 - 3), ox_2 = (j - 2 < 2);
                     const bool oy1 = (y + 1 > n1 - 3), oy_1 = (y - 1 < 2), oy2 = (y + 2 > n1 - 3), oy_2 = (y - 2 < 2);
@@ -275,18 +313,19 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
             const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
             const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
             const bool valid = lane_flux && yz_in[k] && j_in;
-            const T w = valid ? T(1) : T(0);  // flux vanishes outside I
+            // the flux vanishes outside I: zero the Gram entries it is built from
+            const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
+            const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
 #pragma unroll
             for (int A = 0; A < 4; ++A) {
-                const T qx = w * ((gyy + gzz) * ax[A] - gxy * ay[A] - gxz * az[A]);
-                sm.qy[A][r - 2][zl] = w * ((gxx + gzz) * ay[A] - gxy * ax[A] - gyz * az[A]);
-                sm.qz[A][r - 2][zl] = w * ((gxx + gyy) * az[A] - gxz * ax[A] - gyz * ay[A]);
-                // push the x-flux: g(j-1) -= c1 q, g(j+1) += c1 q, g(j-2) -= c2 q, g(j+2) += c2 q
-                const T q = qx * ih;
-                acc[S_M1][A][k] -= C::c1 * q;
-                acc[S_P1][A][k] += C::c1 * q;
-                acc[S_M2][A][k] -= C::c2 * q;
-                acc[S_P2][A][k] += C::c2 * q;
+                const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
+                sm.qy[A][r - 2][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
+                sm.qz[A][r - 2][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
+                // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
+                acc[S_M1][A][k] -= c1h * qx;
+                acc[S_P1][A][k] += c1h * qx;
+                acc[S_M2][A][k] -= c2h * qx;
+                acc[S_P2][A][k] += c2h * qx;
             }
             if (row_out[k] && j_out) {
                 pe2 += (double)(T(-0.5) * cl);
@@ -298,7 +337,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 
         // output plane j-2 is complete
         if (j - 2 >= xb && j - 2 < xe) {
-            const long long base = (long long)(j - 2) * plane;
+            const unsigned base = (unsigned)(j - 2) * (unsigned)plane;
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
                 if (row_out[k]) {
@@ -333,13 +372,13 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                         }
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
-                            pout[A * N3 + base + offk[k]] = pn[A];
-                            vel[A * N3 + base + offk[k]] = v[A];
+                            pout[A][base + offk[k]] = pn[A];
+                            vel[A][base + offk[k]] = v[A];
                         }
                     } else {
-                        if (gout) {
+                        if (has_grad) {
 #pragma unroll
-                            for (int A = 0; A < 4; ++A) gout[A * N3 + base + offk[k]] = projected ? -f[A] : g[A];
+                            for (int A = 0; A < 4; ++A) gout[A][base + offk[k]] = projected ? -f[A] : g[A];
                         }
                     }
                 }
@@ -355,9 +394,9 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
             const int zm2 = max(zl - 2, 0), zm1 = max(zl - 1, 0), zp1 = min(zl + 1, LW - 1), zp2 = min(zl + 2, LW - 1);
 #pragma unroll
             for (int A = 0; A < 4; ++A) {
-                const T dy = C::c1 * (sm.qy[A][rp1][zl] - sm.qy[A][rm1][zl]) + C::c2 * (sm.qy[A][rp2][zl] - sm.qy[A][rm2][zl]);
-                const T dz = C::c1 * (sm.qz[A][r][zp1] - sm.qz[A][r][zm1]) + C::c2 * (sm.qz[A][r][zp2] - sm.qz[A][r][zm2]);
-                acc[S_0][A][k] -= (dy + dz) * ih;
+                const T dy = c1h * (sm.qy[A][rp1][zl] - sm.qy[A][rm1][zl]) + c2h * (sm.qy[A][rp2][zl] - sm.qy[A][rm2][zl]);
+                const T dz = c1h * (sm.qz[A][r][zp1] - sm.qz[A][r][zm1]) + c2h * (sm.qz[A][r][zp2] - sm.qz[A][r][zm2]);
+                acc[S_0][A][k] -= dy + dz;
             }
         }
 
@@ -402,74 +441,114 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
     sw.n2 = a.n2;
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
     sw.plane = n1 * n2;
-    sw.N3 = (long long)n0 * sw.plane;
-    sw.pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
-    sw.pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
-    sw.vel = (T*)a.vel;
-    sw.gout = (T*)a.grad;
+    const long long N3 = (long long)n0 * sw.plane;
+    {
+        const T* pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
+        T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+            sw.pin[A] = pin + A * N3;
+            sw.pout[A] = pout ? pout + A * N3 : nullptr;
+            sw.vel[A] = a.vel ? (T*)a.vel + A * N3 : nullptr;
+            sw.gout[A] = a.grad ? (T*)a.grad + A * N3 : nullptr;
+        }
+    }
+    sw.has_grad = a.grad != nullptr;
     sw.projected = a.projected != 0;
     sw.baryon = a.baryon != 0;
 
-    // tile coordinates
-    const int b = blockIdx.x;
-    const int tz = b % a.tiles_z;
-    const int ty = (b / a.tiles_z) % a.tiles_y;
-    const int tx = b / (a.tiles_z * a.tiles_y);
-    const int z0 = 2 + tz * TL::OZ;
-    const int y0 = 2 + ty * TL::OY;
-    sw.xb = 2 + tx * a.xchunk;
-    sw.xe = min(sw.xb + a.xchunk, n0 - 2);
+    sw.c1h = T(Coef<double>::c1 / a.h);
+    sw.c2h = T(Coef<double>::c2 / a.h);
+    sw.d1h = T(Coef<double>::d1 / (a.h * a.h));
+    sw.d2h = T(Coef<double>::d2 / (a.h * a.h));
+    sw.ih2 = T(1.0 / (a.h * a.h));
+    sw.dt = T(a.dt);
+    sw.m2 = T(a.m * a.m);
 
     const int tid = threadIdx.x;
     sw.lane = tid & 63;
     const int wave = tid >> 6;
     sw.zl = sw.lane % LW;
     sw.rg = wave * TL::RPW + sw.lane / LW;
-    sw.z = z0 - 4 + sw.zl;
-    const int zc = clampi(sw.z, 0, n2 - 1);
     sw.lane_flux = (sw.zl >= 2) && (sw.zl < LW - 2);
-    const bool lane_out = (sw.zl >= 4) && (sw.zl < LW - 4) && (sw.z <= n2 - 3);
-    const bool z_in = (sw.z >= 2) && (sw.z <= n2 - 3);
-    const bool z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
-#pragma unroll
-    for (int k = 0; k < RY; ++k) {
-        const int r = sw.rg + k * R0;
-        const int y = y0 - 2 + r;
-        sw.yk[k] = y;
-        sw.offk[k] = clampi(y, 0, n1 - 1) * n2 + zc;
-        sw.row_out[k] = (r >= 2) && (r < PY - 2) && (y <= n1 - 3) && lane_out;
-        sw.yz_in[k] = z_in && (y >= 2) && (y <= n1 - 3);
-        sw.yz_near[k] = z_near || (y <= 3) || (y >= n1 - 4);
-    }
-    // halo rows of the phi plane: LDS rows 0, 1, PY+2, PY+3
     sw.halo_loader = tid < 4 * LW;
     sw.hrow = sw.halo_loader ? (tid / LW < 2 ? tid / LW : PY + tid / LW) : 0;
     sw.hz = tid % LW;
-    sw.hoff = clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hz, 0, n2 - 1);
+    {
+        // rows of this wave: w*RPW + (0..RPW-1) + k*R0; all of them in {0, 1, PY-2, PY-1}?
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        bool all_halo = true;
+        for (int k = 0; k < RY; ++k)
+            for (int q = 0; q < TL::RPW; ++q) {
+                const int r = wv * TL::RPW + q + k * R0;
+                all_halo = all_halo && (r < 2 || r >= PY - 2);
+            }
+        sw.halo_wave = all_halo;
+    }
 
-    sw.ih = T(1.0 / a.h);
-    sw.ih2 = T(1.0 / (a.h * a.h));
-    sw.dt = T(a.dt);
-    sw.m2 = T(a.m * a.m);
+    // Work items: x is cut into slabs of `xchunk` planes; an item is one (y, z) tile of
+    // one slab, items ordered slab-major with the tiles of a slab consecutive.  Items are
+    // divided evenly over the launched blocks.  Blocks are dispatched round-robin over the
+    // eight XCDs (block b to XCD b % 8); logical indices are assigned so that each XCD holds
+    // a contiguous run of items -- neighbouring tiles of one slab, which march through the
+    // same planes and share halo rows in one L2.
+    const int nb = gridDim.x;
+    const int xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
+    const int b = xcd * q8 + min(xcd, r8) + (int)blockIdx.x / 8;
+    const int nx = n0 - 4;
+    const int ncols = a.tiles_z * a.tiles_y;
+    const int nslabs = (nx + a.xchunk - 1) / a.xchunk;
+    const long long W = (long long)ncols * nslabs;
+    const long long w1 = W * (b + 1) / nb;
+    for (long long w = W * b / nb; w < w1; ++w) {
+        const int slab = (int)(w / ncols);
+        const int tile = (int)(w % ncols);
+        const int x0 = slab * a.xchunk;
+        const int x1 = min(nx, x0 + a.xchunk);
+        const int tz = tile % a.tiles_z;
+        const int ty = tile / a.tiles_z;
+        const int z0 = 2 + tz * TL::OZ;
+        const int y0 = 2 + ty * TL::OY;
+        sw.xb = 2 + x0;
+        sw.xe = 2 + x1;
+        sw.z = z0 - 4 + sw.zl;
+        const int zc = clampi(sw.z, 0, n2 - 1);
+        const bool lane_out = (sw.zl >= 4) && (sw.zl < LW - 4) && (sw.z <= n2 - 3);
+        const bool z_in = (sw.z >= 2) && (sw.z <= n2 - 3);
+        const bool z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
+#pragma unroll
+        for (int k = 0; k < RY; ++k) {
+            const int r = sw.rg + k * R0;
+            const int y = y0 - 2 + r;
+            sw.yk[k] = y;
+            sw.offk[k] = (unsigned)(clampi(y, 0, n1 - 1) * n2 + zc);
+            sw.row_out[k] = (r >= 2) && (r < PY - 2) && (y <= n1 - 3) && lane_out;
+            sw.yz_in[k] = z_in && (y >= 2) && (y <= n1 - 3);
+            sw.yz_near[k] = z_near || (y <= 3) || (y >= n1 - 4);
+        }
+        // halo rows of the phi plane: LDS rows 0, 1, PY+2, PY+3
+        sw.hoff = (unsigned)(clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hz, 0, n2 - 1));
+        // does any output site of this tile lie within two sites of a y or z face of I
+        sw.tile_near = (y0 <= 3) || (y0 + TL::OY - 1 >= n1 - 4) || (z0 <= 3) || (z0 + TL::OZ - 1 >= n2 - 4);
 
 #pragma unroll
-    for (int s = 0; s < 5; ++s)
+        for (int s = 0; s < 5; ++s)
 #pragma unroll
-        for (int A = 0; A < 4; ++A)
+            for (int A = 0; A < 4; ++A)
 #pragma unroll
-            for (int k = 0; k < RY; ++k) sw.acc[s][A][k] = T(0);
+                for (int k = 0; k < RY; ++k) sw.acc[s][A][k] = T(0);
 
-    // prologue: ring slots 0..3 hold planes jstart-2 .. jstart+1; nxt holds jstart+2
-    const int jstart = sw.xb - 2;
-    const int nst = (sw.xe - sw.xb) + 4;
-    sw.load_plane(jstart - 2, sw.ring[0]);
-    sw.load_plane(jstart - 1, sw.ring[1]);
-    sw.load_plane(jstart, sw.ring[2]);
-    sw.load_plane(jstart + 1, sw.ring[3]);
-    sw.load_plane(jstart + 2, sw.nxt);
-    sw.load_halo(jstart, sw.hnxt);
-
-    for (int s = 0; s < nst; ++s) sw.step(jstart + s);
+        // prologue: ring slots 0..3 hold planes jstart-2 .. jstart+1; nxt holds jstart+2
+        const int jstart = sw.xb - 2;
+        const int nst = (sw.xe - sw.xb) + 4;
+        sw.load_plane(jstart - 2, sw.ring[0]);
+        sw.load_plane(jstart - 1, sw.ring[1]);
+        sw.load_plane(jstart, sw.ring[2]);
+        sw.load_plane(jstart + 1, sw.ring[3]);
+        sw.load_plane(jstart + 2, sw.nxt);
+        sw.load_halo(jstart, sw.hnxt);
+        for (int st = 0; st < nst; ++st) sw.step(jstart + st);
+    }
 
     // block reduction of the partial sums (fixed order)
     double vals[5] = {sw.pe2, sw.pe4, sw.pe0, sw.pb, (double)sw.pf2};
@@ -489,13 +568,13 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
     }
     __syncthreads();
     if (tid == 0) {
-        double s[5] = {0, 0, 0, 0, 0};
-        for (int w = 0; w < NW; ++w) {
-            for (int i = 0; i < 4; ++i) s[i] += smem.red[w][i];
-            s[4] = fmax(s[4], smem.red[w][4]);
+        double sum[5] = {0, 0, 0, 0, 0};
+        for (int wv = 0; wv < NW; ++wv) {
+            for (int i = 0; i < 4; ++i) sum[i] += smem.red[wv][i];
+            sum[4] = fmax(sum[4], smem.red[wv][4]);
         }
         double* out = a.partials + (size_t)b * NPART;
-        for (int i = 0; i < 5; ++i) out[i] = s[i];
+        for (int i = 0; i < 5; ++i) out[i] = sum[i];
     }
 }
 

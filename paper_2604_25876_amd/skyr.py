@@ -96,6 +96,14 @@ _SIGNATURES = {
                                      _P]),
     "skyr_observables": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
                                         ctypes.POINTER(Obs), _P, _P]),
+    "skyr_tile_variants": (ctypes.c_int32, [ctypes.c_int]),
+    "skyr_tile_variant_info": (ctypes.c_int, [ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_set_tile": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    "skyr_get_tile": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_autotune": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                     ctypes.POINTER(Flow), _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "skyr_timing_enable": (None, [ctypes.c_int32]),
     "skyr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -278,3 +286,66 @@ def timing_read() -> tuple[float, int]:
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().skyr_timing_read(ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+# ------------------------------------------------------------------ tiles
+def tile_variants(prec: int) -> list[tuple[int, int, int]]:
+    """Compiled sweep shapes (waves per block, lanes per row, flux rows per thread)."""
+    out = []
+    for v in range(lib().skyr_tile_variants(prec)):
+        info = (ctypes.c_int32 * 3)()
+        _check(lib().skyr_tile_variant_info(prec, v, info))
+        out.append(tuple(int(x) for x in info))
+    return out
+
+
+def set_tile(lat: Lattice, prec: int, variant: int, xchunk: int) -> None:
+    _check(lib().skyr_set_tile(ctypes.byref(lat), prec, int(variant), int(xchunk)))
+
+
+def get_tile(lat: Lattice, prec: int) -> tuple[int, int]:
+    v, x = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().skyr_get_tile(ctypes.byref(lat), prec, ctypes.byref(v), ctypes.byref(x)))
+    return int(v.value), int(x.value)
+
+
+def autotune(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work, stream=None):
+    """Measure every shape / slab length on this lattice and keep the fastest.
+    Returns (variant, planes per slab, sweep microseconds).  vel is zeroed."""
+    shape = (4,) + lat.shape
+    dt = field_dtype(prec)
+    v, x, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().skyr_autotune(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
+                               _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
+                               _dev_ptr(work), _stream(stream), ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
+    return int(v.value), int(x.value), float(us.value)
+
+
+def _cache_path():
+    import os
+    return os.environ.get("SKYR_TUNE_CACHE")
+
+
+def autotune_cached(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work, stream=None):
+    """autotune() with a JSON cache keyed by lattice dimensions and precision
+    (file named by the SKYR_TUNE_CACHE environment variable; no cache if unset)."""
+    import json
+    import os
+    path = _cache_path()
+    key = f"{lat.shape[0]}x{lat.shape[1]}x{lat.shape[2]}:{'f64' if prec == F64 else 'f32'}"
+    table = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+        if key in table:
+            v, x = table[key]["variant"], table[key]["xchunk"]
+            set_tile(lat, prec, v, x)
+            return v, x, table[key].get("us")
+    v, x, us = autotune(lat, prec, model, flow, phi, phi_alt, vel, work, stream)
+    if path:
+        table[key] = {"variant": v, "xchunk": x, "us": us}
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return v, x, us
