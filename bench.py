@@ -110,6 +110,66 @@ def sweep_tiles(skyr, torch, w, prec_name, steps=20):
     return rows
 
 
+def _job_buffers(skyr, torch, d):
+    prec = skyr.F32_BULK if d["precision"] == "f32" else skyr.F64
+    lat = skyr.Lattice.cube(d["n"], d["h"])
+    dev = torch.device("cuda:0")
+    phi = skyr.new_field(lat, prec, dev)
+    spec, keep = skyr.spec_from_description(d["init"])
+    skyr.init_field(lat, prec, spec, phi)
+    alt, vel = skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
+    work = skyr.new_workspace(lat, prec, dev)
+    flow = skyr.Flow(d["dt"], 0.0, 10 ** 12, 16, 0)
+    return lat, prec, phi, alt, vel, work, flow
+
+
+def batch_throughput(skyr, torch, jobs, sweeps=64):
+    """The same jobs stepped `sweeps` times (a) together in one batch (one
+    launch per precision and sweep slot, replayed from a captured graph) and
+    (b) one at a time through skyr_anf_step; site-updates/s of each."""
+    bufs = [_job_buffers(skyr, torch, d) for d in jobs]
+    with skyr.Batch(len(jobs)) as b:
+        slots = [b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
+                 for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs)]
+        b.run(8)  # warm-up, graph capture
+        steps0 = [b.poll(s).steps for s in slots]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(sweeps)
+        t_batch = time.perf_counter() - t0
+        upd_b = sum((b.poll(s).steps - s0) * (d["n"] - 4) ** 3 for s, s0, d in zip(slots, steps0, jobs))
+    bufs = [_job_buffers(skyr, torch, d) for d in jobs]
+    for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs):
+        skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, skyr.anf_state(), 8, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_s = 0
+    for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs):
+        st = skyr.anf_state()
+        skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, sweeps, work)
+        steps_s += st.steps * (d["n"] - 4) ** 3
+    t_seq = time.perf_counter() - t0
+    return {"jobs": len(jobs), "sweeps": sweeps, "batched_site_updates_per_s": upd_b / t_batch,
+            "sequential_site_updates_per_s": steps_s / t_seq, "batched_s": t_batch, "sequential_s": t_seq,
+            "speedup": (upd_b / t_batch) / (steps_s / t_seq)}
+
+
+def served_stream(skyr, torch, count=24, cap=1000, rate=40.0):
+    from paper_2604_25876_amd.serve import GpuBackend, Request, Server
+    from skyr_inputs import served_stream as stream
+    reqs = []
+    for i, d in enumerate(stream(5, count, rate)):
+        d = dict(d, steps=cap)
+        reqs.append(Request(d, arrival=d["arrival"], rid=i))
+    free, total = torch.cuda.mem_get_info()
+    be = GpuBackend(max_jobs=32)
+    srv = Server(be, max_jobs=32, hbm_budget=int(0.8 * free), sweeps_per_tick=32)
+    rep = srv.serve(reqs)
+    be.close()
+    rep.update({"rate_per_s": rate, "step_cap": cap, "tol": 1e-4})
+    return rep
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle (as it stands) on the host cores: a few flow steps of the
     same 256^3 initial field, scaled to site-updates/s."""
@@ -145,6 +205,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched and served workloads")
+    ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="print the sweep time of every compiled tile shape and x-chunk, then exit")
     ap.add_argument("--copy-probe", action="store_true",
@@ -183,6 +245,13 @@ def main():
     print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
     r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup)
     print(f"# f64: {r64}", file=sys.stderr, flush=True)
+    batch = serve = None
+    if not args.no_batch:
+        from skyr_inputs import batch_jobs
+        batch = batch_throughput(skyr, torch, batch_jobs(4, 64))
+        print(f"# batch: {batch}", file=sys.stderr, flush=True)
+        serve = served_stream(skyr, torch, count=args.serve_jobs)
+        print(f"# serve: {serve}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W)
@@ -215,6 +284,10 @@ def main():
                      "kernel": "sweep_kernel<float> (step mode)",
                      "kernel_avg_us": r32["sweep_kernel_avg_us"], "bytes_per_launch": r32["bytes_per_launch"]},
         "cpu_baseline": cpu,
+        "batched_64_jobs": batch,
+        "served": serve,
+        "latency_p50_s": serve["latency_p50_s"] if serve else None,
+        "latency_p99_s": serve["latency_p99_s"] if serve else None,
     }
     print(json.dumps(line), flush=True)
 

@@ -220,6 +220,38 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                              const void* phi, skyr_obs* out, void* work, void* stream);
 
+/* Batches: many independent flows (uneven lattices, charges, masses and
+ * precisions) advanced together.  Per sweep slot, one persistent launch per
+ * precision covers every active field's tiles, followed by one finaliser
+ * launch (one block per field); skyr_batch_run replays a captured hipGraph of
+ * `sweeps` slots.  Each field's blocks, partial sums and decisions are those
+ * of the same field flowing alone (the batched sweep uses tile shape 0 of its
+ * precision and the lattice's slab length), so a field's result does not
+ * depend on the other fields in the batch.  A batch object owns only its job
+ * table, control blocks and graph; field, velocity and workspace memory stay
+ * with the caller and must stay valid while the field is in the batch.  A
+ * batch is used by one thread at a time.
+ *   skyr_batch_create  max_jobs slots; work is enqueued on `stream`
+ *   skyr_batch_add     a fresh flow (state as after skyr_anf_state_init, zero
+ *                      velocity); runs until max|F| < flow->tol or
+ *                      flow->max_steps accepted steps; returns its slot
+ *   skyr_batch_run     `sweeps` sweep slots for every active field; waits for
+ *                      them; SKYR_E_BUSY never; errors as skyr_anf_step
+ *   skyr_batch_poll    state of a slot after the last run; once the field has
+ *                      stopped, its result is (copied if needed) in phi
+ *   skyr_batch_remove  frees the slot (phi then holds the field's last state)
+ *   skyr_batch_active  number of occupied slots */
+typedef struct skyr_batch skyr_batch;
+SKYR_API skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out);
+SKYR_API skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
+                                    const skyr_model* model, const skyr_flow* flow, void* phi, void* phi_alt,
+                                    void* vel, void* work, int32_t* slot);
+SKYR_API skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps);
+SKYR_API skyr_status skyr_batch_poll(skyr_batch* b, int32_t slot, skyr_anf_state* st);
+SKYR_API skyr_status skyr_batch_remove(skyr_batch* b, int32_t slot);
+SKYR_API int32_t skyr_batch_active(const skyr_batch* b);
+SKYR_API skyr_status skyr_batch_destroy(skyr_batch* b);
+
 /* Tile shapes of the fused sweep.  A few shapes (waves per block, lanes per
  * row, flux rows per thread) are compiled per precision; x is cut into slabs
  * of `xchunk` (>= 16) planes and one block marches one (y, z) tile of one

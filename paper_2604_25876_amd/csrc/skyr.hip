@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -290,7 +291,7 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
 // The flow's decision after the sweep over phi_k (Sec. 3): arrest when
 // E_k > E_{k-1} (re-run the sweep with v_k = 0), stop when max|F_k| < tol,
 // otherwise accept the update (swap buffers).
-__global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl)
+__device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;  // uniform
     double s[5];
@@ -336,6 +337,16 @@ __global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict
     }
 }
 
+__global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl) { finalize_flow(part, ctl); }
+
+// one block per field of a batch
+__global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, int njobs)
+{
+    const int j = blockIdx.x;
+    if (j >= njobs) return;
+    finalize_flow(jobs[j].partials, jobs[j].ctl);
+}
+
 // ------------------------------------------------------------- launches
 template <typename T, int NW, int LW, int RY>
 static hipError_t launch_shape(int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
@@ -362,6 +373,39 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
     ++v;
         SKYR_SHAPES_F32(SKYR_CASE32)
 #undef SKYR_CASE32
+    }
+    return hipErrorInvalidValue;
+}
+
+// The batched sweep uses the first compiled shape of each precision.
+template <typename T, int NW, int LW, int RY>
+static hipError_t launch_batch(int blocks, const SweepArgs* jobs, const int* map, const int* first, const int* count,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map, first, count);
+    return hipGetLastError();
+}
+
+static hipError_t batch_sweep(skyr_precision prec, int blocks, const SweepArgs* jobs, const int* map, const int* first,
+                              const int* count, hipStream_t s)
+{
+    // shape 0 of each list
+    if (prec == SKYR_F64) {
+        const Shape& sh = kShapesF64[0];
+        int v = 0;
+#define SKYR_B64(a, b, c)                                                                                    \
+    if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
+        return launch_batch<double, a, b, c>(blocks, jobs, map, first, count, s);
+        SKYR_SHAPES_F64(SKYR_B64)
+#undef SKYR_B64
+    } else {
+        const Shape& sh = kShapesF32[0];
+        int v = 0;
+#define SKYR_B32(a, b, c)                                                                                    \
+    if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
+        return launch_batch<float, a, b, c>(blocks, jobs, map, first, count, s);
+        SKYR_SHAPES_F32(SKYR_B32)
+#undef SKYR_B32
     }
     return hipErrorInvalidValue;
 }
@@ -857,6 +901,317 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     if (variant_out) *variant_out = bv;
     if (xchunk_out) *xchunk_out = bx;
     if (best_us_out) *best_us_out = best;
+    return SKYR_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batches
+// A batch owns only its job table, the control blocks and the captured graph;
+// field, velocity and workspace memory stay with the caller.
+struct skyr_batch {
+    struct Job {
+        bool active = false;
+        skyr_lattice lat{};
+        skyr_precision prec = SKYR_F64;
+        Launch L{};
+        void* phi = nullptr;
+        void* phi_alt = nullptr;
+    };
+    int max_jobs = 0;
+    hipStream_t stream = nullptr;    // caller's stream (work is launched here)
+    hipStream_t capture = nullptr;   // private stream used only to capture the graph
+    std::vector<Job> jobs;
+    std::vector<SweepArgs> args;     // host mirror of d_args
+    std::vector<Ctl> ctl;            // host mirror of d_ctl (valid after a run / poll)
+    Ctl* d_ctl = nullptr;            // [max_jobs]
+    SweepArgs* d_args = nullptr;     // [max_jobs]
+    int* d_first = nullptr;          // [max_jobs] first block of a job in its precision's grid
+    int* d_count = nullptr;          // [max_jobs] blocks of a job
+    int* d_map[2] = {nullptr, nullptr};  // block -> job, per precision
+    int map_cap[2] = {0, 0};
+    int grid[2] = {0, 0};
+    bool dirty = true;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_sweeps = 0;
+};
+
+namespace skyr {
+
+static void batch_release_graph(skyr_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_sweeps = 0;
+}
+
+// rebuild the device job tables and block maps from the host description
+static skyr_status batch_rebuild(skyr_batch* b)
+{
+    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[2];
+    for (int j = 0; j < b->max_jobs; ++j) {
+        const auto& J = b->jobs[j];
+        if (!J.active) continue;
+        const int p = J.prec == SKYR_F64 ? 0 : 1;
+        first[j] = (int)map[p].size();
+        count[j] = J.L.blocks();
+        map[p].insert(map[p].end(), count[j], j);
+    }
+    for (int p = 0; p < 2; ++p) {
+        const int n = (int)map[p].size();
+        if (n > b->map_cap[p]) {
+            if (b->d_map[p]) SKYR_HIP(hipFree(b->d_map[p]));
+            b->d_map[p] = nullptr;
+            SKYR_HIP(hipMalloc((void**)&b->d_map[p], sizeof(int) * n));
+            b->map_cap[p] = n;
+        }
+        if (n) SKYR_HIP(hipMemcpy(b->d_map[p], map[p].data(), sizeof(int) * n, hipMemcpyHostToDevice));
+        b->grid[p] = n;
+    }
+    SKYR_HIP(hipMemcpy(b->d_first, first.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
+    SKYR_HIP(hipMemcpy(b->d_count, count.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
+    SKYR_HIP(hipMemcpy(b->d_args, b->args.data(), sizeof(SweepArgs) * b->max_jobs, hipMemcpyHostToDevice));
+    batch_release_graph(b);
+    b->dirty = false;
+    return SKYR_OK;
+}
+
+// capture `sweeps` sweep slots: per slot, the batched sweep of each precision and the finaliser
+static skyr_status batch_capture(skyr_batch* b, int sweeps)
+{
+    batch_release_graph(b);
+    SKYR_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
+        if (b->grid[0] && e == hipSuccess)
+            e = batch_sweep(SKYR_F64, b->grid[0], b->d_args, b->d_map[0], b->d_first, b->d_count, b->capture);
+        if (b->grid[1] && e == hipSuccess)
+            e = batch_sweep(SKYR_F32_BULK, b->grid[1], b->d_args, b->d_map[1], b->d_first, b->d_count, b->capture);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->max_jobs), dim3(256), 0, b->capture, b->d_args,
+                               b->max_jobs);
+            e = hipGetLastError();
+        }
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SKYR_E_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    SKYR_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    b->graph_sweeps = sweeps;
+    return SKYR_OK;
+}
+
+}  // namespace skyr
+
+extern "C" {
+
+skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
+{
+    if (!out || max_jobs < 1 || max_jobs > 4096) return fail(SKYR_E_INVAL, "max_jobs must be 1..4096, out non-null");
+    *out = nullptr;
+    skyr_batch* b = new (std::nothrow) skyr_batch();
+    if (!b) return fail(SKYR_E_NOMEM, "host allocation failed");
+    b->max_jobs = max_jobs;
+    b->stream = (hipStream_t)stream;
+    b->jobs.resize(max_jobs);
+    b->args.assign(max_jobs, SweepArgs{});
+    b->ctl.assign(max_jobs, Ctl{});
+    for (auto& c : b->ctl) c.done = 1;  // empty slots do nothing
+    auto cleanup = [&](hipError_t e) {
+        (void)hipFree(b->d_ctl);
+        (void)hipFree(b->d_args);
+        (void)hipFree(b->d_first);
+        (void)hipFree(b->d_count);
+        if (b->capture) (void)hipStreamDestroy(b->capture);
+        delete b;
+        return fail(SKYR_E_DEVICE, std::string("skyr_batch_create: ") + hipGetErrorString(e));
+    };
+    hipError_t e = hipMalloc((void**)&b->d_ctl, sizeof(Ctl) * max_jobs);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_args, sizeof(SweepArgs) * max_jobs);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_first, sizeof(int) * max_jobs);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_count, sizeof(int) * max_jobs);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpy(b->d_ctl, b->ctl.data(), sizeof(Ctl) * max_jobs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(e);
+    // every slot points at its own (done) control block
+    for (int j = 0; j < max_jobs; ++j) b->args[j].ctl = b->d_ctl + j;
+    *out = b;
+    return SKYR_OK;
+}
+
+skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, void* work, int32_t* slot)
+{
+    if (!b) return fail(SKYR_E_INVAL, "batch is null");
+    skyr_status rc = check_common(lat, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
+        return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
+    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    int j = -1;
+    for (int k = 0; k < b->max_jobs; ++k)
+        if (!b->jobs[k].active) {
+            j = k;
+            break;
+        }
+    if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
+    // the batched sweep uses shape 0 of the precision; the slab length follows the lattice's setting
+    Launch L = plan(lat, prec);
+    L = plan_with(lat, prec, 0, L.xchunk);
+    SweepArgs a = make_args(lat, L, model->m, flow->dt);
+    a.phi0 = phi;
+    a.phi1 = phi_alt;
+    a.vel = vel;
+    a.partials = (double*)((char*)work + CTL_BYTES + OBS_BYTES);
+    a.ctl = b->d_ctl + j;
+    Ctl h{};
+    h.target = flow->max_steps;
+    h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
+    h.nblocks = L.blocks();
+    h.E_prev = INFINITY;
+    h.E = NAN;
+    h.max_force = NAN;
+    h.tol = flow->tol;
+    h.h3 = lat->h * lat->h * lat->h;
+    h.done = flow->max_steps <= 0 ? 1 : 0;
+    h.status = h.done ? 2 : 0;
+    hipStream_t s = b->stream;
+    SKYR_HIP(hipMemcpyAsync(b->d_ctl + j, &h, sizeof h, hipMemcpyHostToDevice, s));
+    {
+        const long long N3 = sites(lat);
+        const int blocks = (int)std::min<long long>((N3 + 255) / 256, 8192);
+        if (prec == SKYR_F64)
+            hipLaunchKernelGGL(copy_frozen_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)phi,
+                               (double*)phi_alt, lat->n[0], lat->n[1], lat->n[2]);
+        else
+            hipLaunchKernelGGL(copy_frozen_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)phi,
+                               (float*)phi_alt, lat->n[0], lat->n[1], lat->n[2]);
+        SKYR_HIP(hipGetLastError());
+    }
+    SKYR_HIP(hipStreamSynchronize(s));
+    auto& J = b->jobs[j];
+    J.active = true;
+    J.lat = *lat;
+    J.prec = prec;
+    J.L = L;
+    J.phi = phi;
+    J.phi_alt = phi_alt;
+    b->args[j] = a;
+    b->ctl[j] = h;
+    b->dirty = true;
+    if (slot) *slot = j;
+    return SKYR_OK;
+}
+
+skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
+{
+    if (!b || sweeps < 1) return fail(SKYR_E_INVAL, "batch must be non-null and sweeps >= 1");
+    if (b->dirty) {
+        skyr_status rc = batch_rebuild(b);
+        if (rc != SKYR_OK) return rc;
+    }
+    if (b->grid[0] + b->grid[1] > 0) {
+        if (!b->exec || b->graph_sweeps != sweeps) {
+            skyr_status rc = batch_capture(b, sweeps);
+            if (rc != SKYR_OK) return rc;
+        }
+        SKYR_HIP(hipGraphLaunch(b->exec, b->stream));
+    }
+    SKYR_HIP(hipMemcpyAsync(b->ctl.data(), b->d_ctl, sizeof(Ctl) * b->max_jobs, hipMemcpyDeviceToHost, b->stream));
+    SKYR_HIP(hipStreamSynchronize(b->stream));
+    return SKYR_OK;
+}
+
+static void state_from_ctl(const Ctl& h, skyr_anf_state* st)
+{
+    st->steps = h.steps;
+    st->arrests = h.arrests;
+    st->redo_sweeps = h.redo_sweeps;
+    st->sweeps = h.sweeps;
+    st->E_prev = h.E_prev;
+    st->E = h.E;
+    st->max_force = h.max_force;
+    st->converged = h.status == 1;
+    st->redo_pending = h.redo;
+    st->nonfinite = h.status == 3;
+    st->_pad = 0;
+}
+
+// once a field has stopped, make sure its result sits in phi
+static skyr_status batch_settle(skyr_batch* b, int j)
+{
+    Ctl& h = b->ctl[j];
+    if (h.cur == 1) {
+        const auto& J = b->jobs[j];
+        SKYR_HIP(hipMemcpyAsync(J.phi, J.phi_alt, 4 * sites(&J.lat) * elem_bytes(J.prec), hipMemcpyDeviceToDevice,
+                                b->stream));
+        h.cur = 0;
+        SKYR_HIP(hipMemcpyAsync(&b->d_ctl[j].cur, &h.cur, sizeof h.cur, hipMemcpyHostToDevice, b->stream));
+        SKYR_HIP(hipStreamSynchronize(b->stream));
+    }
+    return SKYR_OK;
+}
+
+skyr_status skyr_batch_poll(skyr_batch* b, int32_t slot, skyr_anf_state* st)
+{
+    if (!b || !st || slot < 0 || slot >= b->max_jobs || !b->jobs[slot].active)
+        return fail(SKYR_E_INVAL, "no such active batch slot");
+    const Ctl& h = b->ctl[slot];
+    if (h.done) {
+        skyr_status rc = batch_settle(b, slot);
+        if (rc != SKYR_OK) return rc;
+    }
+    state_from_ctl(h, st);
+    if (st->nonfinite) return fail(SKYR_E_NONFINITE, "energy or force is not finite");
+    return SKYR_OK;
+}
+
+skyr_status skyr_batch_remove(skyr_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_jobs || !b->jobs[slot].active)
+        return fail(SKYR_E_INVAL, "no such active batch slot");
+    skyr_status rc = batch_settle(b, slot);
+    if (rc != SKYR_OK) return rc;
+    b->jobs[slot].active = false;
+    Ctl h{};
+    h.done = 1;
+    b->ctl[slot] = h;
+    b->args[slot] = SweepArgs{};
+    b->args[slot].ctl = b->d_ctl + slot;
+    SKYR_HIP(hipMemcpy(b->d_ctl + slot, &h, sizeof h, hipMemcpyHostToDevice));
+    b->dirty = true;
+    return SKYR_OK;
+}
+
+int32_t skyr_batch_active(const skyr_batch* b)
+{
+    if (!b) return 0;
+    int n = 0;
+    for (const auto& J : b->jobs) n += J.active ? 1 : 0;
+    return n;
+}
+
+skyr_status skyr_batch_destroy(skyr_batch* b)
+{
+    if (!b) return SKYR_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_release_graph(b);
+    (void)hipFree(b->d_ctl);
+    (void)hipFree(b->d_args);
+    (void)hipFree(b->d_first);
+    (void)hipFree(b->d_count);
+    for (int p = 0; p < 2; ++p) (void)hipFree(b->d_map[p]);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
     return SKYR_OK;
 }
 

@@ -415,14 +415,16 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     }
 };
 
+// One block's share of one field: logical block b of nb blocks covering the
+// field's work items.  Used by the single-field and the batched kernels.
 template <typename T, int NW, int LW, int RY, int MODE>
-__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
+                                            typename Sweeper<T, NW, LW, RY, MODE>::Smem& smem)
 {
     using SW = Sweeper<T, NW, LW, RY, MODE>;
     using TL = typename SW::TL;
     constexpr int PY = TL::PY;
     constexpr int R0 = TL::R0;
-    __shared__ typename SW::Smem smem;
 
     const Ctl* ctl = a.ctl;
     int cur = 0;
@@ -488,13 +490,7 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 
     // Work items: x is cut into slabs of `xchunk` planes; an item is one (y, z) tile of
     // one slab, items ordered slab-major with the tiles of a slab consecutive.  Items are
-    // divided evenly over the launched blocks.  Blocks are dispatched round-robin over the
-    // eight XCDs (block b to XCD b % 8); logical indices are assigned so that each XCD holds
-    // a contiguous run of items -- neighbouring tiles of one slab, which march through the
-    // same planes and share halo rows in one L2.
-    const int nb = gridDim.x;
-    const int xcd = blockIdx.x % 8, q8 = nb / 8, r8 = nb % 8;
-    const int b = xcd * q8 + min(xcd, r8) + (int)blockIdx.x / 8;
+    // divided evenly over the nb logical blocks of this field.
     const int nx = n0 - 4;
     const int ncols = a.tiles_z * a.tiles_y;
     const int nslabs = (nx + a.xchunk - 1) / a.xchunk;
@@ -576,6 +572,39 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
         double* out = a.partials + (size_t)b * NPART;
         for (int i = 0; i < 5; ++i) out[i] = sum[i];
     }
+}
+
+// Blocks are dispatched round-robin over the eight XCDs (block i to XCD i % 8).
+// The logical index gives each XCD a contiguous run: neighbouring tiles of one
+// slab, which march through the same planes and share halo rows in one L2.
+__device__ __forceinline__ int xcd_logical_block(int i, int n)
+{
+    const int xcd = i % 8, q8 = n / 8, r8 = n % 8;
+    return xcd * q8 + min(xcd, r8) + i / 8;
+}
+
+template <typename T, int NW, int LW, int RY, int MODE>
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+{
+    __shared__ typename Sweeper<T, NW, LW, RY, MODE>::Smem smem;
+    const int nb = gridDim.x;
+    sweep_block<T, NW, LW, RY, MODE>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
+}
+
+// Many fields in one launch: block i (after the XCD remap) belongs to field
+// job_of_block[i] and is its block (i - first_block[job]); every field's blocks
+// and partial sums are exactly those of a launch of that field alone.
+template <typename T, int NW, int LW, int RY>
+__global__ __launch_bounds__(NW * 64) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
+                                                              const int* __restrict__ job_of_block,
+                                                              const int* __restrict__ first_block,
+                                                              const int* __restrict__ blocks_of_job)
+{
+    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP>::Smem smem;
+    const int i = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int j = job_of_block[i];
+    const SweepArgs a = jobs[j];
+    sweep_block<T, NW, LW, RY, MODE_STEP>(a, i - first_block[j], blocks_of_job[j], smem);
 }
 
 }  // namespace skyr

@@ -104,6 +104,14 @@ _SIGNATURES = {
     "skyr_autotune": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "skyr_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    "skyr_batch_add": (ctypes.c_int, [_P, ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                      ctypes.POINTER(Flow), _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_batch_run": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "skyr_batch_poll": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(AnfState)]),
+    "skyr_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "skyr_batch_active": (ctypes.c_int32, [_P]),
+    "skyr_batch_destroy": (ctypes.c_int, [_P]),
     "skyr_timing_enable": (None, [ctypes.c_int32]),
     "skyr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -349,3 +357,58 @@ def autotune_cached(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_
             json.dump(table, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
     return v, x, us
+
+
+# ---------------------------------------------------------------- batches
+class Batch:
+    """Owner of a skyr_batch (many flows advanced by shared launches).  Field,
+    velocity and workspace tensors belong to the caller and must stay alive
+    while their flow is in the batch."""
+
+    def __init__(self, max_jobs: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().skyr_batch_create(int(max_jobs), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.max_jobs = int(max_jobs)
+
+    def add(self, lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work) -> int:
+        shape = (4,) + lat.shape
+        dt = field_dtype(prec)
+        slot = ctypes.c_int32()
+        _check(lib().skyr_batch_add(self._h, ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
+                                    _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
+                                    _dev_ptr(vel, dt, shape), _dev_ptr(work), ctypes.byref(slot)))
+        return int(slot.value)
+
+    def run(self, sweeps: int) -> None:
+        _check(lib().skyr_batch_run(self._h, int(sweeps)))
+
+    def poll(self, slot: int) -> AnfState:
+        st = AnfState()
+        status = lib().skyr_batch_poll(self._h, int(slot), ctypes.byref(st))
+        if status not in (OK, E_NONFINITE):
+            _check(status)
+        return st
+
+    def remove(self, slot: int) -> None:
+        _check(lib().skyr_batch_remove(self._h, int(slot)))
+
+    def active(self) -> int:
+        return int(lib().skyr_batch_active(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().skyr_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

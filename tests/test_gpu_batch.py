@@ -1,0 +1,120 @@
+"""GPU: batched flows (one launch per sweep slot for all fields) and the
+serving loop.  Every field's result must be bitwise the same alone and in
+the mix, and equal to the single-field entry point's result."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def skyr():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2604_25876_amd import skyr as s
+    s.lib()
+    return s
+
+
+def job(n, h, m, dt, prec, B, seed, tol=1e-3, steps=400):
+    return dict(n=n, h=h, m=m, dt=dt, tol=tol, steps=steps, precision=prec,
+                init={"kind": "random_product", "B": B, "seed": seed, "radius": 1.5, "prof_lambda": 1.0})
+
+
+MIX = [job(24, 0.25, 1.0, 0.025, "f64", 1, 11), job(32, 0.2, 0.0, 0.02, "f32", 2, 12),
+       job(28, 0.2, 1.0, 0.02, "f64", 3, 13), job(20, 0.3, 1.0, 0.03, "f32", 1, 14),
+       job(36, 0.2, 1.0, 0.02, "f32", 4, 15, steps=150), job(24, 0.25, 0.0, 0.025, "f64", 2, 16)]
+
+
+def _setup(skyr, d):
+    prec = skyr.F32_BULK if d["precision"] == "f32" else skyr.F64
+    lat = skyr.Lattice.cube(d["n"], d["h"])
+    phi = skyr.new_field(lat, prec, DEV)
+    spec, keep = skyr.spec_from_description(d["init"])
+    skyr.init_field(lat, prec, spec, phi)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    flow = skyr.Flow(d["dt"], d["tol"], d["steps"], 16, 0)
+    return lat, prec, phi, alt, vel, work, flow
+
+
+def _run_batch(skyr, jobs, sweeps=16):
+    bufs = [_setup(skyr, d) for d in jobs]
+    with skyr.Batch(8) as b:
+        slots = [b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
+                 for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs)]
+        states = {}
+        for _ in range(200):
+            b.run(sweeps)
+            for j, s in enumerate(slots):
+                st = b.poll(s)
+                states[j] = st
+            if all(st.converged or st.steps >= jobs[j]["steps"] for j, st in states.items()):
+                break
+        out = []
+        for j, s in enumerate(slots):
+            st = b.poll(s)
+            out.append((bufs[j][2].cpu().numpy().copy(), bufs[j][4].cpu().numpy().copy(), st.steps, st.arrests,
+                        st.converged, st.E_prev))
+    return out
+
+
+def test_batch_alone_equals_mix(skyr):
+    mix = _run_batch(skyr, MIX)
+    for j, d in enumerate(MIX):
+        alone = _run_batch(skyr, [d])[0]
+        got = mix[j]
+        assert got[2] == alone[2] and got[3] == alone[3] and got[4] == alone[4]
+        assert np.array_equal(got[0], alone[0]), f"field {j} differs alone vs mix"
+        assert got[5] == alone[5]
+
+
+def test_batch_equals_single_field_entry_point(skyr):
+    d = MIX[2]
+    res = _run_batch(skyr, [d])[0]
+    lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
+    assert st.steps == res[2] and st.arrests == res[3]
+    assert np.array_equal(phi.cpu().numpy(), res[0])
+
+
+def test_batch_join_while_running(skyr):
+    """A field added after others have run for a while ends bitwise equal to its
+    run alone (continuous batching)."""
+    late = MIX[1]
+    first = [MIX[0], MIX[3]]
+    bufs = [_setup(skyr, d) for d in first]
+    with skyr.Batch(4) as b:
+        for d, (lat, prec, phi, alt, vel, work, flow) in zip(first, bufs):
+            b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
+        b.run(24)
+        lat, prec, phi, alt, vel, work, flow = _setup(skyr, late)
+        s = b.add(lat, prec, skyr.Model(late["m"]), flow, phi, alt, vel, work)
+        for _ in range(100):
+            b.run(16)
+            st = b.poll(s)
+            if st.converged or st.steps >= late["steps"]:
+                break
+        st = b.poll(s)
+        got = phi.cpu().numpy().copy()
+    alone = _run_batch(skyr, [late])[0]
+    assert st.steps == alone[2] and np.array_equal(got, alone[0])
+
+
+def test_served_stream_results_equal_alone(skyr):
+    from paper_2604_25876_amd.serve import GpuBackend, Request, Server
+    jobs = MIX[:4]
+    be = GpuBackend(max_jobs=3)
+    srv = Server(be, max_jobs=3, hbm_budget=2 ** 30, sweeps_per_tick=16, keep_fields=True)
+    reqs = [Request(d, arrival=0.02 * i, rid=i) for i, d in enumerate(jobs)]
+    rep = srv.serve(reqs)
+    be.close()
+    assert rep["jobs"] == 4
+    assert rep["latency_p99_s"] >= rep["latency_p50_s"] > 0
+    for r in srv.done:
+        alone = _run_batch(skyr, [r.desc])[0]
+        assert r.state["steps"] == alone[2]
+        assert np.array_equal(r.result["field"].cpu().numpy(), alone[0]), r.rid
