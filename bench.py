@@ -32,7 +32,45 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"f32": 4 * 4 * 4, "f64": 4 * 4 * 8}
 
 
-def run_flow(skyr, torch, w, prec_name, steps, warmup):
+def kernel_source_hash() -> str:
+    """sha256 over the sources the sweep kernel is built from."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in ("sweep.hpp", "skyr.hip"):
+        with open(os.path.join(ROOT, "paper_2604_25876_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def recorded_traffic(prec_name, tile):
+    """HBM bytes per sweep launch from the committed counter summary, or None.
+
+    The summary holds `key: value` lines (FETCH_SIZE and WRITE_SIZE in KiB per
+    dispatch, the scale factors a plain copy of known size gives for each
+    counter, the tile and the kernel-source hash the counters were taken
+    with).  Counters taken on other kernel sources or another tile do not
+    describe this launch and give None."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic_random-b10-256.md")
+    try:
+        with open(path) as fh:
+            kv = dict(line.split(":", 1) for line in fh.read().splitlines()
+                      if ":" in line and not line.startswith(("#", "|", "`", " ")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    if kv.get(f"{prec_name}_tile") != f"{tile[0]}:{tile[1]}":
+        return None
+    try:
+        fetch = float(kv[f"{prec_name}_fetch_kib"]) * float(kv["fetch_scale"])
+        write = float(kv[f"{prec_name}_write_kib"]) * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return 1024.0 * (fetch + write)
+
+
+def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None):
     prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
     n, h = w["n"], w["h"]
     lat = skyr.Lattice.cube(n, h)
@@ -46,7 +84,10 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup):
     # tolerance 0: every call runs exactly its steps
     flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
     # tile shape for this lattice and precision: measured once, before the timed region
-    tile = skyr.autotune_cached(lat, prec, model, flow, phi, alt, vel, work)
+    if tile is None:
+        tile = skyr.autotune_cached(lat, prec, model, flow, phi, alt, vel, work)
+    else:
+        skyr.set_tile(lat, prec, *tile)
     st = skyr.anf_state()
     skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, warmup, work)
     torch.cuda.synchronize()
@@ -74,7 +115,8 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup):
         elapsed_s=elapsed, site_updates_per_s=done * interior / elapsed, ms_per_step=1e3 * elapsed / max(done, 1),
         sweep_kernel_avg_us=kernel_avg_s * 1e6, sweep_launches=sweep_n, bytes_per_launch=bytes_launch,
         achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"],
-        tile={"shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]})
+        tile={"variant": tile[0], "shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]},
+        traffic=recorded_traffic(prec_name, tile))
 
 
 def sweep_tiles(skyr, torch, w, prec_name, steps=20):
@@ -212,7 +254,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="instead of the flow, copy a 1 GiB device buffer 5 times (reference for the HBM "
                          "byte counters: 1 GiB read + 1 GiB written per copy)")
+    ap.add_argument("--tile-f32", default=None, metavar="V:X",
+                    help="use tile variant V with X-plane slabs for the FP32 flow instead of the autotuner")
+    ap.add_argument("--tile-f64", default=None, metavar="V:X", help="the same for the FP64 flow")
     args = ap.parse_args()
+    tiles = {p: (tuple(int(t) for t in v.split(":")) if v else None)
+             for p, v in (("f32", args.tile_f32), ("f64", args.tile_f64))}
     if args.copy_probe:
         import torch
         src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
@@ -238,12 +285,12 @@ def main():
             sweep_tiles(skyr, torch, W, p)
         return
     if args.only:
-        r = run_flow(skyr, torch, W, args.only, args.steps, args.warmup)
+        r = run_flow(skyr, torch, W, args.only, args.steps, args.warmup, tiles[args.only])
         print(json.dumps(r), flush=True)
         return
-    r32 = run_flow(skyr, torch, W, "f32", args.steps, args.warmup)
+    r32 = run_flow(skyr, torch, W, "f32", args.steps, args.warmup, tiles["f32"])
     print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
-    r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup)
+    r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup, tiles["f64"])
     print(f"# f64: {r64}", file=sys.stderr, flush=True)
     batch = serve = None
     if not args.no_batch:
@@ -275,12 +322,12 @@ def main():
                    "interior_sites": (W["n"] - 4) ** 3, "tile_f32": r32["tile"], "tile_f64": r64["tile"]},
         "f64_flow": {"value": r64["site_updates_per_s"], "ms_per_step": r64["ms_per_step"],
                      "sweep_kernel_avg_us": r64["sweep_kernel_avg_us"], "achieved_GBs": r64["achieved_GBs"],
-                     "arrests": r64["arrests"], "sweeps": r64["sweeps"]},
+                     "arrests": r64["arrests"], "sweeps": r64["sweeps"], "traffic": r64["traffic"]},
         "speedup_f32_over_f64": r32["site_updates_per_s"] / r64["site_updates_per_s"],
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": r32["traffic"],
                      "kernel": "sweep_kernel<float> (step mode)",
                      "kernel_avg_us": r32["sweep_kernel_avg_us"], "bytes_per_launch": r32["bytes_per_launch"]},
         "cpu_baseline": cpu,

@@ -264,10 +264,12 @@ SKYR_API skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk);
 
 /* Autotuner: time every compiled shape with slab lengths 16..256 on this
- * lattice (three flow sweeps each, phi read, phi_alt and vel written), keep
- * the fastest with skyr_set_tile and return it (outputs nullable; best_us is
- * the sweep time in microseconds).  phi is unchanged; phi_alt is scratch and
- * vel is zero on return.  Synchronises `stream`. */
+ * lattice (flow sweeps, phi read, phi_alt and vel written; a candidate's time
+ * is the median of five sweeps, and the four fastest are timed three more
+ * times, interleaved, keeping their best median), keep the fastest with
+ * skyr_set_tile and return it (outputs nullable; best_us is the sweep time in
+ * microseconds).  phi is unchanged; phi_alt is scratch and vel is zero on
+ * return.  Synchronises `stream`. */
 SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                                    const skyr_flow* flow, const void* phi, void* phi_alt, void* vel, void* work,
                                    void* stream, int32_t* variant, int32_t* xchunk, double* best_us);

@@ -850,47 +850,82 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     h.target = INT64_MAX;
     h.E_prev = INFINITY;
     SKYR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
-    hipEvent_t e0, e1;
-    SKYR_HIP(hipEventCreate(&e0));
-    SKYR_HIP(hipEventCreate(&e1));
+    // one event pair per timed sweep; the median of a candidate's sweeps is its time
+    constexpr int kReps = 5;
+    hipEvent_t ev[kReps + 1];
+    int made = 0;
     auto cleanup = [&]() {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     };
-    double best = INFINITY;
-    int bv = 0, bx = kDefaultChunk;
+    for (; made <= kReps; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) {
+            cleanup();
+            return fail(SKYR_E_DEVICE, "autotune: event creation failed");
+        }
+    struct Cand {
+        int v, xc;
+        double us;
+    };
+    std::vector<Cand> cands;
     for (int v = 0; v < shape_count(prec); ++v) {
         int prev_slabs = -1;
         for (int c = 0; c < (int)(sizeof kChunks / sizeof kChunks[0]); ++c) {
-            const int xc = kChunks[c];
-            const Launch L = plan_with(lat, prec, v, xc);
+            const Launch L = plan_with(lat, prec, v, kChunks[c]);
             if (L.slabs == prev_slabs) continue;  // same split as a shorter slab length
             prev_slabs = L.slabs;
-            SweepArgs a = make_args(lat, L, model->m, flow->dt);
-            a.phi0 = phi;
-            a.phi1 = phi_alt;
-            a.vel = vel;
-            a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
-            a.ctl = ctl;
-            hipError_t e = sweep(prec, MODE_STEP, L, a, s);
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = sweep(prec, MODE_STEP, L, a, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                cleanup();
-                return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-            }
-            const double us = 1e3 * ms / 3.0;
-            if (us < best) {
-                best = us;
-                bv = v;
-                bx = xc;
-            }
+            cands.push_back({v, kChunks[c], INFINITY});
         }
     }
+    auto time_one = [&](Cand& cd, int warm) -> hipError_t {
+        const Launch L = plan_with(lat, prec, cd.v, cd.xc);
+        SweepArgs a = make_args(lat, L, model->m, flow->dt);
+        a.phi0 = phi;
+        a.phi1 = phi_alt;
+        a.vel = vel;
+        a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+        a.ctl = ctl;
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < warm && e == hipSuccess; ++r) e = sweep(prec, MODE_STEP, L, a, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+            e = sweep(prec, MODE_STEP, L, a, s);
+            if (e == hipSuccess) e = hipEventRecord(ev[r + 1], s);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+        double t[kReps];
+        for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+            t[r] = 1e3 * ms;
+        }
+        if (e == hipSuccess) {
+            std::sort(t, t + kReps);
+            cd.us = std::min(cd.us, t[kReps / 2]);
+        }
+        return e;
+    };
+    // the first candidate also warms the device clocks up before anything is compared
+    hipError_t e = cands.empty() ? hipSuccess : time_one(cands[0], 24);
+    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) e = time_one(cands[i], 1);
+    // the closest candidates are timed again, interleaved, and keep their best median
+    std::vector<size_t> order(cands.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cands[x].us < cands[y].us; });
+    const size_t top = std::min<size_t>(4, order.size());
+    for (int round = 0; round < 3 && e == hipSuccess; ++round)
+        for (size_t i = 0; i < top && e == hipSuccess; ++i) e = time_one(cands[order[i]], 1);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    double best = INFINITY;
+    int bv = 0, bx = kDefaultChunk;
+    for (const Cand& cd : cands)
+        if (cd.us < best) {
+            best = cd.us;
+            bv = cd.v;
+            bx = cd.xc;
+        }
     cleanup();
     SKYR_HIP(fill(vel, 4 * sites(lat), prec, 0.0, s));
     SKYR_HIP(hipStreamSynchronize(s));
