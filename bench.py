@@ -134,8 +134,10 @@ def sweep_tiles(skyr, torch, w, prec_name, steps=20):
     model = skyr.Model(w["m"])
     flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
     rows = []
+    nx = n - 4
+    chunks = sorted({max(16, -(-nx // s)) for s in range(1, 13)}, reverse=True)
     for v, shape in enumerate(skyr.tile_variants(prec)):
-        for xc in (32, 64, 84, 128, 256):
+        for xc in chunks:
             skyr.set_tile(lat, prec, v, xc)
             phi.copy_(phi0)
             vel.zero_()

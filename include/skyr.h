@@ -263,7 +263,8 @@ SKYR_API skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant
 SKYR_API skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant, int32_t xchunk);
 SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk);
 
-/* Autotuner: time every compiled shape with slab lengths 16..256 on this
+/* Autotuner: time every compiled shape with the slab lengths that split the
+ * interior x-extent evenly into 1..24 slabs (at least 16 planes each) on this
  * lattice (flow sweeps, phi read, phi_alt and vel written; a candidate's time
  * is the median of five sweeps, and the four fastest are timed three more
  * times, interleaved, keeping their best median), keep the fastest with

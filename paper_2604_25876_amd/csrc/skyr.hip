@@ -47,20 +47,20 @@ struct Shape {
     int nw, lw, ry;
     int threads() const { return nw * 64; }
     int oy() const { return (64 / lw) * nw * ry - 4; }
-    int oz() const { return lw - 8; }
+    int oz() const { return lw - 4; }
 };
 
 #ifndef SKYR_SHAPES_F64
-#define SKYR_SHAPES_F64(X) X(8, 32, 1) X(4, 32, 2)
+#define SKYR_SHAPES_F64(X) X(8, 32, 1) X(8, 16, 1)
 #endif
 #ifndef SKYR_SHAPES_F32
-#define SKYR_SHAPES_F32(X) X(16, 64, 1) X(16, 32, 1) X(8, 64, 2)
+#define SKYR_SHAPES_F32(X) X(16, 32, 1) X(8, 32, 2) X(16, 64, 1)
 #endif
 #define SKYR_SHAPE_ENTRY(a, b, c) Shape{a, b, c},
 static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
 static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
-static const int kChunks[] = {16, 24, 32, 48, 64, 96, 128, 256};  // planes per slab
-constexpr int kMinChunk = 16;
+constexpr int kMinChunk = 16;  // shortest slab (planes)
+constexpr int kMaxSlabs = 24;  // the autotuner splits x into 1 .. kMaxSlabs equal slabs
 constexpr int kDefaultChunk = 128;
 
 static int shape_count(skyr_precision prec)
@@ -297,14 +297,11 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
     double s[5];
     reduce_partials(part, ctl->nblocks, s);
     if (threadIdx.x != 0) return;
-    const double E2 = ctl->h3 * s[0], E4 = ctl->h3 * s[1], E0 = ctl->h3 * s[2];
-    const double E = E2 + E4 + E0;
+    // the flow sweep sums the whole energy density in slot 0 (slots 1, 2 are zero)
+    const double E = ctl->h3 * s[0];
     const double r = sqrt(s[4]);
     ctl->sweeps += 1;
     ctl->E = E;
-    ctl->E2 = E2;
-    ctl->E4 = E4;
-    ctl->E0 = E0;
     ctl->max_force = r;
     if (!isfinite(E) || !isfinite(r)) {
         ctl->done = 1;
@@ -867,13 +864,17 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
         double us;
     };
     std::vector<Cand> cands;
+    // slab lengths: the even splits of the interior x-extent into s = 1, 2, ... slabs
+    // (ceil(nx / s) planes, at least kMinChunk), so that the block count is a multiple
+    // of the tile count that can be matched to the number of compute units
+    const int nx = lat->n[0] - 4;
     for (int v = 0; v < shape_count(prec); ++v) {
-        int prev_slabs = -1;
-        for (int c = 0; c < (int)(sizeof kChunks / sizeof kChunks[0]); ++c) {
-            const Launch L = plan_with(lat, prec, v, kChunks[c]);
-            if (L.slabs == prev_slabs) continue;  // same split as a shorter slab length
-            prev_slabs = L.slabs;
-            cands.push_back({v, kChunks[c], INFINITY});
+        int prev = -1;
+        for (int sl = 1; sl <= kMaxSlabs; ++sl) {
+            const int xc = std::max(kMinChunk, (nx + sl - 1) / sl);
+            if (xc == prev) continue;
+            prev = xc;
+            cands.push_back({v, xc, INFINITY});
         }
     }
     auto time_one = [&](Cand& cd, int warm) -> hipError_t {

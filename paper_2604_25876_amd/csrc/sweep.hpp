@@ -7,14 +7,14 @@
 // plus FP64 per-block partial sums of E2, E4, E0, B and the largest |F|^2.
 //
 // Work decomposition (2.5D march):
-//   * a thread block owns an output tile of (PY-4) rows (y) x (LW-8) lanes (z)
+//   * a thread block owns an output tile of (PY-4) rows (y) x (LW-4) columns (z)
 //     and a chunk of planes [xb, xe) along x, and marches through x;
-//   * every thread owns RY "flux positions" (rows r_k, lane zl); the flux
-//     region is PY x LW and overlaps neighbouring tiles by two rows/lanes;
+//   * every thread owns RY "flux positions" (rows r_k, column zl); the flux
+//     region is PY x LW and overlaps neighbouring tiles by two rows/columns;
 //   * x-neighbours live in registers: a ring of five phi planes per position
 //     and a ring of five gradient accumulators (planes j-2..j+2);
-//   * y-neighbours go through LDS (one phi plane with a 2-row halo and one plane
-//     of the y-flux), z-neighbours are exchanged across lanes (ds_bpermute);
+//   * y- and z-neighbours go through LDS: one phi plane with a two-site halo on
+//     all four sides, and one plane each of the y- and z-flux;
 //   * the x-flux of plane j is pushed into the accumulators of planes j+-1, j+-2;
 //     output plane j-2 is complete after plane j and is written at once.
 // Energy, charge and force sums are accumulated in double.
@@ -45,7 +45,8 @@ struct Ctl {
     int32_t renorm64_every;
     int32_t nblocks;      // number of partial-sum blocks of the sweep
     double E_prev;
-    double E, E2, E4, E0;
+    double E;
+    double unused_[3];
     double max_force;
     double tol;
     double h3;
@@ -82,24 +83,21 @@ template <typename T> struct Coef {
     static constexpr T d0 = T(-5.0 / 2.0);
 };
 
-__device__ __forceinline__ float lane_shift(float v, int lane, int d)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + d) & 63) << 2, __float_as_int(v)));
-}
-
-__device__ __forceinline__ double lane_shift(double v, int lane, int d)
-{
-    const int addr = ((lane + d) & 63) << 2;
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 __device__ __forceinline__ float rnorm(float s) { return rsqrtf(s); }
 __device__ __forceinline__ double rnorm(double s) { return 1.0 / sqrt(s); }
+
+// element access by a 32-bit byte offset from a uniform base: the offset stays in one
+// VGPR and the base in SGPRs (no 64-bit address arithmetic per access)
+template <typename T> __device__ __forceinline__ T ldb(const T* base, unsigned off)
+{
+    return *(const T*)((const char*)base + off);
+}
+template <typename T> __device__ __forceinline__ void stb(T* base, unsigned off, T v)
+{
+    *(T*)((char*)base + off) = v;
+}
 
 template <typename T> __device__ __forceinline__ T dot4(const T* a, const T* b)
 {
@@ -130,9 +128,13 @@ template <typename T, int NW, int LW, int RY> struct Tile {
     static constexpr int R0 = NW * RPW;     // rows per row group
     static constexpr int PY = R0 * RY;      // flux rows per tile
     static constexpr int OY = PY - 4;       // output rows per tile
-    static constexpr int OZ = LW - 8;       // output lanes per tile
+    static constexpr int OZ = LW - 4;       // output columns per tile
     static constexpr int THREADS = NW * 64;
-    static_assert(THREADS >= 4 * LW, "halo rows are loaded by the first 4*LW threads");
+    // phi halo of a plane: rows 0, 1, PY+2, PY+3 over all LW+4 columns, then
+    // columns 0, 1, LW+2, LW+3 of rows 2 .. PY+1; one site per loading thread
+    static constexpr int NH_ROWS = 4 * (LW + 4);
+    static constexpr int NH = NH_ROWS + 4 * PY;
+    static_assert(THREADS >= NH, "every halo site of a plane has its own loading thread");
 };
 
 template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
@@ -146,9 +148,9 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     static constexpr bool kHaloFast = sizeof(T) == 8;
 
     struct Smem {
-        T phi[4][PY + 4][LW];  // phi of the current plane, rows y0-4 .. y0+PY-1
-        T qy[4][PY][LW];       // y-flux of the current plane, rows y0-2 .. y0+PY-3
-        T qz[4][PY][LW];       // z-flux of the current plane
+        T phi[2][4][PY + 4][LW + 4];  // phi of two planes, rows y0-4 .. y0+PY-1, columns z0-4 .. z0+LW-1
+        T qy[2][4][PY][LW];           // y-flux of two planes, flux rows and columns
+        T qz[2][4][PY][LW];           // z-flux of two planes
         double red[NW][NPART];
     };
 
@@ -158,16 +160,17 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     T* pout[4];
     T* vel[4];
     T* gout[4];
-    int n0, n1, n2, plane;
+    int n0, n1, n2;
+    unsigned plane_b;  // bytes per x-plane of one component
     int xb, xe;
-    int lane, zl, rg, z, hrow, hz;
-    unsigned hoff;
-    bool halo_loader, lane_flux, redo, renorm64, projected, baryon, has_grad, tile_near;
+    int zl, rg, z, hrow, hcol;
+    unsigned hoff;  // byte offset of this thread's halo site within a plane
+    bool halo_loader, redo, renorm64, projected, baryon, has_grad;
     bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
     int yk[RY];
-    unsigned offk[RY];
-    bool row_out[RY], yz_in[RY], yz_near[RY];
-    T c1h, c2h, d1h, d2h, ih2, dt, m2;  // stencil weights with 1/h, 1/h^2 folded in
+    unsigned offk[RY];  // byte offsets of the flux positions within a plane
+    bool row_out[RY], yz_in[RY], y_near[RY], z_near;
+    T c1h, c2h, d1h, d2h, hd1h, hd2h, dt, m2;  // stencil weights with 1/h, 1/h^2 (and 1/2) folded in
 
     // registers carried along the march
     T ring[5][4][RY];  // phi at planes j-2 .. j+2 (slot = plane mod 5 relative to the start)
@@ -175,37 +178,42 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     T nxt[4][RY];      // prefetched phi(j+3)
     T hnxt[4];         // prefetched halo rows of phi(j+1)
 
-    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb = 0.0;
+    // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
+    // flow step keeps the total energy density in pe2 and leaves the others at zero
+    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0;
     T pf2 = T(0);
 
     __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
 
     __device__ __forceinline__ void load_plane(int x, T (&dst)[4][RY]) const
     {
-        const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * (unsigned)plane;
+        const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * plane_b;
 #pragma unroll
         for (int A = 0; A < 4; ++A)
 #pragma unroll
-            for (int k = 0; k < RY; ++k) dst[A][k] = pin[A][base + offk[k]];
+            for (int k = 0; k < RY; ++k) dst[A][k] = ldb(pin[A], base + offk[k]);
     }
 
     __device__ __forceinline__ void load_halo(int x, T (&dst)[4]) const
     {
         if (halo_loader) {
-            const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * (unsigned)plane;
+            const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * plane_b;
 #pragma unroll
-            for (int A = 0; A < 4; ++A) dst[A] = pin[A][base + hoff];
+            for (int A = 0; A < 4; ++A) dst[A] = ldb(pin[A], base + hoff);
         }
     }
 
-    // one plane of the march: flux at plane j, output at plane j-2.  Ring and
-    // accumulator slots 0..4 hold planes j-2 .. j+2 and are shifted by one
-    // plane at the end of the step.
-    __device__ __forceinline__ void step(int j)
+    // one plane of the march, between two block barriers: flux at plane j, y/z-divergence
+    // of plane j-1, output of plane j-2, and staging of phi(j+1).  LDS buffers alternate
+    // by plane parity: phi(j) and the flux of plane j live in buffer pb, phi(j+1) and the
+    // flux of plane j-1 in buffer pb ^ 1, so one barrier per plane suffices.  Ring and
+    // accumulator slots 0..4 hold planes j-2 .. j+2 and are shifted at the end of the step.
+    __device__ __forceinline__ void step(int j, int pb)
     {
         constexpr int S_M2 = 0, S_M1 = 1, S_0 = 2, S_P1 = 3, S_P2 = 4;
+        const int qb = pb ^ 1;
 
-        // commit the prefetched plane j+2 and the halo of plane j; prefetch j+3 and the halo of j+1
+        // commit the prefetched plane j+2 and the halo of plane j+1; prefetch j+3 and the halo of j+2
         T hcur[4];
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
@@ -214,65 +222,26 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
             hcur[A] = hnxt[A];
         }
         load_plane(j + 3, nxt);
-        load_halo(j + 1, hnxt);
+        load_halo(j + 2, hnxt);
         // velocity of the output plane j-2, used at the end of this step
         T vcur[4][RY];
         if constexpr (MODE == MODE_STEP) {
-            const unsigned vb = (unsigned)clampi(j - 2, 0, n0 - 1) * (unsigned)plane;
+            const unsigned vb = (unsigned)clampi(j - 2, 0, n0 - 1) * plane_b;
 #pragma unroll
             for (int A = 0; A < 4; ++A)
 #pragma unroll
-                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : vel[A][vb + offk[k]];
+                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : ldb((const T*)vel[A], vb + offk[k]);
         }
-
-        // stage phi(j) for the y-stencils
-#pragma unroll
-        for (int A = 0; A < 4; ++A) {
-#pragma unroll
-            for (int k = 0; k < RY; ++k) sm.phi[A][rg + k * R0 + 2][zl] = ring[S_0][A][k];
-            if (halo_loader) sm.phi[A][hrow][hz] = hcur[A];
-        }
-        __syncthreads();
 
         const bool j_in = (j >= 2) && (j <= n0 - 3);
         const bool j_out = (j >= xb) && (j < xe);
         const bool j_near = (j <= 3) || (j >= n0 - 4);
-
-        if (kHaloFast && halo_wave) {
-            // y-halo rows: only the y-flux of this plane is needed (by the rows next to them)
-#pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                const int r = rg + k * R0 + 2;
-                T ax[4], ay[4], az[4];
-#pragma unroll
-                for (int A = 0; A < 4; ++A) {
-                    const T c = ring[S_0][A][k];
-                    ax[A] = c1h * (ring[S_P1][A][k] - ring[S_M1][A][k]) + c2h * (ring[S_P2][A][k] - ring[S_M2][A][k]);
-                    ay[A] = c1h * (sm.phi[A][r + 1][zl] - sm.phi[A][r - 1][zl]) +
-                            c2h * (sm.phi[A][r + 2][zl] - sm.phi[A][r - 2][zl]);
-                    az[A] = c1h * (lane_shift(c, lane, 1) - lane_shift(c, lane, -1)) +
-                            c2h * (lane_shift(c, lane, 2) - lane_shift(c, lane, -2));
-                }
-                const T gxx = dot4(ax, ax), gzz = dot4(az, az);
-                const T gxy = dot4(ax, ay), gyz = dot4(ay, az);
-                const bool valid = lane_flux && yz_in[k] && j_in;
-#pragma unroll
-                for (int A = 0; A < 4; ++A)
-                    sm.qy[A][r - 2][zl] = valid ? (gxx + gzz) * ay[A] - gxy * ax[A] - gyz * az[A] : T(0);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int A = 0; A < 4; ++A)
-#pragma unroll
-                for (int k = 0; k < RY; ++k)
-#pragma unroll
-                    for (int sl = 0; sl < 4; ++sl) ring[sl][A][k] = ring[sl + 1][A][k];
-            return;
-        }
+        const bool full = !(kHaloFast && halo_wave);  // uniform over the wave
 
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
-            const int r = rg + k * R0 + 2;  // LDS row of this position in sm.phi
+            const int r = rg + k * R0 + 2;  // LDS row and column of this position in sm.phi
+            const int cz = zl + 2;
             T c[4], ax[4], ay[4], az[4];
             T cl = T(0);  // phi . Lap phi
 #pragma unroll
@@ -280,64 +249,100 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                 c[A] = ring[S_0][A][k];
                 const T xm2 = ring[S_M2][A][k], xm1 = ring[S_M1][A][k];
                 const T xp1 = ring[S_P1][A][k], xp2 = ring[S_P2][A][k];
-                const T ym2 = sm.phi[A][r - 2][zl], ym1 = sm.phi[A][r - 1][zl];
-                const T yp1 = sm.phi[A][r + 1][zl], yp2 = sm.phi[A][r + 2][zl];
-                const T zm2 = lane_shift(c[A], lane, -2), zm1 = lane_shift(c[A], lane, -1);
-                const T zp1 = lane_shift(c[A], lane, 1), zp2 = lane_shift(c[A], lane, 2);
+                const T ym2 = sm.phi[pb][A][r - 2][cz], ym1 = sm.phi[pb][A][r - 1][cz];
+                const T yp1 = sm.phi[pb][A][r + 1][cz], yp2 = sm.phi[pb][A][r + 2][cz];
+                const T zm2 = sm.phi[pb][A][r][cz - 2], zm1 = sm.phi[pb][A][r][cz - 1];
+                const T zp1 = sm.phi[pb][A][r][cz + 1], zp2 = sm.phi[pb][A][r][cz + 2];
                 ax[A] = c1h * (xp1 - xm1) + c2h * (xp2 - xm2);
                 ay[A] = c1h * (yp1 - ym1) + c2h * (yp2 - ym2);
                 az[A] = c1h * (zp1 - zm1) + c2h * (zp2 - zm2);
-                // the five-point weights sum to zero, so the Laplacian is a weighted sum of
-                // differences from the centre: no cancellation of O(1) terms in single precision
-                const T lap = d1h * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
-                                     ((zp1 - c[A]) + (zm1 - c[A]))) +
-                              d2h * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
-                                     ((zp2 - c[A]) + (zm2 - c[A])));
-                cl += c[A] * lap;
-                // E2 part of the gradient: -1/2 (Lap phi + Lap(1_I phi)); neighbours outside I
-                // carry weight zero in the second Laplacian
-                T corr = T(0);
-                if ((j_near || tile_near) && (j_near || yz_near[k])) {
-                    const int y = yk[k];
-                    const bool ox1 = (j + 1 > n0 - 3), ox_1 = (j - 1 < 2), ox2 = (j + 2 > n0 - 3), ox_2 = (j - 2 < 2);
-                    const bool oy1 = (y + 1 > n1 - 3), oy_1 = (y - 1 < 2), oy2 = (y + 2 > n1 - 3), oy_2 = (y - 2 < 2);
-                    const bool oz1 = (z + 1 > n2 - 3), oz_1 = (z - 1 < 2), oz2 = (z + 2 > n2 - 3), oz_2 = (z - 2 < 2);
-                    corr = C::d1 * ((ox1 ? xp1 : T(0)) + (ox_1 ? xm1 : T(0)) + (oy1 ? yp1 : T(0)) +
-                                    (oy_1 ? ym1 : T(0)) + (oz1 ? zp1 : T(0)) + (oz_1 ? zm1 : T(0))) +
-                           C::d2 * ((ox2 ? xp2 : T(0)) + (ox_2 ? xm2 : T(0)) + (oy2 ? yp2 : T(0)) +
-                                    (oy_2 ? ym2 : T(0)) + (oz2 ? zp2 : T(0)) + (oz_2 ? zm2 : T(0)));
+                if (full && j_out) {
+                    // the five-point weights sum to zero, so the Laplacian is a weighted sum of
+                    // differences from the centre: no cancellation of O(1) terms in single precision
+                    const T lap = d1h * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
+                                         ((zp1 - c[A]) + (zm1 - c[A]))) +
+                                  d2h * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
+                                         ((zp2 - c[A]) + (zm2 - c[A])));
+                    cl += c[A] * lap;
+                    // E2 part of the gradient: -1/2 (Lap phi + Lap(1_I phi)) = -Lap phi + 1/2 (the
+                    // terms of Lap phi whose neighbour lies outside I); only sites within two of a
+                    // face of I have such terms, one direction at a time
+                    T o1 = T(0), o2 = T(0);  // sums of the outside first / second neighbours
+                    if (j_near) {            // uniform over the block
+                        if (j + 1 > n0 - 3) o1 += xp1;
+                        if (j - 1 < 2) o1 += xm1;
+                        if (j + 2 > n0 - 3) o2 += xp2;
+                        if (j - 2 < 2) o2 += xm2;
+                    }
+                    if (y_near[k]) {
+                        const int y = yk[k];
+                        o1 += ((y + 1 > n1 - 3) ? yp1 : T(0)) + ((y - 1 < 2) ? ym1 : T(0));
+                        o2 += ((y + 2 > n1 - 3) ? yp2 : T(0)) + ((y - 2 < 2) ? ym2 : T(0));
+                    }
+                    if (z_near) {
+                        o1 += ((z + 1 > n2 - 3) ? zp1 : T(0)) + ((z - 1 < 2) ? zm1 : T(0));
+                        o2 += ((z + 2 > n2 - 3) ? zp2 : T(0)) + ((z - 2 < 2) ? zm2 : T(0));
+                    }
+                    acc[S_0][A][k] += (hd1h * o1 + hd2h * o2) - lap;
                 }
-                acc[S_0][A][k] += T(0.5) * corr * ih2 - lap;
             }
 
             const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
             const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
-            const bool valid = lane_flux && yz_in[k] && j_in;
+            const bool valid = yz_in[k] && j_in;
             // the flux vanishes outside I: zero the Gram entries it is built from
             const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
             const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
 #pragma unroll
-            for (int A = 0; A < 4; ++A) {
-                const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
-                sm.qy[A][r - 2][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
-                sm.qz[A][r - 2][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
-                // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
-                acc[S_M1][A][k] -= c1h * qx;
-                acc[S_P1][A][k] += c1h * qx;
-                acc[S_M2][A][k] -= c2h * qx;
-                acc[S_P2][A][k] += c2h * qx;
+            for (int A = 0; A < 4; ++A) sm.qy[pb][A][r - 2][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
+            if (full) {
+#pragma unroll
+                for (int A = 0; A < 4; ++A) {
+                    const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
+                    sm.qz[pb][A][r - 2][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
+                    // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
+                    acc[S_M1][A][k] -= c1h * qx;
+                    acc[S_P1][A][k] += c1h * qx;
+                    acc[S_M2][A][k] -= c2h * qx;
+                    acc[S_P2][A][k] += c2h * qx;
+                }
+                if (row_out[k] && j_out) {
+                    const T e2 = T(-0.5) * cl;
+                    const T e4 = T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
+                    const T e0 = m2 * (T(1) - c[0]);
+                    if constexpr (MODE == MODE_STEP) {
+                        pe2 += (double)(e2 + e4 + e0);  // the flow needs the total energy only
+                    } else {
+                        pe2 += (double)e2;
+                        pe4 += (double)e4;
+                        pe0 += (double)e0;
+                        if (baryon) pb_sum += (double)det4(c, ax, ay, az);
+                    }
+                }
             }
-            if (row_out[k] && j_out) {
-                pe2 += (double)(T(-0.5) * cl);
-                pe4 += (double)(T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz));
-                pe0 += (double)(m2 * (T(1) - c[0]));
-                if (baryon) pb += (double)det4(c, ax, ay, az);
+        }
+
+        // y- and z-divergence of the flux of plane j-1 (written before the last barrier)
+        if (full && j - 1 >= xb && j - 1 < xe) {
+#pragma unroll
+            for (int k = 0; k < RY; ++k) {
+                const int r = rg + k * R0;
+                const int rm2 = max(r - 2, 0), rm1 = max(r - 1, 0), rp1 = min(r + 1, PY - 1), rp2 = min(r + 2, PY - 1);
+                const int zm2 = max(zl - 2, 0), zm1 = max(zl - 1, 0), zp1 = min(zl + 1, LW - 1), zp2 = min(zl + 2, LW - 1);
+#pragma unroll
+                for (int A = 0; A < 4; ++A) {
+                    const T dy = c1h * (sm.qy[qb][A][rp1][zl] - sm.qy[qb][A][rm1][zl]) +
+                                 c2h * (sm.qy[qb][A][rp2][zl] - sm.qy[qb][A][rm2][zl]);
+                    const T dz = c1h * (sm.qz[qb][A][r][zp1] - sm.qz[qb][A][r][zm1]) +
+                                 c2h * (sm.qz[qb][A][r][zp2] - sm.qz[qb][A][r][zm2]);
+                    acc[S_M1][A][k] -= dy + dz;
+                }
             }
         }
 
         // output plane j-2 is complete
-        if (j - 2 >= xb && j - 2 < xe) {
-            const unsigned base = (unsigned)(j - 2) * (unsigned)plane;
+        if (full && j - 2 >= xb && j - 2 < xe) {
+            const unsigned base = (unsigned)(j - 2) * plane_b;
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
                 if (row_out[k]) {
@@ -372,33 +377,27 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                         }
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
-                            pout[A][base + offk[k]] = pn[A];
-                            vel[A][base + offk[k]] = v[A];
+                            stb(pout[A], base + offk[k], pn[A]);
+                            stb(vel[A], base + offk[k], v[A]);
                         }
                     } else {
                         if (has_grad) {
 #pragma unroll
-                            for (int A = 0; A < 4; ++A) gout[A][base + offk[k]] = projected ? -f[A] : g[A];
+                            for (int A = 0; A < 4; ++A) stb(gout[A], base + offk[k], projected ? -f[A] : g[A]);
                         }
                     }
                 }
             }
         }
-        __syncthreads();
 
-        // y- and z-divergence of the flux into g(j)
+        // stage phi(j+1) and its halo for the next plane
 #pragma unroll
-        for (int k = 0; k < RY; ++k) {
-            const int r = rg + k * R0;
-            const int rm2 = max(r - 2, 0), rm1 = max(r - 1, 0), rp1 = min(r + 1, PY - 1), rp2 = min(r + 2, PY - 1);
-            const int zm2 = max(zl - 2, 0), zm1 = max(zl - 1, 0), zp1 = min(zl + 1, LW - 1), zp2 = min(zl + 2, LW - 1);
+        for (int A = 0; A < 4; ++A) {
 #pragma unroll
-            for (int A = 0; A < 4; ++A) {
-                const T dy = c1h * (sm.qy[A][rp1][zl] - sm.qy[A][rm1][zl]) + c2h * (sm.qy[A][rp2][zl] - sm.qy[A][rm2][zl]);
-                const T dz = c1h * (sm.qz[A][r][zp1] - sm.qz[A][r][zm1]) + c2h * (sm.qz[A][r][zp2] - sm.qz[A][r][zm2]);
-                acc[S_0][A][k] -= dy + dz;
-            }
+            for (int k = 0; k < RY; ++k) sm.phi[qb][A][rg + k * R0 + 2][zl + 2] = ring[S_P1][A][k];
+            if (halo_loader) sm.phi[qb][A][hrow][hcol] = hcur[A];
         }
+        __syncthreads();
 
         // advance the rings by one plane; the freed accumulator starts plane j+3
 #pragma unroll
@@ -442,8 +441,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     sw.n1 = a.n1;
     sw.n2 = a.n2;
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
-    sw.plane = n1 * n2;
-    const long long N3 = (long long)n0 * sw.plane;
+    sw.plane_b = (unsigned)(n1 * n2) * (unsigned)sizeof(T);
+    const long long N3 = (long long)n0 * n1 * n2;
     {
         const T* pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
         T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
@@ -463,19 +462,27 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     sw.c2h = T(Coef<double>::c2 / a.h);
     sw.d1h = T(Coef<double>::d1 / (a.h * a.h));
     sw.d2h = T(Coef<double>::d2 / (a.h * a.h));
-    sw.ih2 = T(1.0 / (a.h * a.h));
+    sw.hd1h = T(0.5 * Coef<double>::d1 / (a.h * a.h));
+    sw.hd2h = T(0.5 * Coef<double>::d2 / (a.h * a.h));
     sw.dt = T(a.dt);
     sw.m2 = T(a.m * a.m);
 
     const int tid = threadIdx.x;
-    sw.lane = tid & 63;
+    const int lane = tid & 63;
     const int wave = tid >> 6;
-    sw.zl = sw.lane % LW;
-    sw.rg = wave * TL::RPW + sw.lane / LW;
-    sw.lane_flux = (sw.zl >= 2) && (sw.zl < LW - 2);
-    sw.halo_loader = tid < 4 * LW;
-    sw.hrow = sw.halo_loader ? (tid / LW < 2 ? tid / LW : PY + tid / LW) : 0;
-    sw.hz = tid % LW;
+    sw.zl = lane % LW;
+    sw.rg = wave * TL::RPW + lane / LW;
+    sw.halo_loader = tid < TL::NH;
+    if (tid < TL::NH_ROWS) {
+        const int q = tid / (LW + 4);
+        sw.hrow = q < 2 ? q : PY + q;
+        sw.hcol = tid % (LW + 4);
+    } else {
+        const int u = min(tid, TL::NH - 1) - TL::NH_ROWS;  // 0 .. 4 PY - 1
+        const int q = u & 3;
+        sw.hrow = 2 + (u >> 2);
+        sw.hcol = q < 2 ? q : LW + q;
+    }
     {
         // rows of this wave: w*RPW + (0..RPW-1) + k*R0; all of them in {0, 1, PY-2, PY-1}?
         const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -507,25 +514,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
         const int y0 = 2 + ty * TL::OY;
         sw.xb = 2 + x0;
         sw.xe = 2 + x1;
-        sw.z = z0 - 4 + sw.zl;
+        sw.z = z0 - 2 + sw.zl;
         const int zc = clampi(sw.z, 0, n2 - 1);
-        const bool lane_out = (sw.zl >= 4) && (sw.zl < LW - 4) && (sw.z <= n2 - 3);
+        const bool lane_out = (sw.zl >= 2) && (sw.zl < LW - 2) && (sw.z <= n2 - 3);
         const bool z_in = (sw.z >= 2) && (sw.z <= n2 - 3);
-        const bool z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
+        sw.z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
 #pragma unroll
         for (int k = 0; k < RY; ++k) {
             const int r = sw.rg + k * R0;
             const int y = y0 - 2 + r;
             sw.yk[k] = y;
-            sw.offk[k] = (unsigned)(clampi(y, 0, n1 - 1) * n2 + zc);
+            sw.offk[k] = (unsigned)(clampi(y, 0, n1 - 1) * n2 + zc) * (unsigned)sizeof(T);
             sw.row_out[k] = (r >= 2) && (r < PY - 2) && (y <= n1 - 3) && lane_out;
             sw.yz_in[k] = z_in && (y >= 2) && (y <= n1 - 3);
-            sw.yz_near[k] = z_near || (y <= 3) || (y >= n1 - 4);
+            sw.y_near[k] = (y <= 3) || (y >= n1 - 4);
         }
-        // halo rows of the phi plane: LDS rows 0, 1, PY+2, PY+3
-        sw.hoff = (unsigned)(clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hz, 0, n2 - 1));
-        // does any output site of this tile lie within two sites of a y or z face of I
-        sw.tile_near = (y0 <= 3) || (y0 + TL::OY - 1 >= n1 - 4) || (z0 <= 3) || (z0 + TL::OZ - 1 >= n2 - 4);
+        // halo site of the phi plane loaded by this thread
+        sw.hoff = (unsigned)(clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hcol, 0, n2 - 1)) *
+                  (unsigned)sizeof(T);
 
 #pragma unroll
         for (int s = 0; s < 5; ++s)
@@ -542,12 +548,25 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
         sw.load_plane(jstart, sw.ring[2]);
         sw.load_plane(jstart + 1, sw.ring[3]);
         sw.load_plane(jstart + 2, sw.nxt);
-        sw.load_halo(jstart, sw.hnxt);
-        for (int st = 0; st < nst; ++st) sw.step(jstart + st);
+        // phi(jstart) and its halo go to LDS buffer 0 before the first plane; the halo of
+        // jstart+1 is prefetched
+        {
+            T h0[4];
+            sw.load_halo(jstart, h0);
+            sw.load_halo(jstart + 1, sw.hnxt);
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+#pragma unroll
+                for (int k = 0; k < RY; ++k) smem.phi[0][A][sw.rg + k * R0 + 2][sw.zl + 2] = sw.ring[2][A][k];
+                if (sw.halo_loader) smem.phi[0][A][sw.hrow][sw.hcol] = h0[A];
+            }
+        }
+        __syncthreads();
+        for (int st = 0; st < nst; ++st) sw.step(jstart + st, st & 1);
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[5] = {sw.pe2, sw.pe4, sw.pe0, sw.pb, (double)sw.pf2};
+    double vals[5] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         double v = vals[i];
@@ -558,7 +577,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
         }
         vals[i] = v;
     }
-    if (sw.lane == 0) {
+    if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < 5; ++i) smem.red[wave][i] = vals[i];
     }
