@@ -71,6 +71,9 @@ def recorded_traffic(prec_name, tile):
 
 
 def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None):
+    """Time `steps` accepted flow steps of the workload after `warmup`.  The
+    FP32-bulk flow uses the power arrest rule (its recommended setting), the
+    FP64 flow the paper's energy rule."""
     prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
     n, h = w["n"], w["h"]
     lat = skyr.Lattice.cube(n, h)
@@ -82,7 +85,8 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None):
     work = skyr.new_workspace(lat, prec, dev)
     model = skyr.Model(w["m"])
     # tolerance 0: every call runs exactly its steps
-    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, 0)
+    rule = "power" if prec_name == "f32" else "energy"
+    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, skyr.arrest_rule(rule))
     # tile shape for this lattice and precision: measured once, before the timed region
     if tile is None:
         tile = skyr.autotune_cached(lat, prec, model, flow, phi, alt, vel, work)
@@ -115,7 +119,7 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None):
         elapsed_s=elapsed, site_updates_per_s=done * interior / elapsed, ms_per_step=1e3 * elapsed / max(done, 1),
         sweep_kernel_avg_us=kernel_avg_s * 1e6, sweep_launches=sweep_n, bytes_per_launch=bytes_launch,
         achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"],
-        tile={"variant": tile[0], "shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]},
+        arrest=rule, tile={"variant": tile[0], "shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]},
         traffic=recorded_traffic(prec_name, tile))
 
 
@@ -163,7 +167,7 @@ def _job_buffers(skyr, torch, d):
     skyr.init_field(lat, prec, spec, phi)
     alt, vel = skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
     work = skyr.new_workspace(lat, prec, dev)
-    flow = skyr.Flow(d["dt"], 0.0, 10 ** 12, 16, 0)
+    flow = skyr.Flow(d["dt"], 0.0, 10 ** 12, 16, skyr.arrest_rule(d.get("arrest", "energy")))
     return lat, prec, phi, alt, vel, work, flow
 
 
@@ -198,9 +202,24 @@ def batch_throughput(skyr, torch, jobs, sweeps=64):
             "speedup": (upd_b / t_batch) / (steps_s / t_seq)}
 
 
-def served_stream(skyr, torch, count=24, cap=1000, rate=40.0):
+# steps to convergence of a typical request of the served stream (median of a
+# measured sample of its first jobs), used only to set the arrival rate
+SERVE_STEPS_EST = 9000
+
+
+def served_stream(skyr, torch, count=24, cap=20000, rate=None, throughput=None):
+    """The served workload (Poisson arrivals, jobs of mixed size and precision).
+    The arrival rate is 1.2 x the estimated service capacity: batched
+    site-updates/s over the mean work of a request (SERVE_STEPS_EST steps of
+    its interior sites), unless given."""
     from paper_2604_25876_amd.serve import GpuBackend, Request, Server
     from skyr_inputs import served_stream as stream
+    probe = stream(5, count, 1.0)
+    mean_sites = sum((d["n"] - 4) ** 3 for d in probe) / len(probe)
+    capacity = None
+    if rate is None:
+        capacity = (throughput or 2e10) / (mean_sites * SERVE_STEPS_EST)
+        rate = 1.2 * capacity
     reqs = []
     for i, d in enumerate(stream(5, count, rate)):
         d = dict(d, steps=cap)
@@ -210,7 +229,9 @@ def served_stream(skyr, torch, count=24, cap=1000, rate=40.0):
     srv = Server(be, max_jobs=32, hbm_budget=int(0.8 * free), sweeps_per_tick=32)
     rep = srv.serve(reqs)
     be.close()
-    rep.update({"rate_per_s": rate, "step_cap": cap, "tol": 1e-4})
+    rep.update({"rate_per_s": rate, "capacity_est_jobs_per_s": capacity, "step_cap": cap,
+                "tol": "1e-4 (FP64, energy arrest rule); max(1e-4, 2 x FP32 force floor) (FP32-bulk, power rule)",
+                "at_cap_fraction": rep["capped"] / max(rep["jobs"], 1)})
     return rep
 
 
@@ -299,7 +320,7 @@ def main():
         from skyr_inputs import batch_jobs
         batch = batch_throughput(skyr, torch, batch_jobs(4, 64))
         print(f"# batch: {batch}", file=sys.stderr, flush=True)
-        serve = served_stream(skyr, torch, count=args.serve_jobs)
+        serve = served_stream(skyr, torch, count=args.serve_jobs, throughput=batch["batched_site_updates_per_s"])
         print(f"# serve: {serve}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -320,7 +341,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": W["name"], "n": W["n"], "h": W["h"], "m": W["m"], "dt": W["dt"],
-                   "init": W["init"], "precision": "f32-bulk (f64 sums, arrest test, renormalisation every 16)",
+                   "init": W["init"], "precision": "f32-bulk (f64 sums and arrest test, renormalisation every 16)",
+                   "arrest_f32": r32["arrest"], "arrest_f64": r64["arrest"],
                    "interior_sites": (W["n"] - 4) ** 3, "tile_f32": r32["tile"], "tile_f64": r64["tile"]},
         "f64_flow": {"value": r64["site_updates_per_s"], "ms_per_step": r64["ms_per_step"],
                      "sweep_kernel_avg_us": r64["sweep_kernel_avg_us"], "achieved_GBs": r64["achieved_GBs"],

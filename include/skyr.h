@@ -75,18 +75,35 @@ typedef struct {
     double m;
 } skyr_model;
 
+/* When the flow resets the velocity (Sec. 3, arrest).
+ *   SKYR_ARREST_ENERGY  the paper's rule: arrest at step k when E_k > E_{k-1}
+ *                       (strict; E_{-1} = +inf).
+ *   SKYR_ARREST_POWER   its instantaneous form: arrest at step k when the power
+ *                       P_k = h^3 sum_I F_k . v_k is negative (dE/dt = -F . v, so
+ *                       the energy has started to rise).  P needs no difference of
+ *                       two total energies; in single precision the rounding noise
+ *                       of E_k exceeds the per-step energy decrease well before the
+ *                       force reaches its floor, and the energy rule then fires on
+ *                       noise.  Recommended with SKYR_F32_BULK.
+ * Either way an arrest keeps phi_k and restarts from it with v_k = 0. */
+typedef enum {
+    SKYR_ARREST_ENERGY = 0,
+    SKYR_ARREST_POWER = 1
+} skyr_arrest_rule;
+
 /* Arrested Newton flow controls (Sec. 3).
  *   dt             fictitious time step (kick-drift step)
  *   tol            stop when max over I of |F| < tol, F the projected force
  *   max_steps      total cap on accepted steps across calls
  *   renorm64_every SKYR_F32_BULK only: every this many steps the renormalisation
- *                  phi <- phi/|phi| is done in double (0 = never; default 16) */
+ *                  phi <- phi/|phi| is done in double (0 = never; default 16)
+ *   arrest         a skyr_arrest_rule (0 = the paper's energy rule) */
 typedef struct {
     double dt;
     double tol;
     int64_t max_steps;
     int32_t renorm64_every;
-    int32_t _pad;
+    int32_t arrest;
 } skyr_flow;
 
 /* Initial data (Sec. 4). */

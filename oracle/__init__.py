@@ -80,6 +80,7 @@ def _load():
         "ora_baryon": (d, [i3, d, dp]),
         "ora_observables": (None, [i3, d, d, dp, dp]),
         "ora_update_at": (None, [dp, dp, dp, d, ctypes.c_int, dp, dp]),
+        "ora_power": (d, [i3, d, dp, dp]),
         "ora_anf": (i64, [i3, d, d, d, d, i64, ctypes.c_int, dp, dp, ctypes.POINTER(AnfState), dp,
                           ctypes.POINTER(i32)]),
         "ora_init_product": (None, [i3, d, i32, ctypes.POINTER(Constituent), dp]),
@@ -180,6 +181,13 @@ def project(phi, g) -> tuple[np.ndarray, float]:
     return gT, float(r)
 
 
+def power(gT, vel, h: float) -> float:
+    """h^3 sum over the interior of F . v with F = -gT (dE/dt along v is -power)."""
+    gT = _field(gT)
+    vel = _field(vel)
+    return float(_load().ora_power(_dims(gT.shape[1:]), h, _ptr(gT), _ptr(vel)))
+
+
 def gradient_at(phi, h: float, m: float, x: int, y: int, z: int) -> np.ndarray:
     """g at one interior site, from the flux at its stencil neighbours."""
     phi = _field(phi)
@@ -224,17 +232,21 @@ def observables(phi, h: float, m: float) -> dict:
 
 # ------------------------------------------------------------------------ ANF
 def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, state: AnfState | None = None,
-        arrest: bool = True, trace: bool = False):
+        arrest: bool = True, trace: bool = False, rule: str = "energy"):
     """Arrested Newton flow, in place on (phi, vel), until state.steps reaches
-    target_steps, max|F| < tol, or a non-finite value.  Returns
-    (phi, vel, state, E_trace, arrest_trace); traces are None unless trace."""
+    target_steps, max|F| < tol, or a non-finite value.  rule = "energy"
+    (arrest when E_n > E_{n-1}) or "power" (arrest when h^3 sum F_n . v_n < 0).
+    Returns (phi, vel, state, E_trace, arrest_trace); traces are None unless trace."""
+    if rule not in ("energy", "power"):
+        raise ValueError(f"unknown arrest rule {rule!r}")
     phi = _field(phi).copy()
     vel = _field(vel).copy()
     st = AnfState.fresh() if state is None else state
     n_max = max(int(target_steps) - int(st.steps), 0) + 1
     Et = np.full(n_max, np.nan) if trace else None
     At = np.zeros(n_max, dtype=np.int32) if trace else None
-    nev = _load().ora_anf(_dims(phi.shape[1:]), h, m, dt, tol, int(target_steps), int(bool(arrest)), _ptr(phi),
+    mode = 0 if not arrest else (1 if rule == "energy" else 2)
+    nev = _load().ora_anf(_dims(phi.shape[1:]), h, m, dt, tol, int(target_steps), mode, _ptr(phi),
                           _ptr(vel), ctypes.byref(st), _ptr(Et) if trace else None,
                           At.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if trace else None)
     if trace:

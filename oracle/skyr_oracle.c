@@ -504,11 +504,29 @@ ORA_API void ora_update_at(const double phi[4], const double vel[4], const doubl
     }
 }
 
+/* Power of the velocity field against the force, h^3 sum over I of F . v with
+ * F = -gT (the rate dE/dt = -F . v along the flow; Sec. 3, arrest read as
+ * "the energy starts to rise"). */
+ORA_API double ora_power(const int n[3], double h, const double *gT, const double *vel)
+{
+    const size_t N3 = n_sites(n);
+    double P = 0.0;
+    for (int x = 2; x <= n[0] - 3; x++)
+        for (int y = 2; y <= n[1] - 3; y++)
+            for (int z = 2; z <= n[2] - 3; z++) {
+                size_t s = site(n, x, y, z);
+                for (int A = 0; A < 4; A++) P += -FLD(gT, A, s) * FLD(vel, A, s);
+            }
+    return h * h * h * P;
+}
+
 /*
  * Run the flow from the state st until st->steps reaches target_steps, the
  * largest tangential gradient falls below tol, or a value stops being finite.
- * At step n:  E_n = E(phi_n); if E_n > E_{n-1} the velocity is reset (arrest);
- *             F_n = -(g - (g.phi) phi); stop if max|F_n| < tol;
+ * At step n:  E_n = E(phi_n); F_n = -(g - (g.phi) phi);
+ *             arrest (v_n := 0) if E_n > E_{n-1}            (arrest = 1, energy rule)
+ *                            or if h^3 sum F_n . v_n < 0    (arrest = 2, power rule);
+ *             stop if max|F_n| < tol;
  *             v_{n+1} = v_n + dt F_n; phi_{n+1} = normalise(phi_n + dt v_{n+1}).
  * arrest = 0 gives the plain Newton flow (no resets).
  * E_trace / arrest_trace (nullable) receive E_n and the reset flag for each
@@ -524,13 +542,15 @@ ORA_API int64_t ora_anf(const int n[3], double h, double m, double dt, double to
     int64_t evaluated = 0;
     while (st->steps < target_steps) {
         double E = ora_energy(n, h, m, phi);
-        int reset = arrest && (E > st->E_prev);
+        ora_gradient(n, h, m, phi, g);
+        double r = ora_project(n, phi, g, gT);
+        int reset = 0;
+        if (arrest == 1) reset = E > st->E_prev;
+        else if (arrest == 2) reset = ora_power(n, h, gT, vel) < 0.0;
         if (reset) {
             memset(vel, 0, 4 * N3 * sizeof(double));
             st->arrests++;
         }
-        ora_gradient(n, h, m, phi, g);
-        double r = ora_project(n, phi, g, gT);
         st->E = E;
         st->max_force = r;
         if (E_trace) E_trace[evaluated] = E;

@@ -248,32 +248,31 @@ __global__ void copy_frozen_kernel(const T* __restrict__ src, T* __restrict__ ds
 
 // Fixed-order reduction of the per-block partials: thread t sums blocks
 // t, t + 256, ... in order, then a fixed tree.  out = {E2, E4, E0, Bsum, maxF2}.
-__device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[5])
+__device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[6])
 {
-    __shared__ double red[256][5];
+    __shared__ double red[256][6];
     const int t = threadIdx.x;
-    double s[5] = {0, 0, 0, 0, 0};
+    double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b = t; b < nblocks; b += 256) {
         const double* p = part + (size_t)b * NPART;
-        for (int i = 0; i < 4; ++i) s[i] += p[i];
-        s[4] = fmax(s[4], p[4]);
+        for (int i = 0; i < 6; ++i) s[i] = (i == P_F2) ? fmax(s[i], p[i]) : s[i] + p[i];
     }
-    for (int i = 0; i < 5; ++i) red[t][i] = s[i];
+    for (int i = 0; i < 6; ++i) red[t][i] = s[i];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
-            for (int i = 0; i < 4; ++i) red[t][i] += red[t + w][i];
-            red[t][4] = fmax(red[t][4], red[t + w][4]);
+            for (int i = 0; i < 6; ++i)
+                red[t][i] = (i == P_F2) ? fmax(red[t][i], red[t + w][i]) : red[t][i] + red[t + w][i];
         }
         __syncthreads();
     }
-    for (int i = 0; i < 5; ++i) out[i] = red[0][i];
+    for (int i = 0; i < 6; ++i) out[i] = red[0][i];
 }
 
 // obs = {E, E2, E4, E0, B, virial, max_force}
 __global__ void observe_kernel(const double* __restrict__ part, int nblocks, double h, double* __restrict__ obs)
 {
-    double s[5];
+    double s[6];
     reduce_partials(part, nblocks, s);
     if (threadIdx.x == 0) {
         const double h3 = h * h * h;
@@ -289,12 +288,13 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
 }
 
 // The flow's decision after the sweep over phi_k (Sec. 3): arrest when
-// E_k > E_{k-1} (re-run the sweep with v_k = 0), stop when max|F_k| < tol,
+// E_k > E_{k-1} (energy rule) or when the power h^3 sum F_k . v_k < 0 (power
+// rule), re-running the sweep with v_k = 0; stop when max|F_k| < tol;
 // otherwise accept the update (swap buffers).
 __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;  // uniform
-    double s[5];
+    double s[6];
     reduce_partials(part, ctl->nblocks, s);
     if (threadIdx.x != 0) return;
     // the flow sweep sums the whole energy density in slot 0 (slots 1, 2 are zero)
@@ -302,6 +302,7 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
     const double r = sqrt(s[4]);
     ctl->sweeps += 1;
     ctl->E = E;
+    ctl->P = ctl->h3 * s[P_POW];
     ctl->max_force = r;
     if (!isfinite(E) || !isfinite(r)) {
         ctl->done = 1;
@@ -309,7 +310,7 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
         return;
     }
     bool arrest = false;
-    if (!ctl->redo && E > ctl->E_prev) {
+    if (!ctl->redo && (ctl->arrest_rule == SKYR_ARREST_POWER ? ctl->P < 0.0 : E > ctl->E_prev)) {
         arrest = true;
         ctl->arrests += 1;
     }
@@ -710,6 +711,8 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (!(flow->tol >= 0.0)) return fail(SKYR_E_INVAL, "tol must be >= 0");
     if (nsteps < 0 || flow->max_steps < 0 || flow->renorm64_every < 0) return fail(SKYR_E_INVAL, "negative step count");
+    if (flow->arrest != SKYR_ARREST_ENERGY && flow->arrest != SKYR_ARREST_POWER)
+        return fail(SKYR_E_INVAL, "unknown arrest rule");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     hipStream_t s = (hipStream_t)stream;
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
@@ -734,6 +737,7 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     h.redo_sweeps = st->redo_sweeps;
     h.sweeps = st->sweeps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
+    h.arrest_rule = flow->arrest;
     h.nblocks = L.blocks();
     h.E_prev = st->E_prev;
     h.E = st->E;
@@ -1092,6 +1096,8 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
         return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
+    if (flow->arrest != SKYR_ARREST_ENERGY && flow->arrest != SKYR_ARREST_POWER)
+        return fail(SKYR_E_INVAL, "unknown arrest rule");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     int j = -1;
     for (int k = 0; k < b->max_jobs; ++k)
@@ -1112,6 +1118,7 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     Ctl h{};
     h.target = flow->max_steps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
+    h.arrest_rule = flow->arrest;
     h.nblocks = L.blocks();
     h.E_prev = INFINITY;
     h.E = NAN;

@@ -29,7 +29,7 @@ namespace skyr {
 
 // partial-sum slots per thread block (doubles)
 constexpr int NPART = 8;
-enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4 };
+enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4, P_POW = 5 };
 
 // Control block of one flow, in device memory at the start of the workspace.
 struct Ctl {
@@ -44,9 +44,12 @@ struct Ctl {
     int64_t sweeps;
     int32_t renorm64_every;
     int32_t nblocks;      // number of partial-sum blocks of the sweep
+    int32_t arrest_rule;  // skyr_arrest_rule
+    int32_t pad_i;
     double E_prev;
     double E;
-    double unused_[3];
+    double P;             // power h^3 sum F_k . v_k of the last sweep (arrest rule POWER)
+    double unused_[1];
     double max_force;
     double tol;
     double h3;
@@ -165,7 +168,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     int xb, xe;
     int zl, rg, z, hrow, hcol;
     unsigned hoff;  // byte offset of this thread's halo site within a plane
-    bool halo_loader, redo, renorm64, projected, baryon, has_grad;
+    bool halo_loader, redo, renorm64, projected, baryon, has_grad, power;
     bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
     int yk[RY];
     unsigned offk[RY];  // byte offsets of the flux positions within a plane
@@ -181,6 +184,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
     // flow step keeps the total energy density in pe2 and leaves the others at zero
     double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0;
+    double pp = 0.0;  // power F . v of the incoming velocity (flow step, arrest rule POWER)
     T pf2 = T(0);
 
     __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
@@ -358,6 +362,12 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                     for (int A = 0; A < 4; ++A) f[A] = gp * p[A] - g[A];  // F = -(g - (g.phi) phi)
                     pf2 = fmax(pf2, dot4(f, f));
                     if constexpr (MODE == MODE_STEP) {
+                        if (power) {
+                            T fv = T(0);
+#pragma unroll
+                            for (int A = 0; A < 4; ++A) fv += f[A] * vcur[A][k];
+                            pp += (double)fv;
+                        }
                         T v[4], q[4], pn[4];
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
@@ -430,10 +440,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     SW sw(smem);
     sw.redo = false;
     sw.renorm64 = false;
+    sw.power = false;
     if constexpr (MODE == MODE_STEP) {
         if (ctl->done) return;  // uniform: the flow has stopped
         cur = ctl->cur;
         sw.redo = ctl->redo != 0;
+        sw.power = ctl->arrest_rule == 1 && !sw.redo;
         const int kr = ctl->renorm64_every;
         sw.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
     }
@@ -566,9 +578,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[5] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2};
+    double vals[6] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, sw.pp};
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
         double v = vals[i];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -579,17 +591,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 5; ++i) smem.red[wave][i] = vals[i];
+        for (int i = 0; i < 6; ++i) smem.red[wave][i] = vals[i];
     }
     __syncthreads();
     if (tid == 0) {
-        double sum[5] = {0, 0, 0, 0, 0};
+        double sum[6] = {0, 0, 0, 0, 0, 0};
         for (int wv = 0; wv < NW; ++wv) {
-            for (int i = 0; i < 4; ++i) sum[i] += smem.red[wv][i];
-            sum[4] = fmax(sum[4], smem.red[wv][4]);
+            for (int i = 0; i < 6; ++i) sum[i] = (i == 4) ? fmax(sum[i], smem.red[wv][i]) : sum[i] + smem.red[wv][i];
         }
         double* out = a.partials + (size_t)b * NPART;
-        for (int i = 0; i < 5; ++i) out[i] = sum[i];
+        for (int i = 0; i < 6; ++i) out[i] = sum[i];
     }
 }
 

@@ -17,6 +17,14 @@ LIB_PATH = _PKG / "libskyr.so"
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, -1, -2, -3, -4, -5
 F64, F32_BULK = 0, 1
+ARREST_ENERGY, ARREST_POWER = 0, 1
+
+
+def arrest_rule(rule) -> int:
+    """skyr_arrest_rule value of "energy" / "power" (or of the value itself)."""
+    if isinstance(rule, str):
+        return {"energy": ARREST_ENERGY, "power": ARREST_POWER}[rule]
+    return int(rule)
 INIT_HEDGEHOG, INIT_RATIONAL_MAP, INIT_PRODUCT, INIT_RANDOM_PRODUCT = 0, 1, 2, 3
 
 
@@ -44,7 +52,7 @@ class Model(ctypes.Structure):
 
 class Flow(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
-                ("renorm64_every", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+                ("renorm64_every", ctypes.c_int32), ("arrest", ctypes.c_int32)]
 
 
 class Constituent(ctypes.Structure):

@@ -64,11 +64,22 @@ RANDOM_B10_256 = dict(name="random-b10-256", n=256, h=0.1, m=1.0, dt=0.01, tol=1
 
 WORKLOADS = {w["name"]: w for w in (HEDGEHOG_40, HEDGEHOG_40_SMALLDT, CUBE_B4_128, RANDOM_B10_256)}
 
+# Single-precision force floor: max |F| of a converged FP64 field rounded to FP32,
+# evaluated in FP32, measured at h = 0.1 ... 0.2 and fitted as FLOOR32_COEF / h^2.
+FLOOR32_COEF = 1.3e-6
+
+
+def f32_tolerance(tol: float, h: float) -> float:
+    """Stopping tolerance of an FP32-bulk relaxation: the requested one, but no
+    less than twice the single-precision force floor at spacing h."""
+    return max(tol, 2.0 * FLOOR32_COEF / (h * h))
+
 
 def batch_jobs(master_seed: int = 4, count: int = 64) -> list[dict]:
     """The batched workload: `count` independent relaxations with B ~ U{1..8},
-    n ~ U{48, 64, 96, 128}, m ~ U{0, 1}, h = 0.15, dt = 0.015, FP32 bulk,
-    random product-ansatz initial data with a per-job seed."""
+    n ~ U{48, 64, 96, 128}, m ~ U{0, 1}, h = 0.15, dt = 0.015, FP32 bulk
+    with the power arrest rule, random product-ansatz initial data with a
+    per-job seed."""
     g = SplitMix64(master_seed)
     jobs = []
     for j in range(count):
@@ -76,9 +87,9 @@ def batch_jobs(master_seed: int = 4, count: int = 64) -> list[dict]:
         n = g.choice([48, 64, 96, 128])
         m = float(g.randint(0, 1))
         seed = g.next()
-        jobs.append(dict(name=f"batch-{master_seed}-{j}", n=n, h=0.15, m=m, dt=0.015, tol=1e-4, steps=20000,
-                         precision="f32", init={"kind": "random_product", "B": B, "seed": seed, "radius": 3.0,
-                                                "prof_lambda": 1.0}))
+        jobs.append(dict(name=f"batch-{master_seed}-{j}", n=n, h=0.15, m=m, dt=0.015, tol=f32_tolerance(1e-4, 0.15),
+                         steps=20000, precision="f32", arrest="power",
+                         init={"kind": "random_product", "B": B, "seed": seed, "radius": 3.0, "prof_lambda": 1.0}))
     return jobs
 
 
@@ -86,7 +97,8 @@ def served_stream(master_seed: int = 5, count: int = 256, rate: float = 1.0) -> 
     """The served workload: Poisson arrivals (exponential gaps of mean 1/rate
     seconds) of relaxations with B ~ U{1..12}, n log-uniform on [48, 192]
     rounded to even, h ~ U[0.1, 0.2], precision FP32 or FP64 with p = 1/2,
-    dt = 0.1 h, tolerance 1e-4, cap 20000 steps."""
+    dt = 0.1 h, tolerance 1e-4, cap 20000 steps.  FP64 jobs use the energy
+    arrest rule; FP32-bulk jobs the power rule and f32_tolerance(1e-4, h)."""
     g = SplitMix64(master_seed)
     t = 0.0
     jobs = []
@@ -97,8 +109,9 @@ def served_stream(master_seed: int = 5, count: int = 256, rate: float = 1.0) -> 
         h = 0.1 + 0.1 * g.uniform()
         prec = "f32" if g.uniform() < 0.5 else "f64"
         seed = g.next()
-        jobs.append(dict(name=f"serve-{master_seed}-{j}", arrival=t, n=n, h=h, m=1.0, dt=0.1 * h, tol=1e-4,
-                         steps=20000, precision=prec,
+        jobs.append(dict(name=f"serve-{master_seed}-{j}", arrival=t, n=n, h=h, m=1.0, dt=0.1 * h,
+                         tol=f32_tolerance(1e-4, h) if prec == "f32" else 1e-4, steps=20000, precision=prec,
+                         arrest="power" if prec == "f32" else "energy",
                          init={"kind": "random_product", "B": B, "seed": seed, "radius": 3.0, "prof_lambda": 1.0}))
     return jobs
 

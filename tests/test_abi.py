@@ -77,7 +77,8 @@ def test_invalid_arguments_rejected_without_device_work():
     # flow arguments
     st = skyr.anf_state()
     for flow in (skyr.Flow(0.0, 0.0, 10, 0, 0), skyr.Flow(-1.0, 0.0, 10, 0, 0), skyr.Flow(0.1, -1.0, 10, 0, 0),
-                 skyr.Flow(0.1, 0.0, -1, 0, 0), skyr.Flow(float("nan"), 0.0, 10, 0, 0)):
+                 skyr.Flow(0.1, 0.0, -1, 0, 0), skyr.Flow(float("nan"), 0.0, 10, 0, 0),
+                 skyr.Flow(0.1, 0.0, 10, 0, 2), skyr.Flow(0.1, 0.0, 10, 0, -1)):
         assert L.skyr_anf_step(ctypes.byref(lat), 0, ctypes.byref(model), ctypes.byref(flow), fake,
                                ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.byref(st), 1, fake,
                                None) == skyr.E_INVAL

@@ -207,6 +207,22 @@ def test_flow_with_arrests_matches_oracle(skyr):
     assert np.abs(phi.cpu().numpy() - ref).max() < 1e-10
 
 
+def test_flow_power_rule_matches_oracle(skyr):
+    """Power arrest rule (reset when h^3 sum F.v < 0): the resets fire on the
+    same steps as in the oracle and the fields agree after 80 steps."""
+    n, h, m, dt = 24, 0.25, 1.0, 0.06
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+    ref0 = phi.cpu().numpy()
+    st = skyr.anf_state()
+    flow = skyr.Flow(dt, 0.0, 10 ** 9, 0, skyr.ARREST_POWER)
+    skyr.anf_step(lat, 0, skyr.Model(m), flow, phi, alt, vel, st, 80, work)
+    ref, rvel, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, 0.0, 80, rule="power")
+    assert rst.arrests > 0
+    assert st.steps == 80 and st.arrests == rst.arrests and st.redo_sweeps == rst.arrests
+    assert np.abs(phi.cpu().numpy() - ref).max() < 1e-10
+    assert np.abs(vel.cpu().numpy() - rvel).max() < 1e-9
+
+
 def test_flow_resume_across_calls(skyr):
     """Chained calls (7 + 13 + 20 steps) equal one call of 40 steps, bitwise."""
     n, h, m, dt = 28, 0.25, 1.0, 0.05
@@ -256,6 +272,27 @@ def test_converged_f32_bulk_against_oracle(skyr):
           f"oracle {ro['E']:.10f} B32 {got['B']:.8f} oracle B {ro['B']:.8f}")
     assert e64 == pytest.approx(ro["E"], rel=1e-6)
     assert got["E"] == pytest.approx(ro["E"], rel=1e-6)
+    assert got["B"] == pytest.approx(ro["B"], abs=1e-3)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_converged_power_rule_against_oracle(skyr, prec):
+    """Power arrest rule, FP64 and FP32-bulk: the hedgehog relaxes to the same
+    minimum as the oracle's energy-rule flow (energy within 1e-8 in FP64,
+    1e-6 in FP32-bulk; B within 1e-3)."""
+    n, h, m, dt = 40, 0.2, 1.0, 0.02
+    tol = 1e-5 if prec == 0 else 1e-4
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt, prec=prec)
+    ref0 = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(m), skyr.Flow(dt, tol, 20000, 16, skyr.ARREST_POWER), phi, alt, vel, st,
+                  20000, work)
+    assert st.converged == 1
+    ref, _, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, 1e-5, 20000)
+    got = skyr.observables(lat, prec, skyr.Model(m), phi, work)
+    ro = oracle.observables(ref, h, m)
+    print(f"power rule prec {prec}: steps {st.steps} arrests {st.arrests} E {got['E']:.12f} oracle {ro['E']:.12f}")
+    assert got["E"] == pytest.approx(ro["E"], rel=1e-8 if prec == 0 else 1e-6)
     assert got["B"] == pytest.approx(ro["B"], abs=1e-3)
 
 

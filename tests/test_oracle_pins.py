@@ -359,6 +359,56 @@ def test_arrest_trace():
     np.testing.assert_allclose(v2, -dt * gT, atol=1e-15)
 
 
+def _tangential(phi, v):
+    """v - (v.phi) phi on the interior, zero on the frozen layers."""
+    t = v - (v * phi).sum(0, keepdims=True) * phi
+    t[:, ~interior_mask(phi.shape[1:])] = 0.0
+    return t
+
+
+def test_power_is_minus_energy_rate():
+    """The power h^3 sum F.v used by the power arrest rule is minus the rate of
+    change of the discrete energy along a tangential velocity field v:
+    P = -dE/de of E(phi + e v) at e = 0 (central differences of the energy,
+    Richardson-extrapolated).  Pins its sign, the h^3 factor and F = -gT."""
+    n, h, m = (9, 10, 8), 0.3, 0.8
+    phi = random_unit_field(n, 21, 0.5)
+    v = _tangential(phi, random_unit_field(n, 22, 1.0) - random_unit_field(n, 23, 1.0))
+    gT, _ = oracle.project(phi, oracle.gradient(phi, h, m))
+    P = oracle.power(gT, v, h)
+
+    def slope(e):
+        return (oracle.energy(phi + e * v, h, m) - oracle.energy(phi - e * v, h, m)) / (2 * e)
+
+    e = 1e-4
+    dE = (4 * slope(e / 2) - slope(e)) / 3
+    assert abs(P) > 1e-3
+    assert P == pytest.approx(-dE, rel=1e-8)
+
+
+def test_power_rule_trace_and_same_minimum():
+    """Power rule: the velocity is reset at step n exactly when h^3 sum F_n.v_n
+    < 0 for the state entering that step (never at step 0, v = 0); and the
+    power and energy rules relax the hedgehog to the same discrete minimum."""
+    n, h, m, dt = 20, 0.25, 1.0, 0.06
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    _, _, st, _, At = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, 60, trace=True, rule="power")
+    assert At[0] == 0 and st.arrests == At.sum() and st.arrests > 0
+    p, v, s2 = phi, np.zeros_like(phi), oracle.AnfState.fresh()
+    for k in range(60):
+        gT, _ = oracle.project(p, oracle.gradient(p, h, m))
+        assert bool(At[k]) == (oracle.power(gT, v, h) < 0.0)
+        p, v, s2, _, _ = oracle.anf(p, v, h, m, dt, 0.0, k + 1, s2, rule="power")
+    n, h, dt = 24, 0.2, 0.02
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    res = {}
+    for rule in ("energy", "power"):
+        _, _, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 1e-7, 20000, rule=rule)
+        assert st.converged == 1
+        res[rule] = st.E
+    assert res["power"] == pytest.approx(res["energy"], rel=1e-12)
+
+
 def test_resume_equals_uninterrupted():
     n, h, m, dt = 16, 0.25, 1.0, 0.04
     phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
