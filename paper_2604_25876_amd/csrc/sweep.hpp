@@ -88,7 +88,9 @@ template <typename T> struct Coef {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ float rnorm(float s) { return rsqrtf(s); }
+// 1/sqrt(s) for s near 1 (a renormalisation): the hardware reciprocal square root,
+// without the denormal rescaling rsqrtf wraps around it
+__device__ __forceinline__ float rnorm(float s) { return __builtin_amdgcn_rsqf(s); }
 __device__ __forceinline__ double rnorm(double s) { return 1.0 / sqrt(s); }
 
 // element access by a 32-bit byte offset from a uniform base: the offset stays in one
@@ -101,6 +103,14 @@ template <typename T> __device__ __forceinline__ void stb(T* base, unsigned off,
 {
     *(T*)((char*)base + off) = v;
 }
+
+// max of two non-negative values (or NaN): for floats the unsigned order of the bit
+// patterns is the numeric order, and a NaN pattern exceeds +inf
+__device__ __forceinline__ float fmax_nonneg(float a, float b)
+{
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ double fmax_nonneg(double a, double b) { return fmax(a, b); }
 
 template <typename T> __device__ __forceinline__ T dot4(const T* a, const T* b)
 {
@@ -152,8 +162,12 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 
     struct Smem {
         T phi[2][4][PY + 4][LW + 4];  // phi of two planes, rows y0-4 .. y0+PY-1, columns z0-4 .. z0+LW-1
-        T qy[2][4][PY][LW];           // y-flux of two planes, flux rows and columns
-        T qz[2][4][PY][LW];           // z-flux of two planes
+        // y- and z-flux of two planes, flux row r at [r + 2]: two unwritten rows above and below
+        // let the divergence read rows r-2 .. r+2 and (row-major, flat) columns c-2 .. c+2
+        // without clamping; the values read there only reach positions whose result is
+        // discarded.  The row stride stays LW, so the two rows of a wave fall on distinct banks.
+        T qy[2][4][PY + 4][LW];
+        T qz[2][4][PY + 4][LW];
         double red[NW][NPART];
     };
 
@@ -168,7 +182,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     int xb, xe;
     int zl, rg, z, hrow, hcol;
     unsigned hoff;  // byte offset of this thread's halo site within a plane
-    bool halo_loader, redo, renorm64, projected, baryon, has_grad, power;
+    bool halo_loader, redo, renorm64, projected, baryon, has_grad;
     bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
     int yk[RY];
     unsigned offk[RY];  // byte offsets of the flux positions within a plane
@@ -184,7 +198,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
     // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
     // flow step keeps the total energy density in pe2 and leaves the others at zero
     double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0;
-    double pp = 0.0;  // power F . v of the incoming velocity (flow step, arrest rule POWER)
+    T pp = T(0);  // power F . v of the incoming velocity (flow step; used by the power arrest rule)
     T pf2 = T(0);
 
     __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
@@ -298,12 +312,12 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
             const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
             const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
 #pragma unroll
-            for (int A = 0; A < 4; ++A) sm.qy[pb][A][r - 2][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
+            for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
             if (full) {
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
                     const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
-                    sm.qz[pb][A][r - 2][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
+                    sm.qz[pb][A][r][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
                     // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
                     acc[S_M1][A][k] -= c1h * qx;
                     acc[S_P1][A][k] += c1h * qx;
@@ -330,15 +344,13 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
         if (full && j - 1 >= xb && j - 1 < xe) {
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
-                const int r = rg + k * R0;
-                const int rm2 = max(r - 2, 0), rm1 = max(r - 1, 0), rp1 = min(r + 1, PY - 1), rp2 = min(r + 2, PY - 1);
-                const int zm2 = max(zl - 2, 0), zm1 = max(zl - 1, 0), zp1 = min(zl + 1, LW - 1), zp2 = min(zl + 2, LW - 1);
+                const int o = (rg + k * R0 + 2) * LW + zl;
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    const T dy = c1h * (sm.qy[qb][A][rp1][zl] - sm.qy[qb][A][rm1][zl]) +
-                                 c2h * (sm.qy[qb][A][rp2][zl] - sm.qy[qb][A][rm2][zl]);
-                    const T dz = c1h * (sm.qz[qb][A][r][zp1] - sm.qz[qb][A][r][zm1]) +
-                                 c2h * (sm.qz[qb][A][r][zp2] - sm.qz[qb][A][r][zm2]);
+                    const T* qy = &sm.qy[qb][A][0][0] + o;
+                    const T* qz = &sm.qz[qb][A][0][0] + o;
+                    const T dy = c1h * (qy[LW] - qy[-LW]) + c2h * (qy[2 * LW] - qy[-2 * LW]);
+                    const T dz = c1h * (qz[1] - qz[-1]) + c2h * (qz[2] - qz[-2]);
                     acc[S_M1][A][k] -= dy + dz;
                 }
             }
@@ -360,14 +372,10 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
                     const T gp = dot4(g, p);
 #pragma unroll
                     for (int A = 0; A < 4; ++A) f[A] = gp * p[A] - g[A];  // F = -(g - (g.phi) phi)
-                    pf2 = fmax(pf2, dot4(f, f));
+                    pf2 = fmax_nonneg(pf2, dot4(f, f));
                     if constexpr (MODE == MODE_STEP) {
-                        if (power) {
-                            T fv = T(0);
-#pragma unroll
-                            for (int A = 0; A < 4; ++A) fv += f[A] * vcur[A][k];
-                            pp += (double)fv;
-                        }
+                        // power of the incoming velocity (zero on a redo sweep, where v = 0)
+                        pp += f[0] * vcur[0][k] + f[1] * vcur[1][k] + f[2] * vcur[2][k] + f[3] * vcur[3][k];
                         T v[4], q[4], pn[4];
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
@@ -440,12 +448,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     SW sw(smem);
     sw.redo = false;
     sw.renorm64 = false;
-    sw.power = false;
     if constexpr (MODE == MODE_STEP) {
         if (ctl->done) return;  // uniform: the flow has stopped
         cur = ctl->cur;
         sw.redo = ctl->redo != 0;
-        sw.power = ctl->arrest_rule == 1 && !sw.redo;
         const int kr = ctl->renorm64_every;
         sw.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
     }
@@ -578,7 +584,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[6] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, sw.pp};
+    double vals[6] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, (double)sw.pp};
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double v = vals[i];
