@@ -93,8 +93,14 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 __device__ __forceinline__ float rnorm(float s) { return __builtin_amdgcn_rsqf(s); }
 __device__ __forceinline__ double rnorm(double s) { return 1.0 / sqrt(s); }
 
-// element access by a 32-bit byte offset from a uniform base: the offset stays in one
-// VGPR and the base in SGPRs (no 64-bit address arithmetic per access)
+// Field access by a 32-bit byte offset from a base that is uniform over the block: the
+// offset stays in one VGPR and the base in SGPRs (no 64-bit address arithmetic per
+// access).  Kernel arguments are known to be global, uniform pointers; pointers read
+// from a batch's job table are made so explicitly (uniform_ptr, global address space).
+#define SKYR_GLOBAL __attribute__((address_space(1)))
+template <typename T> using gptr = SKYR_GLOBAL T*;
+template <bool GLOBAL, typename T> using fptr = std::conditional_t<GLOBAL, gptr<T>, T*>;
+
 template <typename T> __device__ __forceinline__ T ldb(const T* base, unsigned off)
 {
     return *(const T*)((const char*)base + off);
@@ -102,6 +108,23 @@ template <typename T> __device__ __forceinline__ T ldb(const T* base, unsigned o
 template <typename T> __device__ __forceinline__ void stb(T* base, unsigned off, T v)
 {
     *(T*)((char*)base + off) = v;
+}
+template <typename T> __device__ __forceinline__ T ldb(gptr<const T> base, unsigned off)
+{
+    return *(gptr<const T>)((SKYR_GLOBAL const char*)base + off);
+}
+template <typename T> __device__ __forceinline__ void stb(gptr<T> base, unsigned off, T v)
+{
+    *(gptr<T>)((SKYR_GLOBAL char*)base + off) = v;
+}
+
+// a pointer that is the same in every lane, made visibly uniform (held in SGPRs)
+template <typename P> __device__ __forceinline__ P uniform_ptr(P p)
+{
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (P)(((unsigned long long)hi << 32) | lo);
 }
 
 // max of two non-negative values (or NaN): for floats the unsigned order of the bit
@@ -150,7 +173,7 @@ template <typename T, int NW, int LW, int RY> struct Tile {
     static_assert(THREADS >= NH, "every halo site of a plane has its own loading thread");
 };
 
-template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false> struct Sweeper {
     using TL = Tile<T, NW, LW, RY>;
     static constexpr int PY = TL::PY;
     static constexpr int R0 = TL::R0;
@@ -173,10 +196,10 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 
     Smem& sm;
     // per-component base pointers (uniform); element offsets within a component fit 32 bits
-    const T* pin[4];
-    T* pout[4];
-    T* vel[4];
-    T* gout[4];
+    fptr<FROM_TABLE, const T> pin[4];
+    fptr<FROM_TABLE, T> pout[4];
+    fptr<FROM_TABLE, T> vel[4];
+    fptr<FROM_TABLE, T> gout[4];
     int n0, n1, n2;
     unsigned plane_b;  // bytes per x-plane of one component
     int xb, xe;
@@ -248,7 +271,7 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 #pragma unroll
             for (int A = 0; A < 4; ++A)
 #pragma unroll
-                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : ldb((const T*)vel[A], vb + offk[k]);
+                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : ldb((fptr<FROM_TABLE, const T>)vel[A], vb + offk[k]);
         }
 
         const bool j_in = (j >= 2) && (j <= n0 - 3);
@@ -433,12 +456,13 @@ template <typename T, int NW, int LW, int RY, int MODE> struct Sweeper {
 };
 
 // One block's share of one field: logical block b of nb blocks covering the
-// field's work items.  Used by the single-field and the batched kernels.
-template <typename T, int NW, int LW, int RY, int MODE>
+// field's work items.  Used by the single-field and the batched kernels
+// (FROM_TABLE: the arguments were read from the batch's job table).
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
-                                            typename Sweeper<T, NW, LW, RY, MODE>::Smem& smem)
+                                            typename Sweeper<T, NW, LW, RY, MODE, FROM_TABLE>::Smem& smem)
 {
-    using SW = Sweeper<T, NW, LW, RY, MODE>;
+    using SW = Sweeper<T, NW, LW, RY, MODE, FROM_TABLE>;
     using TL = typename SW::TL;
     constexpr int PY = TL::PY;
     constexpr int R0 = TL::R0;
@@ -464,12 +488,20 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     {
         const T* pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
         T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
+        T* pvel = (T*)a.vel;
+        T* pgrad = (T*)a.grad;
+        if constexpr (FROM_TABLE) {
+            // read from the job table: the same for the whole block, kept in SGPRs
+            pin = uniform_ptr(pin);
+            pout = uniform_ptr(pout);
+            pvel = uniform_ptr(pvel);
+        }
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-            sw.pin[A] = pin + A * N3;
-            sw.pout[A] = pout ? pout + A * N3 : nullptr;
-            sw.vel[A] = a.vel ? (T*)a.vel + A * N3 : nullptr;
-            sw.gout[A] = a.grad ? (T*)a.grad + A * N3 : nullptr;
+            sw.pin[A] = (fptr<FROM_TABLE, const T>)(pin + A * N3);
+            sw.pout[A] = (fptr<FROM_TABLE, T>)(pout ? pout + A * N3 : nullptr);
+            sw.vel[A] = (fptr<FROM_TABLE, T>)(pvel ? pvel + A * N3 : nullptr);
+            sw.gout[A] = (fptr<FROM_TABLE, T>)(pgrad ? pgrad + A * N3 : nullptr);
         }
     }
     sw.has_grad = a.grad != nullptr;
@@ -636,11 +668,11 @@ __global__ __launch_bounds__(NW * 64) void batch_sweep_kernel(const SweepArgs* _
                                                               const int* __restrict__ first_block,
                                                               const int* __restrict__ blocks_of_job)
 {
-    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP>::Smem smem;
+    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP, true>::Smem smem;
     const int i = xcd_logical_block(blockIdx.x, gridDim.x);
     const int j = job_of_block[i];
     const SweepArgs a = jobs[j];
-    sweep_block<T, NW, LW, RY, MODE_STEP>(a, i - first_block[j], blocks_of_job[j], smem);
+    sweep_block<T, NW, LW, RY, MODE_STEP, true>(a, i - first_block[j], blocks_of_job[j], smem);
 }
 
 }  // namespace skyr

@@ -296,6 +296,31 @@ def test_converged_power_rule_against_oracle(skyr, prec):
     assert got["B"] == pytest.approx(ro["B"], abs=1e-3)
 
 
+@pytest.mark.parametrize("kr", [1, 16, 64])
+def test_f32_bulk_norm_drift(skyr, kr):
+    """FP32-bulk with the FP64 renormalisation every kr steps: after 640 steps
+    of the random B = 4 product (64^3, h = 0.15) every interior site still has
+    | |phi| - 1 | <= 1e-6 (the single-precision renormalisation keeps it at the
+    rounding level between the double-precision ones), and the frozen layers
+    are untouched."""
+    n, h, m, dt = 64, 0.15, 1.0, 0.015
+    desc = {"kind": "random_product", "B": 4, "seed": 3, "radius": 2.0, "prof_lambda": 1.0}
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt, prec=1, desc=desc)
+    frozen0 = phi.clone()
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 1, skyr.Model(m), skyr.Flow(dt, 0.0, 640, kr, skyr.ARREST_POWER), phi, alt, vel, st, 640, work)
+    assert st.steps == 640 and not st.nonfinite
+    p = phi.double().cpu().numpy()
+    nrm = np.sqrt((p ** 2).sum(0))
+    inner = np.zeros(p.shape[1:], dtype=bool)
+    inner[2:-2, 2:-2, 2:-2] = True
+    dev = np.abs(nrm[inner] - 1.0).max()
+    print(f"kr {kr}: max | |phi| - 1 | = {dev:.3e}")
+    assert dev <= 1e-6
+    f0 = frozen0.cpu().numpy()
+    assert np.array_equal(phi.cpu().numpy()[:, ~inner], f0[:, ~inner])
+
+
 # ---------------------------------------------------------- edge cases
 def test_smallest_lattice(skyr):
     """n = 5: a single interior site."""
