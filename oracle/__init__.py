@@ -71,22 +71,22 @@ def _load():
     sig = {
         "ora_first_derivatives": (None, [i3, d, dp, dp]),
         "ora_laplacian": (None, [i3, d, dp, dp]),
-        "ora_energy_parts": (None, [i3, d, d, dp, dp]),
-        "ora_energy": (d, [i3, d, d, dp]),
+        "ora_energy_parts": (None, [i3, d, dp, dp, dp]),
+        "ora_energy": (d, [i3, d, dp, dp]),
         "ora_flux": (None, [i3, d, dp, dp]),
-        "ora_gradient": (None, [i3, d, d, dp, dp]),
+        "ora_gradient": (None, [i3, d, dp, dp, dp]),
         "ora_project": (d, [i3, dp, dp, dp]),
-        "ora_gradient_at": (None, [i3, d, d, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]),
+        "ora_gradient_at": (None, [i3, d, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]),
         "ora_baryon": (d, [i3, d, dp]),
-        "ora_observables": (None, [i3, d, d, dp, dp]),
+        "ora_observables": (None, [i3, d, dp, dp, dp]),
         "ora_update_at": (None, [dp, dp, dp, d, ctypes.c_int, dp, dp]),
         "ora_power": (d, [i3, d, dp, dp]),
-        "ora_anf": (i64, [i3, d, d, d, d, i64, ctypes.c_int, dp, dp, ctypes.POINTER(AnfState), dp,
+        "ora_anf": (i64, [i3, d, dp, d, d, i64, ctypes.c_int, dp, dp, ctypes.POINTER(AnfState), dp,
                           ctypes.POINTER(i32)]),
         "ora_init_product": (None, [i3, d, i32, ctypes.POINTER(Constituent), dp]),
         "ora_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, i64]),
         "ora_random_constituents": (None, [ctypes.c_uint64, i32, d, d, d, ctypes.POINTER(Constituent)]),
-        "ora_gradient_literal": (None, [i3, d, d, dp, dp]),
+        "ora_gradient_literal": (None, [i3, d, dp, dp, dp]),
         "ora_num_threads": (ctypes.c_int, []),
         "ora_set_num_threads": (None, [ctypes.c_int]),
     }
@@ -96,6 +96,14 @@ def _load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def _mass(m) -> ctypes.Array:
+    """Potential masses {m_x, m_y, m_z, m_w}: a float is the pion mass m_x alone."""
+    vals = [float(m)] if np.isscalar(m) else [float(v) for v in m]
+    if not 1 <= len(vals) <= 4:
+        raise ValueError("give the pion mass or up to four potential masses")
+    return (ctypes.c_double * 4)(*(vals + [0.0] * (4 - len(vals))))
 
 
 def _dims(shape) -> ctypes.Array:
@@ -145,13 +153,13 @@ def energy_parts(phi, h: float, m: float) -> tuple[float, float, float]:
     """(E2, E4, E0) of the discrete energy E_h = h^3 sum_I e."""
     phi = _field(phi)
     out = np.zeros(3)
-    _load().ora_energy_parts(_dims(phi.shape[1:]), h, m, _ptr(phi), _ptr(out))
+    _load().ora_energy_parts(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(out))
     return float(out[0]), float(out[1]), float(out[2])
 
 
 def energy(phi, h: float, m: float) -> float:
     phi = _field(phi)
-    return float(_load().ora_energy(_dims(phi.shape[1:]), h, m, _ptr(phi)))
+    return float(_load().ora_energy(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi)))
 
 
 # ------------------------------------------------------------------- gradient
@@ -168,7 +176,7 @@ def gradient(phi, h: float, m: float) -> np.ndarray:
     """g = h^-3 dE_h/dphi on the interior, zero on the frozen layers."""
     phi = _field(phi)
     g = np.empty_like(phi)
-    _load().ora_gradient(_dims(phi.shape[1:]), h, m, _ptr(phi), _ptr(g))
+    _load().ora_gradient(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(g))
     return g
 
 
@@ -192,7 +200,7 @@ def gradient_at(phi, h: float, m: float, x: int, y: int, z: int) -> np.ndarray:
     """g at one interior site, from the flux at its stencil neighbours."""
     phi = _field(phi)
     g = np.zeros(4)
-    _load().ora_gradient_at(_dims(phi.shape[1:]), h, m, _ptr(phi), int(x), int(y), int(z), _ptr(g))
+    _load().ora_gradient_at(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), int(x), int(y), int(z), _ptr(g))
     return g
 
 
@@ -201,7 +209,7 @@ def gradient_literal(phi, h: float, m: float) -> np.ndarray:
     derivatives and D_i D_j mixed derivatives; zero within 4 layers of a face."""
     phi = _field(phi)
     g = np.empty_like(phi)
-    _load().ora_gradient_literal(_dims(phi.shape[1:]), h, m, _ptr(phi), _ptr(g))
+    _load().ora_gradient_literal(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(g))
     return g
 
 
@@ -225,7 +233,7 @@ def observables(phi, h: float, m: float) -> dict:
     """{E, E2, E4, E0, B, virial, max_force}; virial = E2 - E4 + 3 E0."""
     phi = _field(phi)
     out = np.zeros(7)
-    _load().ora_observables(_dims(phi.shape[1:]), h, m, _ptr(phi), _ptr(out))
+    _load().ora_observables(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(out))
     keys = ("E", "E2", "E4", "E0", "B", "virial", "max_force")
     return {k: float(v) for k, v in zip(keys, out)}
 
@@ -235,18 +243,21 @@ def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, 
         arrest: bool = True, trace: bool = False, rule: str = "energy"):
     """Arrested Newton flow, in place on (phi, vel), until state.steps reaches
     target_steps, max|F| < tol, or a non-finite value.  rule = "energy"
-    (arrest when E_n > E_{n-1}) or "power" (arrest when h^3 sum F_n . v_n < 0).
+    (arrest when E_n > E_{n-1}), "power" (arrest when h^3 sum F_n . v_n < 0)
+    or "gradient" (the first-order gradient flow, no velocity); arrest=False
+    with an arrest rule gives the plain Newton flow.  m: the pion mass, or the
+    four potential masses (m_x, m_y, m_z, m_w).
     Returns (phi, vel, state, E_trace, arrest_trace); traces are None unless trace."""
-    if rule not in ("energy", "power"):
-        raise ValueError(f"unknown arrest rule {rule!r}")
+    if rule not in ("energy", "power", "gradient"):
+        raise ValueError(f"unknown flow rule {rule!r}")
     phi = _field(phi).copy()
     vel = _field(vel).copy()
     st = AnfState.fresh() if state is None else state
     n_max = max(int(target_steps) - int(st.steps), 0) + 1
     Et = np.full(n_max, np.nan) if trace else None
     At = np.zeros(n_max, dtype=np.int32) if trace else None
-    mode = 0 if not arrest else (1 if rule == "energy" else 2)
-    nev = _load().ora_anf(_dims(phi.shape[1:]), h, m, dt, tol, int(target_steps), mode, _ptr(phi),
+    mode = 3 if rule == "gradient" else (0 if not arrest else (1 if rule == "energy" else 2))
+    nev = _load().ora_anf(_dims(phi.shape[1:]), h, _mass(m), dt, tol, int(target_steps), mode, _ptr(phi),
                           _ptr(vel), ctypes.byref(st), _ptr(Et) if trace else None,
                           At.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if trace else None)
     if trace:

@@ -163,10 +163,28 @@ static void laplacian_at(const double *phi, const int n[3], double h, int x, int
     }
 }
 
+/* Potential density of phi0 (Sec. 6, the four potentials of the program, in this
+ * energy's normalisation, i.e. halved):
+ *   V = m_x^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
+ * mass = {m_x, m_y, m_z, m_w}; m_x is the pion mass m of Sec. 2.1. */
+static double potential(const double *mass, double p0)
+{
+    double u = 1.0 - p0;
+    return mass[0] * mass[0] * u + 0.5 * mass[1] * mass[1] * (1.0 - p0 * p0) + 0.5 * mass[2] * mass[2] * u * u +
+           0.25 * mass[3] * mass[3] * u * u * u * u;
+}
+
+/* dV/dphi0 */
+static double potential_slope(const double *mass, double p0)
+{
+    double u = 1.0 - p0;
+    return -mass[0] * mass[0] - mass[1] * mass[1] * p0 - mass[2] * mass[2] * u - mass[3] * mass[3] * u * u * u;
+}
+
 /* e2 = -1/2 phi.Lap_h phi;  G_ij = a_i . a_j, S = tr G, e4 = (S^2 - sum_ij G_ij^2)/4;
- * e0 = m^2 (1 - phi0) */
-static void density_parts(const double p[4], const double lap[4], double a[3][4], double m, double *e2, double *e4,
-                          double *e0)
+ * e0 = V(phi0) */
+static void density_parts(const double p[4], const double lap[4], double a[3][4], const double *mass, double *e2,
+                          double *e4, double *e0)
 {
     double G[3][3];
     for (int i = 0; i < 3; i++)
@@ -179,11 +197,11 @@ static void density_parts(const double p[4], const double lap[4], double a[3][4]
             GG += G[i][j] * G[i][j];
     *e2 = -0.5 * dot4(p, lap);
     *e4 = 0.25 * (S * S - GG);
-    *e0 = m * m * (1.0 - p[0]);
+    *e0 = potential(mass, p[0]);
 }
 
 /* E2, E4, E0 = h^3 sum over I of the three parts (deterministic order). */
-ORA_API void ora_energy_parts(const int n[3], double h, double m, const double *phi, double out[3])
+ORA_API void ora_energy_parts(const int n[3], double h, const double *mass, const double *phi, double out[3])
 {
     const size_t N3 = n_sites(n);
     double *plane = calloc((size_t)n[0] * 3, sizeof(double));
@@ -197,7 +215,7 @@ ORA_API void ora_energy_parts(const int n[3], double h, double m, const double *
                 for (int A = 0; A < 4; A++) p[A] = FLD(phi, A, s);
                 derivs_at(phi, n, h, x, y, z, a);
                 laplacian_at(phi, n, h, x, y, z, lap);
-                density_parts(p, lap, a, m, &e2, &e4, &e0);
+                density_parts(p, lap, a, mass, &e2, &e4, &e0);
                 s2 += e2;
                 s4 += e4;
                 s0 += e0;
@@ -219,10 +237,10 @@ ORA_API void ora_energy_parts(const int n[3], double h, double m, const double *
     out[2] = h3 * t0;
 }
 
-ORA_API double ora_energy(const int n[3], double h, double m, const double *phi)
+ORA_API double ora_energy(const int n[3], double h, const double *mass, const double *phi)
 {
     double p[3];
-    ora_energy_parts(n, h, m, phi, p);
+    ora_energy_parts(n, h, mass, phi, p);
     return p[0] + p[1] + p[2];
 }
 
@@ -272,8 +290,8 @@ ORA_API void ora_flux(const int n[3], double h, const double *phi, double *P)
  *             = -1/2 (1_I(y) Lap phi(y) + Lap(1_I phi)(y))       (Lap symmetric)
  *   E4 part:  sum over x in I and axis i of Q_i(x) da_i(x)/dphi(y) = -D_i Q_i(y)
  *             (D antisymmetric, Q = 0 outside I)
- *   E0 part:  -m^2 e_0. */
-ORA_API void ora_gradient(const int n[3], double h, double m, const double *phi, double *g)
+ *   E0 part:  dV/dphi0 e_0. */
+ORA_API void ora_gradient(const int n[3], double h, const double *mass, const double *phi, double *g)
 {
     const size_t N3 = n_sites(n);
     double *P = malloc(12 * N3 * sizeof(double));
@@ -300,7 +318,7 @@ ORA_API void ora_gradient(const int n[3], double h, double m, const double *phi,
                     double div = 0.0;
                     for (int i = 0; i < 3; i++)
                         div += d1(P + ((size_t)i * 4 + A) * N3, n, i, x, y, z, h);
-                    FLD(g, A, s) = -0.5 * (lap[A] + lapI[A]) - div - (A == 0 ? m * m : 0.0);
+                    FLD(g, A, s) = -0.5 * (lap[A] + lapI[A]) - div + (A == 0 ? potential_slope(mass, FLD(phi, 0, s)) : 0.0);
                 }
             }
     free(P);
@@ -344,7 +362,7 @@ ORA_API double ora_project(const int n[3], const double *phi, const double *g, d
 /* The same gradient at one interior site, computed locally from the
  * definition (quartic flux at the twelve stencil neighbours, Laplacians of
  * phi and of 1_I phi).  Used to check single outputs of large lattices. */
-ORA_API void ora_gradient_at(const int n[3], double h, double m, const double *phi, int x, int y, int z,
+ORA_API void ora_gradient_at(const int n[3], double h, const double *mass, const double *phi, int x, int y, int z,
                              double g[4])
 {
     const size_t N3 = n_sites(n);
@@ -370,7 +388,7 @@ ORA_API void ora_gradient_at(const int n[3], double h, double m, const double *p
             }
         }
     for (int A = 0; A < 4; A++)
-        g[A] = -0.5 * (lap[A] + lapI[A]) - div[A] - (A == 0 ? m * m : 0.0);
+        g[A] = -0.5 * (lap[A] + lapI[A]) - div[A] + (A == 0 ? potential_slope(mass, FLD(phi, 0, s0)) : 0.0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -438,14 +456,14 @@ ORA_API double ora_baryon(const int n[3], double h, const double *phi)
  * Derrick scaling argument, up to the sign and factor of the stress trace),
  * and the largest tangential gradient norm.
  * out = {E, E2, E4, E0, B, virial, max_force}. */
-ORA_API void ora_observables(const int n[3], double h, double m, const double *phi, double out[7])
+ORA_API void ora_observables(const int n[3], double h, const double *mass, const double *phi, double out[7])
 {
     const size_t N3 = n_sites(n);
     double p[3];
-    ora_energy_parts(n, h, m, phi, p);
+    ora_energy_parts(n, h, mass, phi, p);
     double *g = malloc(4 * N3 * sizeof(double));
     double *gT = malloc(4 * N3 * sizeof(double));
-    ora_gradient(n, h, m, phi, g);
+    ora_gradient(n, h, mass, phi, g);
     double r = ora_project(n, phi, g, gT);
     free(g);
     free(gT);
@@ -528,12 +546,14 @@ ORA_API double ora_power(const int n[3], double h, const double *gT, const doubl
  *                            or if h^3 sum F_n . v_n < 0    (arrest = 2, power rule);
  *             stop if max|F_n| < tol;
  *             v_{n+1} = v_n + dt F_n; phi_{n+1} = normalise(phi_n + dt v_{n+1}).
- * arrest = 0 gives the plain Newton flow (no resets).
+ * arrest = 0 gives the plain Newton flow (no resets); arrest = 3 the gradient
+ * flow (Sec. 6, the program's flow modes): phi_{n+1} = normalise(phi_n + dt F_n),
+ * the velocity stays zero.
  * E_trace / arrest_trace (nullable) receive E_n and the reset flag for each
  * evaluated step, indexed from the step count on entry.
  * Returns the number of evaluated steps.
  */
-ORA_API int64_t ora_anf(const int n[3], double h, double m, double dt, double tol, int64_t target_steps, int arrest,
+ORA_API int64_t ora_anf(const int n[3], double h, const double *mass, double dt, double tol, int64_t target_steps, int arrest,
                         double *phi, double *vel, ora_anf_state *st, double *E_trace, int32_t *arrest_trace)
 {
     const size_t N3 = n_sites(n);
@@ -541,8 +561,8 @@ ORA_API int64_t ora_anf(const int n[3], double h, double m, double dt, double to
     double *gT = malloc(4 * N3 * sizeof(double));
     int64_t evaluated = 0;
     while (st->steps < target_steps) {
-        double E = ora_energy(n, h, m, phi);
-        ora_gradient(n, h, m, phi, g);
+        double E = ora_energy(n, h, mass, phi);
+        ora_gradient(n, h, mass, phi, g);
         double r = ora_project(n, phi, g, gT);
         int reset = 0;
         if (arrest == 1) reset = E > st->E_prev;
@@ -575,7 +595,20 @@ ORA_API int64_t ora_anf(const int n[3], double h, double m, double dt, double to
                         v[A] = FLD(vel, A, s);
                         F[A] = -FLD(gT, A, s);
                     }
-                    kick_drift(p, v, F, dt);
+                    if (arrest == 3) {
+                        double q[4], nrm2 = 0.0;
+                        for (int A = 0; A < 4; A++) {
+                            q[A] = p[A] + dt * F[A];
+                            nrm2 += q[A] * q[A];
+                        }
+                        double nr = sqrt(nrm2);
+                        for (int A = 0; A < 4; A++) {
+                            p[A] = q[A] / nr;
+                            v[A] = 0.0;
+                        }
+                    } else {
+                        kick_drift(p, v, F, dt);
+                    }
                     for (int A = 0; A < 4; A++) {
                         FLD(phi, A, s) = p[A];
                         FLD(vel, A, s) = v[A];
@@ -778,7 +811,7 @@ ORA_API void ora_random_constituents(uint64_t seed, int32_t B, double radius, do
 /* it agrees with the exact discrete gradient to O(h^4) on smooth fields.  */
 /* ------------------------------------------------------------------------ */
 
-ORA_API void ora_gradient_literal(const int n[3], double h, double m, const double *phi, double *g)
+ORA_API void ora_gradient_literal(const int n[3], double h, const double *mass, const double *phi, double *g)
 {
     const size_t N3 = n_sites(n);
     double *a = malloc(12 * N3 * sizeof(double));
@@ -821,7 +854,7 @@ ORA_API void ora_gradient_literal(const int n[3], double h, double m, const doub
                         t += d[i][A] * c;
                         for (int j = 0; j < 3; j++) t -= dd[i][j][A] * dot4(d[i], d[j]);
                     }
-                    g[(size_t)A * N3 + s] = -t - (A == 0 ? m * m : 0.0);
+                    g[(size_t)A * N3 + s] = -t + (A == 0 ? potential_slope(mass, phi[s]) : 0.0);
                 }
             }
     free(a);

@@ -153,6 +153,56 @@ def test_gradient_is_derivative_of_discrete_energy_bruteforce():
     assert np.all(g[:, ~I] == 0.0)
 
 
+def test_gradient_bruteforce_with_all_potentials():
+    """The same brute-force check with all four potentials switched on
+    (m_x, m_y, m_z, m_w): pins dV/dphi0 against V itself."""
+    n, h = 7, 0.31
+    mass = (0.9, 0.7, 1.3, 0.6)
+    phi = random_unit_field((n, n, n), 12, 0.8)
+    g = oracle.gradient(phi, h, mass)
+    I = interior_mask((n, n, n))
+    worst = 0.0
+    for x, y, z in zip(*np.nonzero(I)):
+        def fun(e, x=x, y=y, z=z):
+            p = phi.copy()
+            p[0, x, y, z] += e
+            return oracle.energy(p, h, mass)
+        fd = _richardson_derivative(fun, 1e-3)
+        worst = max(worst, abs(fd - h ** 3 * g[0, x, y, z]) / (abs(fd) + 1e-3))
+    assert worst < 1e-8
+
+
+def test_potentials_on_a_uniform_field():
+    """A field that is the same at every site (frozen layers included) has no
+    derivatives: E2 = E4 = 0 and E0 = h^3 (n-4)^3 V(phi0), with V the sum of the
+    program's four potentials (Sec. 6: 2 m_x^2 (1-phi0), m_y^2 (1-phi0^2),
+    m_z^2 (1-phi0)^2, m_w^2 (1-phi0)^4 / 2), halved to this energy's
+    normalisation; deep inside, the gradient is dV/dphi0 on the phi0 component
+    (checked against a central difference of V)."""
+    n, h = 12, 0.2
+    mass = (0.8, 1.1, 0.6, 1.7)
+    alpha = 1.1
+    phi = np.zeros((4, n, n, n))
+    phi[0] = math.cos(alpha)
+    phi[1] = math.sin(alpha) * 0.6
+    phi[3] = math.sin(alpha) * 0.8
+
+    def V(c):
+        mx, my, mz, mw = mass
+        return 0.5 * (2 * mx ** 2 * (1 - c) + my ** 2 * (1 - c * c) + mz ** 2 * (1 - c) ** 2
+                      + 0.5 * mw ** 2 * (1 - c) ** 4)
+
+    e2, e4, e0 = oracle.energy_parts(phi, h, mass)
+    assert abs(e2) < 1e-13 and abs(e4) < 1e-13
+    assert e0 == pytest.approx(h ** 3 * (n - 4) ** 3 * V(math.cos(alpha)), rel=1e-13)
+    g = oracle.gradient(phi, h, mass)
+    c, d = math.cos(alpha), 1e-4
+    dV = (8 * (V(c + d) - V(c - d)) - (V(c + 2 * d) - V(c - 2 * d))) / (12 * d)
+    mid = n // 2
+    assert g[0, mid, mid, mid] == pytest.approx(dV, rel=1e-9)
+    assert np.abs(g[1:, mid, mid, mid]).max() < 1e-12
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_gradient_directional_and_tangent(seed):
     """Random directions on a 10^3 lattice: dE/dt = h^3 sum g.xi; for tangent
@@ -407,6 +457,44 @@ def test_power_rule_trace_and_same_minimum():
         assert st.converged == 1
         res[rule] = st.E
     assert res["power"] == pytest.approx(res["energy"], rel=1e-12)
+
+
+def test_gradient_flow_is_first_order_descent():
+    """Gradient flow (Sec. 6, the program's third flow mode): one step
+    phi' = normalise(phi + dt F) lowers the energy by dt h^3 sum |F|^2 to first
+    order in dt (the ratio tends to 1 linearly), and the velocity stays zero."""
+    n, h, m = 16, 0.25, 1.0
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog(prof_lambda=0.8)])
+    E0 = oracle.energy(phi, h, m)
+    gT, _ = oracle.project(phi, oracle.gradient(phi, h, m))
+    rate = oracle.power(gT, -gT, h)  # h^3 sum |F|^2
+    dev = []
+    for dt in (2e-3, 1e-3):
+        p, v, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, dt, 0.0, 1, rule="gradient")
+        assert np.all(v == 0.0)
+        dev.append(abs((oracle.energy(p, h, m) - E0) / (-dt * rate) - 1.0))
+    assert dev[1] < 0.6 * dev[0] and dev[1] < 0.05
+
+
+def test_gradient_flow_descends_to_the_same_minimum():
+    """Gradient flow started from a perturbation of the arrested-Newton-flow
+    minimum of the hedgehog lowers the energy at every step (dt below the
+    stability edge) and removes all but 1e-4 of the energy excess in 1500 steps:
+    both flows share their minimum."""
+    n, h, m = 24, 0.2, 1.0
+    phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+    ps, _, sa, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, 0.02, 1e-8, 20000)
+    assert sa.converged == 1
+    rng = np.random.default_rng(5)
+    inner = interior_mask(ps.shape[1:])
+    pert = ps.copy()
+    pert[:, inner] += 2e-3 * rng.standard_normal((4, int(inner.sum())))
+    pert /= np.sqrt((pert ** 2).sum(0, keepdims=True))
+    excess0 = oracle.energy(pert, h, m) - sa.E
+    _, v, st, Et, At = oracle.anf(pert, np.zeros_like(pert), h, m, 2e-4, 0.0, 1500, rule="gradient", trace=True)
+    assert st.arrests == 0 and np.all(v == 0.0)
+    assert np.all(np.diff(Et) <= 0.0)
+    assert 0.0 <= Et[-1] - sa.E < 1e-4 * excess0
 
 
 def test_resume_equals_uninterrupted():
