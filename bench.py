@@ -86,7 +86,7 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None):
     model = skyr.Model(w["m"])
     # tolerance 0: every call runs exactly its steps
     rule = "power" if prec_name == "f32" else "energy"
-    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, skyr.arrest_rule(rule))
+    flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, skyr.flow_mode(rule))
     # tile shape for this lattice and precision: measured once, before the timed region
     if tile is None:
         tile = skyr.autotune_cached(lat, prec, model, flow, phi, alt, vel, work)
@@ -167,7 +167,7 @@ def _job_buffers(skyr, torch, d):
     skyr.init_field(lat, prec, spec, phi)
     alt, vel = skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
     work = skyr.new_workspace(lat, prec, dev)
-    flow = skyr.Flow(d["dt"], 0.0, 10 ** 12, 16, skyr.arrest_rule(d.get("arrest", "energy")))
+    flow = skyr.Flow(d["dt"], 0.0, 10 ** 12, 16, skyr.flow_mode(d.get("flow", "energy")))
     return lat, prec, phi, alt, vel, work, flow
 
 

@@ -70,40 +70,53 @@ typedef struct {
     double h;
 } skyr_lattice;
 
-/* Rescaled pion mass m (Sec. 2, m = 2 m_pi / (F_pi e)). */
+/* Potential masses (Sec. 2.1 and the program's four potentials, Sec. 6), in this
+ * library's energy normalisation (one half of the printed density):
+ *   V(phi0) = m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
+ * m is the rescaled pion mass (m = 2 m_pi / (F_pi e)); m_y, m_z, m_w are the modified
+ * pion mass, loosely bound and lightly bound potential masses (0 = absent). */
 typedef struct {
     double m;
+    double m_y;
+    double m_z;
+    double m_w;
 } skyr_model;
 
-/* When the flow resets the velocity (Sec. 3, arrest).
- *   SKYR_ARREST_ENERGY  the paper's rule: arrest at step k when E_k > E_{k-1}
- *                       (strict; E_{-1} = +inf).
- *   SKYR_ARREST_POWER   its instantaneous form: arrest at step k when the power
- *                       P_k = h^3 sum_I F_k . v_k is negative (dE/dt = -F . v, so
- *                       the energy has started to rise).  P needs no difference of
- *                       two total energies; in single precision the rounding noise
- *                       of E_k exceeds the per-step energy decrease well before the
- *                       force reaches its floor, and the energy rule then fires on
- *                       noise.  Recommended with SKYR_F32_BULK.
- * Either way an arrest keeps phi_k and restarts from it with v_k = 0. */
+/* Flow mode (Sec. 3; the program's flow modes, Sec. 6).
+ *   SKYR_ARREST_ENERGY  arrested Newton flow with the paper's rule: arrest at step k
+ *                       when E_k > E_{k-1} (strict; E_{-1} = +inf).
+ *   SKYR_ARREST_POWER   arrested Newton flow, arresting when the power
+ *                       P_k = h^3 sum_I F_k . v_k is negative (dE/dt = -F . v: the
+ *                       instantaneous form of "the energy starts to rise").  P needs
+ *                       no difference of two total energies; in single precision the
+ *                       rounding noise of E_k exceeds the per-step energy decrease
+ *                       well before the force reaches its floor, and the energy rule
+ *                       then fires on noise.  Recommended with SKYR_F32_BULK.
+ *   SKYR_NEWTON_FLOW    Newton flow: the same kick-drift steps, never arrested (it
+ *                       does not converge to a minimum by itself).
+ *   SKYR_GRADIENT_FLOW  first-order gradient flow phi_{k+1} = normalise(phi_k + dt F_k);
+ *                       the velocity stays zero.
+ * An arrest keeps phi_k and restarts from it with v_k = 0. */
 typedef enum {
     SKYR_ARREST_ENERGY = 0,
-    SKYR_ARREST_POWER = 1
-} skyr_arrest_rule;
+    SKYR_ARREST_POWER = 1,
+    SKYR_NEWTON_FLOW = 2,
+    SKYR_GRADIENT_FLOW = 3
+} skyr_flow_mode;
 
-/* Arrested Newton flow controls (Sec. 3).
- *   dt             fictitious time step (kick-drift step)
+/* Flow controls (Sec. 3).
+ *   dt             fictitious time step (kick-drift step; gradient flow: phi += dt F)
  *   tol            stop when max over I of |F| < tol, F the projected force
  *   max_steps      total cap on accepted steps across calls
  *   renorm64_every SKYR_F32_BULK only: every this many steps the renormalisation
  *                  phi <- phi/|phi| is done in double (0 = never; default 16)
- *   arrest         a skyr_arrest_rule (0 = the paper's energy rule) */
+ *   mode           a skyr_flow_mode (0 = arrested Newton flow, the paper's rule) */
 typedef struct {
     double dt;
     double tol;
     int64_t max_steps;
     int32_t renorm64_every;
-    int32_t arrest;
+    int32_t mode;
 } skyr_flow;
 
 /* Initial data (Sec. 4). */

@@ -310,7 +310,8 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
         return;
     }
     bool arrest = false;
-    if (!ctl->redo && (ctl->arrest_rule == SKYR_ARREST_POWER ? ctl->P < 0.0 : E > ctl->E_prev)) {
+    if (!ctl->redo && ((ctl->flow_mode == SKYR_ARREST_POWER && ctl->P < 0.0) ||
+                       (ctl->flow_mode == SKYR_ARREST_ENERGY && E > ctl->E_prev))) {
         arrest = true;
         ctl->arrests += 1;
     }
@@ -346,13 +347,28 @@ __global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, int nj
 }
 
 // ------------------------------------------------------------- launches
+// the kernel variant with the extra potentials and the gradient flow is used only
+// by models and flows that need it
+static bool needs_ext(const SweepArgs& a)
+{
+    return a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.gradient_flow != 0;
+}
+
 template <typename T, int NW, int LW, int RY>
 static hipError_t launch_shape(int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
 {
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP>), dim3(L.blocks()), dim3(NW * 64), 0, s, args);
-    else
-        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD>), dim3(L.blocks()), dim3(NW * 64), 0, s, args);
+    const dim3 grid(L.blocks()), block(NW * 64);
+    if (needs_ext(args)) {
+        if (mode == MODE_STEP)
+            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP, true>), grid, block, 0, s, args);
+        else
+            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD, true>), grid, block, 0, s, args);
+    } else {
+        if (mode == MODE_STEP)
+            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP, false>), grid, block, 0, s, args);
+        else
+            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD, false>), grid, block, 0, s, args);
+    }
     return hipGetLastError();
 }
 
@@ -377,15 +393,20 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
 
 // The batched sweep uses the first compiled shape of each precision.
 template <typename T, int NW, int LW, int RY>
-static hipError_t launch_batch(int blocks, const SweepArgs* jobs, const int* map, const int* first, const int* count,
-                               hipStream_t s)
+static hipError_t launch_batch(bool ext, int blocks, const SweepArgs* jobs, const int* map, const int* first,
+                               const int* count, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map, first, count);
+    if (ext)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, true>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
+                           first, count);
+    else
+        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, false>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
+                           first, count);
     return hipGetLastError();
 }
 
-static hipError_t batch_sweep(skyr_precision prec, int blocks, const SweepArgs* jobs, const int* map, const int* first,
-                              const int* count, hipStream_t s)
+static hipError_t batch_sweep(skyr_precision prec, bool ext, int blocks, const SweepArgs* jobs, const int* map,
+                              const int* first, const int* count, hipStream_t s)
 {
     // shape 0 of each list
     if (prec == SKYR_F64) {
@@ -393,7 +414,7 @@ static hipError_t batch_sweep(skyr_precision prec, int blocks, const SweepArgs* 
         int v = 0;
 #define SKYR_B64(a, b, c)                                                                                    \
     if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
-        return launch_batch<double, a, b, c>(blocks, jobs, map, first, count, s);
+        return launch_batch<double, a, b, c>(ext, blocks, jobs, map, first, count, s);
         SKYR_SHAPES_F64(SKYR_B64)
 #undef SKYR_B64
     } else {
@@ -401,14 +422,14 @@ static hipError_t batch_sweep(skyr_precision prec, int blocks, const SweepArgs* 
         int v = 0;
 #define SKYR_B32(a, b, c)                                                                                    \
     if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
-        return launch_batch<float, a, b, c>(blocks, jobs, map, first, count, s);
+        return launch_batch<float, a, b, c>(ext, blocks, jobs, map, first, count, s);
         SKYR_SHAPES_F32(SKYR_B32)
 #undef SKYR_B32
     }
     return hipErrorInvalidValue;
 }
 
-static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, double m, double dt)
+static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_model* model, double dt)
 {
     SweepArgs a{};
     a.n0 = lat->n[0];
@@ -418,7 +439,10 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, double m, d
     a.tiles_y = L.tiles_y;
     a.xchunk = L.xchunk;
     a.h = lat->h;
-    a.m = m;
+    a.m = model->m;
+    a.m_y = model->m_y;
+    a.m_z = model->m_z;
+    a.m_w = model->m_w;
     a.dt = dt;
     return a;
 }
@@ -631,7 +655,7 @@ static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, co
                                 void* grad, int projected, int baryon, double obs_out[7], void* work, hipStream_t s)
 {
     const Launch L = plan(lat, prec);
-    SweepArgs a = make_args(lat, L, model->m, 0.0);
+    SweepArgs a = make_args(lat, L, model, 0.0);
     a.phi0 = phi;
     a.grad = grad;
     a.projected = projected;
@@ -656,7 +680,9 @@ static skyr_status check_common(const skyr_lattice* lat, skyr_precision prec, co
     skyr_status st = check_lattice(lat, prec);
     if (st != SKYR_OK) return st;
     if (!model || !phi || !work) return fail(SKYR_E_INVAL, "model, phi and work must be non-null");
-    if (!std::isfinite(model->m)) return fail(SKYR_E_INVAL, "mass must be finite");
+    if (!std::isfinite(model->m) || !std::isfinite(model->m_y) || !std::isfinite(model->m_z) ||
+        !std::isfinite(model->m_w))
+        return fail(SKYR_E_INVAL, "masses must be finite");
     if (!aligned256(work)) return fail(SKYR_E_INVAL, "workspace must be 256-byte aligned");
     return SKYR_OK;
 }
@@ -711,8 +737,7 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (!(flow->tol >= 0.0)) return fail(SKYR_E_INVAL, "tol must be >= 0");
     if (nsteps < 0 || flow->max_steps < 0 || flow->renorm64_every < 0) return fail(SKYR_E_INVAL, "negative step count");
-    if (flow->arrest != SKYR_ARREST_ENERGY && flow->arrest != SKYR_ARREST_POWER)
-        return fail(SKYR_E_INVAL, "unknown arrest rule");
+    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     hipStream_t s = (hipStream_t)stream;
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
@@ -721,7 +746,8 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     const Launch L = plan(lat, prec);
     char* w = (char*)work;
     Ctl* ctl = (Ctl*)w;
-    SweepArgs a = make_args(lat, L, model->m, flow->dt);
+    SweepArgs a = make_args(lat, L, model, flow->dt);
+    a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
     a.phi1 = phi_alt;
     a.vel = vel;
@@ -737,7 +763,7 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     h.redo_sweeps = st->redo_sweeps;
     h.sweeps = st->sweeps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
-    h.arrest_rule = flow->arrest;
+    h.flow_mode = flow->mode;
     h.nblocks = L.blocks();
     h.E_prev = st->E_prev;
     h.E = st->E;
@@ -883,7 +909,8 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     }
     auto time_one = [&](Cand& cd, int warm) -> hipError_t {
         const Launch L = plan_with(lat, prec, cd.v, cd.xc);
-        SweepArgs a = make_args(lat, L, model->m, flow->dt);
+        SweepArgs a = make_args(lat, L, model, flow->dt);
+        a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
         a.phi0 = phi;
         a.phi1 = phi_alt;
         a.vel = vel;
@@ -971,6 +998,7 @@ struct skyr_batch {
     int* d_map[2] = {nullptr, nullptr};  // block -> job, per precision
     int map_cap[2] = {0, 0};
     int grid[2] = {0, 0};
+    bool ext[2] = {false, false};  // some job of the precision needs the extended kernel variant
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -992,10 +1020,12 @@ static void batch_release_graph(skyr_batch* b)
 static skyr_status batch_rebuild(skyr_batch* b)
 {
     std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[2];
+    b->ext[0] = b->ext[1] = false;
     for (int j = 0; j < b->max_jobs; ++j) {
         const auto& J = b->jobs[j];
         if (!J.active) continue;
         const int p = J.prec == SKYR_F64 ? 0 : 1;
+        b->ext[p] = b->ext[p] || needs_ext(b->args[j]);
         first[j] = (int)map[p].size();
         count[j] = J.L.blocks();
         map[p].insert(map[p].end(), count[j], j);
@@ -1027,9 +1057,11 @@ static skyr_status batch_capture(skyr_batch* b, int sweeps)
     hipError_t e = hipSuccess;
     for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
         if (b->grid[0] && e == hipSuccess)
-            e = batch_sweep(SKYR_F64, b->grid[0], b->d_args, b->d_map[0], b->d_first, b->d_count, b->capture);
+            e = batch_sweep(SKYR_F64, b->ext[0], b->grid[0], b->d_args, b->d_map[0], b->d_first, b->d_count,
+                            b->capture);
         if (b->grid[1] && e == hipSuccess)
-            e = batch_sweep(SKYR_F32_BULK, b->grid[1], b->d_args, b->d_map[1], b->d_first, b->d_count, b->capture);
+            e = batch_sweep(SKYR_F32_BULK, b->ext[1], b->grid[1], b->d_args, b->d_map[1], b->d_first, b->d_count,
+                            b->capture);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->max_jobs), dim3(256), 0, b->capture, b->d_args,
                                b->max_jobs);
@@ -1096,8 +1128,7 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
         return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
-    if (flow->arrest != SKYR_ARREST_ENERGY && flow->arrest != SKYR_ARREST_POWER)
-        return fail(SKYR_E_INVAL, "unknown arrest rule");
+    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     int j = -1;
     for (int k = 0; k < b->max_jobs; ++k)
@@ -1109,7 +1140,8 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     // the batched sweep uses shape 0 of the precision; the slab length follows the lattice's setting
     Launch L = plan(lat, prec);
     L = plan_with(lat, prec, 0, L.xchunk);
-    SweepArgs a = make_args(lat, L, model->m, flow->dt);
+    SweepArgs a = make_args(lat, L, model, flow->dt);
+    a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
     a.phi1 = phi_alt;
     a.vel = vel;
@@ -1118,7 +1150,7 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     Ctl h{};
     h.target = flow->max_steps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
-    h.arrest_rule = flow->arrest;
+    h.flow_mode = flow->mode;
     h.nblocks = L.blocks();
     h.E_prev = INFINITY;
     h.E = NAN;

@@ -44,7 +44,7 @@ struct Ctl {
     int64_t sweeps;
     int32_t renorm64_every;
     int32_t nblocks;      // number of partial-sum blocks of the sweep
-    int32_t arrest_rule;  // skyr_arrest_rule
+    int32_t flow_mode;    // skyr_flow_mode
     int32_t pad_i;
     double E_prev;
     double E;
@@ -71,7 +71,9 @@ struct SweepArgs {
     int xchunk;            // planes per slab
     int projected;     // MODE_GRAD: write g - (g.phi) phi instead of g
     int baryon;        // accumulate the baryon density
-    double h, m, dt;
+    double h, dt;
+    double m, m_y, m_z, m_w;  // potential masses
+    int gradient_flow;        // MODE_STEP: phi += dt F, no velocity
 };
 
 // stencil coefficients (Sec. 3)
@@ -173,7 +175,9 @@ template <typename T, int NW, int LW, int RY> struct Tile {
     static_assert(THREADS >= NH, "every halo site of a plane has its own loading thread");
 };
 
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false> struct Sweeper {
+// EXT: the kernel variant with the extra potentials (m_y, m_z, m_w) and the gradient
+// flow; the plain variant has the pion-mass potential and the kick-drift update only.
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, bool EXT = false> struct Sweeper {
     using TL = Tile<T, NW, LW, RY>;
     static constexpr int PY = TL::PY;
     static constexpr int R0 = TL::R0;
@@ -210,7 +214,10 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
     int yk[RY];
     unsigned offk[RY];  // byte offsets of the flux positions within a plane
     bool row_out[RY], yz_in[RY], y_near[RY], z_near;
-    T c1h, c2h, d1h, d2h, hd1h, hd2h, dt, m2;  // stencil weights with 1/h, 1/h^2 (and 1/2) folded in
+    T c1h, c2h, d1h, d2h, hd1h, hd2h, dt;  // stencil weights with 1/h, 1/h^2 (and 1/2) folded in
+    T m2, my2, mz2, mw2;                   // squared potential masses
+    bool more_pot;                         // any of m_y, m_z, m_w nonzero
+    bool grad_flow;                        // gradient flow: phi += dt F, no velocity
 
     // registers carried along the march
     T ring[5][4][RY];  // phi at planes j-2 .. j+2 (slot = plane mod 5 relative to the start)
@@ -225,6 +232,28 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
     T pf2 = T(0);
 
     __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
+
+    // potential density V(phi0) and dV/dphi0: m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2
+    // + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4 (the program's four potentials,
+    // Sec. 6, halved to this energy's normalisation)
+    __device__ __forceinline__ T potential(T p0) const
+    {
+        const T u = T(1) - p0;
+        T v = m2 * u;
+        if constexpr (EXT) {
+            if (more_pot) v += T(0.5) * my2 * (T(1) - p0 * p0) + T(0.5) * mz2 * u * u + T(0.25) * mw2 * (u * u) * (u * u);
+        }
+        return v;
+    }
+    __device__ __forceinline__ T potential_slope(T p0) const
+    {
+        const T u = T(1) - p0;
+        T d = -m2;
+        if constexpr (EXT) {
+            if (more_pot) d -= my2 * p0 + mz2 * u + mw2 * u * u * u;
+        }
+        return d;
+    }
 
     __device__ __forceinline__ void load_plane(int x, T (&dst)[4][RY]) const
     {
@@ -350,7 +379,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
                 if (row_out[k] && j_out) {
                     const T e2 = T(-0.5) * cl;
                     const T e4 = T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
-                    const T e0 = m2 * (T(1) - c[0]);
+                    const T e0 = potential(c[0]);
                     if constexpr (MODE == MODE_STEP) {
                         pe2 += (double)(e2 + e4 + e0);  // the flow needs the total energy only
                     } else {
@@ -391,7 +420,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
                         g[A] = acc[S_M2][A][k];
                         p[A] = ring[S_M2][A][k];
                     }
-                    g[0] -= m2;
+                    g[0] += potential_slope(p[0]);
                     const T gp = dot4(g, p);
 #pragma unroll
                     for (int A = 0; A < 4; ++A) f[A] = gp * p[A] - g[A];  // F = -(g - (g.phi) phi)
@@ -402,8 +431,13 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
                         T v[4], q[4], pn[4];
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
-                            v[A] = vcur[A][k] + dt * f[A];
-                            q[A] = p[A] + dt * v[A];
+                            if constexpr (EXT) {
+                                v[A] = grad_flow ? T(0) : vcur[A][k] + dt * f[A];
+                                q[A] = p[A] + dt * (grad_flow ? f[A] : v[A]);
+                            } else {
+                                v[A] = vcur[A][k] + dt * f[A];
+                                q[A] = p[A] + dt * v[A];
+                            }
                         }
                         if (renorm64) {
                             const double s2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
@@ -458,11 +492,11 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
 // One block's share of one field: logical block b of nb blocks covering the
 // field's work items.  Used by the single-field and the batched kernels
 // (FROM_TABLE: the arguments were read from the batch's job table).
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false>
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, bool EXT = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
-                                            typename Sweeper<T, NW, LW, RY, MODE, FROM_TABLE>::Smem& smem)
+                                            typename Sweeper<T, NW, LW, RY, MODE, FROM_TABLE, EXT>::Smem& smem)
 {
-    using SW = Sweeper<T, NW, LW, RY, MODE, FROM_TABLE>;
+    using SW = Sweeper<T, NW, LW, RY, MODE, FROM_TABLE, EXT>;
     using TL = typename SW::TL;
     constexpr int PY = TL::PY;
     constexpr int R0 = TL::R0;
@@ -516,6 +550,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     sw.hd2h = T(0.5 * Coef<double>::d2 / (a.h * a.h));
     sw.dt = T(a.dt);
     sw.m2 = T(a.m * a.m);
+    sw.my2 = T(a.m_y * a.m_y);
+    sw.mz2 = T(a.m_z * a.m_z);
+    sw.mw2 = T(a.m_w * a.m_w);
+    sw.more_pot = a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0;
+    sw.grad_flow = MODE == MODE_STEP && a.gradient_flow != 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -651,28 +690,28 @@ __device__ __forceinline__ int xcd_logical_block(int i, int n)
     return xcd * q8 + min(xcd, r8) + i / 8;
 }
 
-template <typename T, int NW, int LW, int RY, int MODE>
+template <typename T, int NW, int LW, int RY, int MODE, bool EXT>
 __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 {
-    __shared__ typename Sweeper<T, NW, LW, RY, MODE>::Smem smem;
+    __shared__ typename Sweeper<T, NW, LW, RY, MODE, false, EXT>::Smem smem;
     const int nb = gridDim.x;
-    sweep_block<T, NW, LW, RY, MODE>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
+    sweep_block<T, NW, LW, RY, MODE, false, EXT>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
 }
 
 // Many fields in one launch: block i (after the XCD remap) belongs to field
 // job_of_block[i] and is its block (i - first_block[job]); every field's blocks
 // and partial sums are exactly those of a launch of that field alone.
-template <typename T, int NW, int LW, int RY>
+template <typename T, int NW, int LW, int RY, bool EXT>
 __global__ __launch_bounds__(NW * 64) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
                                                               const int* __restrict__ job_of_block,
                                                               const int* __restrict__ first_block,
                                                               const int* __restrict__ blocks_of_job)
 {
-    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP, true>::Smem smem;
+    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP, true, EXT>::Smem smem;
     const int i = xcd_logical_block(blockIdx.x, gridDim.x);
     const int j = job_of_block[i];
     const SweepArgs a = jobs[j];
-    sweep_block<T, NW, LW, RY, MODE_STEP, true>(a, i - first_block[j], blocks_of_job[j], smem);
+    sweep_block<T, NW, LW, RY, MODE_STEP, true, EXT>(a, i - first_block[j], blocks_of_job[j], smem);
 }
 
 }  // namespace skyr

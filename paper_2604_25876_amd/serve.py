@@ -87,7 +87,7 @@ class GpuBackend:
         alt, vel = s.new_field(lat, prec, self.device), s.new_field(lat, prec, self.device)
         work = s.new_workspace(lat, prec, self.device)
         flow = s.Flow(desc["dt"], desc["tol"], int(desc["steps"]), int(desc.get("renorm64_every", 16)),
-                      s.arrest_rule(desc.get("arrest", "energy")))
+                      s.flow_mode(desc.get("flow", "energy")))
         slot = self.batch.add(lat, prec, s.Model(desc["m"]), flow, phi, alt, vel, work)
         self.bufs[slot] = (lat, prec, desc, phi, alt, vel, work)
         return slot

@@ -17,14 +17,16 @@ LIB_PATH = _PKG / "libskyr.so"
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, -1, -2, -3, -4, -5
 F64, F32_BULK = 0, 1
-ARREST_ENERGY, ARREST_POWER = 0, 1
+ARREST_ENERGY, ARREST_POWER, NEWTON_FLOW, GRADIENT_FLOW = 0, 1, 2, 3
+_FLOW_MODES = {"energy": ARREST_ENERGY, "power": ARREST_POWER, "newton": NEWTON_FLOW, "gradient": GRADIENT_FLOW}
 
 
-def arrest_rule(rule) -> int:
-    """skyr_arrest_rule value of "energy" / "power" (or of the value itself)."""
-    if isinstance(rule, str):
-        return {"energy": ARREST_ENERGY, "power": ARREST_POWER}[rule]
-    return int(rule)
+def flow_mode(mode) -> int:
+    """skyr_flow_mode value of "energy" / "power" (arrested Newton flow with that
+    arrest rule), "newton" or "gradient" (or of the value itself)."""
+    if isinstance(mode, str):
+        return _FLOW_MODES[mode]
+    return int(mode)
 INIT_HEDGEHOG, INIT_RATIONAL_MAP, INIT_PRODUCT, INIT_RANDOM_PRODUCT = 0, 1, 2, 3
 
 
@@ -47,12 +49,14 @@ class Lattice(ctypes.Structure):
 
 
 class Model(ctypes.Structure):
-    _fields_ = [("m", ctypes.c_double)]
+    """Potential masses: the pion mass m and the optional m_y, m_z, m_w."""
+    _fields_ = [("m", ctypes.c_double), ("m_y", ctypes.c_double), ("m_z", ctypes.c_double),
+                ("m_w", ctypes.c_double)]
 
 
 class Flow(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
-                ("renorm64_every", ctypes.c_int32), ("arrest", ctypes.c_int32)]
+                ("renorm64_every", ctypes.c_int32), ("mode", ctypes.c_int32)]
 
 
 class Constituent(ctypes.Structure):

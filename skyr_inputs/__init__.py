@@ -88,7 +88,7 @@ def batch_jobs(master_seed: int = 4, count: int = 64) -> list[dict]:
         m = float(g.randint(0, 1))
         seed = g.next()
         jobs.append(dict(name=f"batch-{master_seed}-{j}", n=n, h=0.15, m=m, dt=0.015, tol=f32_tolerance(1e-4, 0.15),
-                         steps=20000, precision="f32", arrest="power",
+                         steps=20000, precision="f32", flow="power",
                          init={"kind": "random_product", "B": B, "seed": seed, "radius": 3.0, "prof_lambda": 1.0}))
     return jobs
 
@@ -111,7 +111,7 @@ def served_stream(master_seed: int = 5, count: int = 256, rate: float = 1.0) -> 
         seed = g.next()
         jobs.append(dict(name=f"serve-{master_seed}-{j}", arrival=t, n=n, h=h, m=1.0, dt=0.1 * h,
                          tol=f32_tolerance(1e-4, h) if prec == "f32" else 1e-4, steps=20000, precision=prec,
-                         arrest="power" if prec == "f32" else "energy",
+                         flow="power" if prec == "f32" else "energy",
                          init={"kind": "random_product", "B": B, "seed": seed, "radius": 3.0, "prof_lambda": 1.0}))
     return jobs
 

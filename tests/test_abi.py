@@ -31,10 +31,31 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     assert ctypes.sizeof(skyr.Lattice) == 24
+    assert ctypes.sizeof(skyr.Model) == 32
     assert ctypes.sizeof(skyr.Flow) == 32
     assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16
     assert ctypes.sizeof(skyr.Obs) == 56
     assert ctypes.sizeof(skyr.AnfState) == 4 * 8 + 3 * 8 + 4 * 4
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof of every public struct as the C compiler sees include/skyr.h equals
+    the binding's ctypes layout."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    names = {"skyr_lattice": skyr.Lattice, "skyr_model": skyr.Model, "skyr_flow": skyr.Flow,
+             "skyr_constituent": skyr.Constituent, "skyr_init_spec": skyr.InitSpec, "skyr_obs": skyr.Obs,
+             "skyr_anf_state": skyr.AnfState}
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "skyr.h"\nint main(void){\n' +
+                   "".join(f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", str(ROOT / "include"), "-o", str(exe), str(src)])
+    sizes = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    for (n, cls), sz in zip(names.items(), sizes):
+        assert ctypes.sizeof(cls) == sz, n
 
 
 def test_workspace_bytes():
@@ -78,7 +99,7 @@ def test_invalid_arguments_rejected_without_device_work():
     st = skyr.anf_state()
     for flow in (skyr.Flow(0.0, 0.0, 10, 0, 0), skyr.Flow(-1.0, 0.0, 10, 0, 0), skyr.Flow(0.1, -1.0, 10, 0, 0),
                  skyr.Flow(0.1, 0.0, -1, 0, 0), skyr.Flow(float("nan"), 0.0, 10, 0, 0),
-                 skyr.Flow(0.1, 0.0, 10, 0, 2), skyr.Flow(0.1, 0.0, 10, 0, -1)):
+                 skyr.Flow(0.1, 0.0, 10, 0, 4), skyr.Flow(0.1, 0.0, 10, 0, -1)):
         assert L.skyr_anf_step(ctypes.byref(lat), 0, ctypes.byref(model), ctypes.byref(flow), fake,
                                ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.byref(st), 1, fake,
                                None) == skyr.E_INVAL

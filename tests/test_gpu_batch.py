@@ -18,13 +18,13 @@ def skyr():
     return s
 
 
-def job(n, h, m, dt, prec, B, seed, tol=1e-3, steps=400, arrest="energy"):
-    return dict(n=n, h=h, m=m, dt=dt, tol=tol, steps=steps, precision=prec, arrest=arrest,
+def job(n, h, m, dt, prec, B, seed, tol=1e-3, steps=400, flow="energy"):
+    return dict(n=n, h=h, m=m, dt=dt, tol=tol, steps=steps, precision=prec, flow=flow,
                 init={"kind": "random_product", "B": B, "seed": seed, "radius": 1.5, "prof_lambda": 1.0})
 
 
-MIX = [job(24, 0.25, 1.0, 0.025, "f64", 1, 11), job(32, 0.2, 0.0, 0.02, "f32", 2, 12, arrest="power"),
-       job(28, 0.2, 1.0, 0.02, "f64", 3, 13, arrest="power"), job(20, 0.3, 1.0, 0.03, "f32", 1, 14),
+MIX = [job(24, 0.25, 1.0, 0.025, "f64", 1, 11), job(32, 0.2, 0.0, 0.02, "f32", 2, 12, flow="power"),
+       job(28, 0.2, 1.0, 0.02, "f64", 3, 13, flow="power"), job(20, 0.3, 1.0, 0.03, "f32", 1, 14),
        job(36, 0.2, 1.0, 0.02, "f32", 4, 15, steps=150), job(24, 0.25, 0.0, 0.025, "f64", 2, 16)]
 
 
@@ -36,7 +36,7 @@ def _setup(skyr, d):
     skyr.init_field(lat, prec, spec, phi)
     alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
     work = skyr.new_workspace(lat, prec, DEV)
-    flow = skyr.Flow(d["dt"], d["tol"], d["steps"], 16, skyr.arrest_rule(d.get("arrest", "energy")))
+    flow = skyr.Flow(d["dt"], d["tol"], d["steps"], 16, skyr.flow_mode(d.get("flow", "energy")))
     return lat, prec, phi, alt, vel, work, flow
 
 
