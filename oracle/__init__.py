@@ -99,11 +99,12 @@ def _load():
 
 
 def _mass(m) -> ctypes.Array:
-    """Potential masses {m_x, m_y, m_z, m_w}: a float is the pion mass m_x alone."""
+    """Model constants {m, m_y, m_z, m_w, c6}: a float is the pion mass m alone;
+    a sequence gives the potential masses and, fifth, the sextic coefficient."""
     vals = [float(m)] if np.isscalar(m) else [float(v) for v in m]
-    if not 1 <= len(vals) <= 4:
-        raise ValueError("give the pion mass or up to four potential masses")
-    return (ctypes.c_double * 4)(*(vals + [0.0] * (4 - len(vals))))
+    if not 1 <= len(vals) <= 5:
+        raise ValueError("give the pion mass, or up to four potential masses and c6")
+    return (ctypes.c_double * 5)(*(vals + [0.0] * (5 - len(vals))))
 
 
 def _dims(shape) -> ctypes.Array:
@@ -149,12 +150,12 @@ def laplacian(phi, h: float) -> np.ndarray:
 
 
 # --------------------------------------------------------------------- energy
-def energy_parts(phi, h: float, m: float) -> tuple[float, float, float]:
-    """(E2, E4, E0) of the discrete energy E_h = h^3 sum_I e."""
+def energy_parts(phi, h: float, m) -> tuple[float, float, float, float]:
+    """(E2, E4, E0, E6) of the discrete energy E_h = h^3 sum_I e."""
     phi = _field(phi)
-    out = np.zeros(3)
+    out = np.zeros(4)
     _load().ora_energy_parts(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(out))
-    return float(out[0]), float(out[1]), float(out[2])
+    return float(out[0]), float(out[1]), float(out[2]), float(out[3])
 
 
 def energy(phi, h: float, m: float) -> float:
@@ -229,12 +230,12 @@ def baryon(phi, h: float) -> float:
     return float(_load().ora_baryon(_dims(phi.shape[1:]), h, _ptr(phi)))
 
 
-def observables(phi, h: float, m: float) -> dict:
-    """{E, E2, E4, E0, B, virial, max_force}; virial = E2 - E4 + 3 E0."""
+def observables(phi, h: float, m) -> dict:
+    """{E, E2, E4, E0, B, virial, max_force, E6}; virial = E2 - E4 + 3 E0 - 3 E6."""
     phi = _field(phi)
-    out = np.zeros(7)
+    out = np.zeros(8)
     _load().ora_observables(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(out))
-    keys = ("E", "E2", "E4", "E0", "B", "virial", "max_force")
+    keys = ("E", "E2", "E4", "E0", "B", "virial", "max_force", "E6")
     return {k: float(v) for k, v in zip(keys, out)}
 
 

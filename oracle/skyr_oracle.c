@@ -152,6 +152,26 @@ static double dot4(const double *u, const double *v)
     return u[0] * v[0] + u[1] * v[1] + u[2] * v[2] + u[3] * v[3];
 }
 
+static double det4(const double c0[4], const double c1[4], const double c2[4], const double c3[4]);
+
+/* Sextic (BPS-Skyrme) term at one interior site (Sec. 6: c6 4 pi^4 (B0)^2 in the
+ * printed normalisation, halved here, with B0 = b = -(1/2 pi^2) det[phi, a_1, a_2, a_3]):
+ *   e6 = c6 det^2 / 2.
+ * det is linear in each column, so its derivative with respect to column k is the
+ * determinant with that column replaced by the unit vector e_A.  Returns det and
+ * fills C[k][A] = d det / d(column k)_A, k = 0 (phi), 1..3 (a_1..a_3). */
+static double det_and_cofactors(const double p[4], double a[3][4], double C[4][4])
+{
+    static const double E[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int A = 0; A < 4; A++) {
+        C[0][A] = det4(E[A], a[0], a[1], a[2]);
+        C[1][A] = det4(p, E[A], a[1], a[2]);
+        C[2][A] = det4(p, a[0], E[A], a[2]);
+        C[3][A] = det4(p, a[0], a[1], E[A]);
+    }
+    return det4(p, a[0], a[1], a[2]);
+}
+
 /* Lap_h phi^A at one site: sum over the three axes of the five-point second difference */
 static void laplacian_at(const double *phi, const int n[3], double h, int x, int y, int z, double lap[4])
 {
@@ -166,7 +186,7 @@ static void laplacian_at(const double *phi, const int n[3], double h, int x, int
 /* Potential density of phi0 (Sec. 6, the four potentials of the program, in this
  * energy's normalisation, i.e. halved):
  *   V = m_x^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
- * mass = {m_x, m_y, m_z, m_w}; m_x is the pion mass m of Sec. 2.1. */
+ * mass = {m_x, m_y, m_z, m_w, c6} (the model constants); m_x is the pion mass m of Sec. 2.1. */
 static double potential(const double *mass, double p0)
 {
     double u = 1.0 - p0;
@@ -201,13 +221,16 @@ static void density_parts(const double p[4], const double lap[4], double a[3][4]
 }
 
 /* E2, E4, E0 = h^3 sum over I of the three parts (deterministic order). */
-ORA_API void ora_energy_parts(const int n[3], double h, const double *mass, const double *phi, double out[3])
+/* E2, E4, E0, E6 = h^3 sum over I of the four parts (deterministic order).
+ * model = {m, m_y, m_z, m_w, c6}. */
+ORA_API void ora_energy_parts(const int n[3], double h, const double *model, const double *phi, double out[4])
 {
     const size_t N3 = n_sites(n);
-    double *plane = calloc((size_t)n[0] * 3, sizeof(double));
+    const double c6 = model[4];
+    double *plane = calloc((size_t)n[0] * 4, sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int x = 2; x <= n[0] - 3; x++) {
-        double s2 = 0.0, s4 = 0.0, s0 = 0.0;
+        double s2 = 0.0, s4 = 0.0, s0 = 0.0, s6 = 0.0;
         for (int y = 2; y <= n[1] - 3; y++)
             for (int z = 2; z <= n[2] - 3; z++) {
                 double a[3][4], lap[4], p[4], e2, e4, e0;
@@ -215,33 +238,40 @@ ORA_API void ora_energy_parts(const int n[3], double h, const double *mass, cons
                 for (int A = 0; A < 4; A++) p[A] = FLD(phi, A, s);
                 derivs_at(phi, n, h, x, y, z, a);
                 laplacian_at(phi, n, h, x, y, z, lap);
-                density_parts(p, lap, a, mass, &e2, &e4, &e0);
+                density_parts(p, lap, a, model, &e2, &e4, &e0);
                 s2 += e2;
                 s4 += e4;
                 s0 += e0;
+                if (c6 != 0.0) {
+                    double d = det4(p, a[0], a[1], a[2]);
+                    s6 += 0.5 * c6 * d * d;
+                }
             }
-        plane[3 * x + 0] = s2;
-        plane[3 * x + 1] = s4;
-        plane[3 * x + 2] = s0;
+        plane[4 * x + 0] = s2;
+        plane[4 * x + 1] = s4;
+        plane[4 * x + 2] = s0;
+        plane[4 * x + 3] = s6;
     }
-    double t2 = 0.0, t4 = 0.0, t0 = 0.0;
+    double t2 = 0.0, t4 = 0.0, t0 = 0.0, t6 = 0.0;
     for (int x = 0; x < n[0]; x++) {
-        t2 += plane[3 * x + 0];
-        t4 += plane[3 * x + 1];
-        t0 += plane[3 * x + 2];
+        t2 += plane[4 * x + 0];
+        t4 += plane[4 * x + 1];
+        t0 += plane[4 * x + 2];
+        t6 += plane[4 * x + 3];
     }
     free(plane);
     double h3 = h * h * h;
     out[0] = h3 * t2;
     out[1] = h3 * t4;
     out[2] = h3 * t0;
+    out[3] = h3 * t6;
 }
 
-ORA_API double ora_energy(const int n[3], double h, const double *mass, const double *phi)
+ORA_API double ora_energy(const int n[3], double h, const double *model, const double *phi)
 {
-    double p[3];
-    ora_energy_parts(n, h, mass, phi, p);
-    return p[0] + p[1] + p[2];
+    double p[4];
+    ora_energy_parts(n, h, model, phi, p);
+    return p[0] + p[1] + p[2] + p[3];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -294,9 +324,29 @@ ORA_API void ora_flux(const int n[3], double h, const double *phi, double *P)
 ORA_API void ora_gradient(const int n[3], double h, const double *mass, const double *phi, double *g)
 {
     const size_t N3 = n_sites(n);
+    const double c6 = mass[4];
     double *P = malloc(12 * N3 * sizeof(double));
     double *phiI = malloc(4 * N3 * sizeof(double));
     ora_flux(n, h, phi, P);
+    /* sextic part: flux c6 det C_i added to the quartic flux (zero outside I), local
+     * term c6 det C_0 at the site itself */
+    double *L6 = calloc(4 * N3, sizeof(double));
+    if (c6 != 0.0) {
+#pragma omp parallel for schedule(static)
+        for (int x = 2; x <= n[0] - 3; x++)
+            for (int y = 2; y <= n[1] - 3; y++)
+                for (int z = 2; z <= n[2] - 3; z++) {
+                    size_t s = site(n, x, y, z);
+                    double a[3][4], p[4], C[4][4];
+                    derivs_at(phi, n, h, x, y, z, a);
+                    for (int A = 0; A < 4; A++) p[A] = FLD(phi, A, s);
+                    double d = det_and_cofactors(p, a, C);
+                    for (int A = 0; A < 4; A++) {
+                        for (int i = 0; i < 3; i++) P[((size_t)i * 4 + A) * N3 + s] += c6 * d * C[i + 1][A];
+                        FLD(L6, A, s) = c6 * d * C[0][A];
+                    }
+                }
+    }
     /* 1_I phi: the field with every site outside the interior set to zero */
     for (int A = 0; A < 4; A++)
         for (int x = 0; x < n[0]; x++)
@@ -318,11 +368,13 @@ ORA_API void ora_gradient(const int n[3], double h, const double *mass, const do
                     double div = 0.0;
                     for (int i = 0; i < 3; i++)
                         div += d1(P + ((size_t)i * 4 + A) * N3, n, i, x, y, z, h);
-                    FLD(g, A, s) = -0.5 * (lap[A] + lapI[A]) - div + (A == 0 ? potential_slope(mass, FLD(phi, 0, s)) : 0.0);
+                    FLD(g, A, s) = -0.5 * (lap[A] + lapI[A]) - div + FLD(L6, A, s) +
+                                   (A == 0 ? potential_slope(mass, FLD(phi, 0, s)) : 0.0);
                 }
             }
     free(P);
     free(phiI);
+    free(L6);
 }
 
 /* Tangent projection (Sec. 3, eq. Newton_flow): gT = g - (g.phi) phi on I.
@@ -382,13 +434,28 @@ ORA_API void ora_gradient_at(const int n[3], double h, const double *mass, const
             derivs_at(phi, n, h, xx, yy, zz, a);
             flux_from_derivs(a, P);
             size_t s = site(n, xx, yy, zz);
+            if (mass[4] != 0.0) {
+                double pp[4], C[4][4];
+                for (int A = 0; A < 4; A++) pp[A] = FLD(phi, A, s);
+                double d = det_and_cofactors(pp, a, C);
+                for (int ii = 0; ii < 3; ii++)
+                    for (int A = 0; A < 4; A++) P[ii][A] += mass[4] * d * C[ii + 1][A];
+            }
             for (int A = 0; A < 4; A++) {
                 div[A] += c1[k] * P[i][A] / h;
                 lapI[A] += c2[k] * FLD(phi, A, s) / (h * h);
             }
         }
+    double L6[4] = {0, 0, 0, 0};
+    if (mass[4] != 0.0) {
+        double a[3][4], pp[4], C[4][4];
+        derivs_at(phi, n, h, x, y, z, a);
+        for (int A = 0; A < 4; A++) pp[A] = FLD(phi, A, s0);
+        double d = det_and_cofactors(pp, a, C);
+        for (int A = 0; A < 4; A++) L6[A] = mass[4] * d * C[0][A];
+    }
     for (int A = 0; A < 4; A++)
-        g[A] = -0.5 * (lap[A] + lapI[A]) - div[A] + (A == 0 ? potential_slope(mass, FLD(phi, 0, s0)) : 0.0);
+        g[A] = -0.5 * (lap[A] + lapI[A]) - div[A] + L6[A] + (A == 0 ? potential_slope(mass, FLD(phi, 0, s0)) : 0.0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -452,14 +519,14 @@ ORA_API double ora_baryon(const int n[3], double h, const double *phi)
     return h * h * h * t;
 }
 
-/* Observables: E2, E4, E0, E, B, virial V = E2 - E4 + 3 E0 (Sec. 5.6; the
- * Derrick scaling argument, up to the sign and factor of the stress trace),
- * and the largest tangential gradient norm.
- * out = {E, E2, E4, E0, B, virial, max_force}. */
-ORA_API void ora_observables(const int n[3], double h, const double *mass, const double *phi, double out[7])
+/* Observables: E2, E4, E0, E6, E, B, virial V = E2 - E4 + 3 E0 - 3 E6 (Sec. 5.6;
+ * the Derrick scaling argument: under x -> lambda x the parts scale as
+ * lambda^-1, lambda, lambda^-3, lambda^3), and the largest tangential gradient
+ * norm.  out = {E, E2, E4, E0, B, virial, max_force, E6}. */
+ORA_API void ora_observables(const int n[3], double h, const double *mass, const double *phi, double out[8])
 {
     const size_t N3 = n_sites(n);
-    double p[3];
+    double p[4];
     ora_energy_parts(n, h, mass, phi, p);
     double *g = malloc(4 * N3 * sizeof(double));
     double *gT = malloc(4 * N3 * sizeof(double));
@@ -467,13 +534,14 @@ ORA_API void ora_observables(const int n[3], double h, const double *mass, const
     double r = ora_project(n, phi, g, gT);
     free(g);
     free(gT);
-    out[0] = p[0] + p[1] + p[2];
+    out[0] = p[0] + p[1] + p[2] + p[3];
     out[1] = p[0];
     out[2] = p[1];
     out[3] = p[2];
     out[4] = ora_baryon(n, h, phi);
-    out[5] = p[0] - p[1] + 3.0 * p[2];
+    out[5] = p[0] - p[1] + 3.0 * p[2] - 3.0 * p[3];
     out[6] = r;
+    out[7] = p[3];
 }
 
 /* ------------------------------------------------------------------------ */

@@ -102,7 +102,7 @@ def test_gradient_f64_matches_oracle(skyr, shape, projected):
         ref, _ = oracle.project(phi, ref)
     got = g.cpu().numpy()
     assert _rel_inf(got, ref) <= 1e-12
-    E2, E4, E0 = oracle.energy_parts(phi, h, m)
+    E2, E4, E0, _ = oracle.energy_parts(phi, h, m)
     assert parts["E2"] == pytest.approx(E2, rel=1e-12)
     assert parts["E4"] == pytest.approx(E4, rel=1e-12)
     assert parts["E0"] == pytest.approx(E0, rel=1e-12)

@@ -105,7 +105,7 @@ def test_checkerboard_is_penalised_by_e2_only():
     inner = np.zeros((n, n, n), dtype=bool)
     inner[4:-4, 4:-4, 4:-4] = True
     assert np.abs(a[:, :, inner]).max() < 1e-15
-    E2, E4, E0 = oracle.energy_parts(phi, h, 0.0)
+    E2, E4, E0, _ = oracle.energy_parts(phi, h, 0.0)
     # per inner site: -1/2 phi.Lap phi = 1/2 (32/(6 h^2)) * 3 * (pion amplitude)^2 to leading order
     assert E2 > 0.5 * 3 * (16.0 / 6.0) * (eps ** 2) / h ** 2 * h ** 3 * inner.sum()
 
@@ -117,12 +117,14 @@ def test_h_homogeneity():
     n = 11
     phi = random_unit_field((n, n, n), 7, 0.4)
     h1, h2, m = 0.2, 0.35, 0.9
-    p1 = oracle.energy_parts(phi, h1, m)
-    p2 = oracle.energy_parts(phi, h2, m)
+    model = (m, 0.0, 0.0, 0.0, 0.7)  # with the sextic term
+    p1 = oracle.energy_parts(phi, h1, model)
+    p2 = oracle.energy_parts(phi, h2, model)
     r = h2 / h1
     assert p2[0] == pytest.approx(p1[0] * r, rel=1e-13)
     assert p2[1] == pytest.approx(p1[1] / r, rel=1e-13)
     assert p2[2] == pytest.approx(p1[2] * r ** 3, rel=1e-13)
+    assert p2[3] == pytest.approx(p1[3] / r ** 3, rel=1e-13)  # E6: six derivatives, h^3 volume
     assert oracle.baryon(phi, h2) == pytest.approx(oracle.baryon(phi, h1), rel=1e-12, abs=1e-14)
 
 
@@ -153,23 +155,59 @@ def test_gradient_is_derivative_of_discrete_energy_bruteforce():
     assert np.all(g[:, ~I] == 0.0)
 
 
-def test_gradient_bruteforce_with_all_potentials():
-    """The same brute-force check with all four potentials switched on
-    (m_x, m_y, m_z, m_w): pins dV/dphi0 against V itself."""
+def test_gradient_bruteforce_with_all_potentials_and_sextic():
+    """The same brute-force check with all four potentials and the sextic term
+    switched on (m, m_y, m_z, m_w, c6): pins dV/dphi0 against V and the sextic
+    flux and local cofactor term against e6 = c6 det^2 / 2."""
     n, h = 7, 0.31
-    mass = (0.9, 0.7, 1.3, 0.6)
+    model = (0.9, 0.7, 1.3, 0.6, 0.8)
     phi = random_unit_field((n, n, n), 12, 0.8)
-    g = oracle.gradient(phi, h, mass)
+    g = oracle.gradient(phi, h, model)
     I = interior_mask((n, n, n))
     worst = 0.0
     for x, y, z in zip(*np.nonzero(I)):
-        def fun(e, x=x, y=y, z=z):
-            p = phi.copy()
-            p[0, x, y, z] += e
-            return oracle.energy(p, h, mass)
-        fd = _richardson_derivative(fun, 1e-3)
-        worst = max(worst, abs(fd - h ** 3 * g[0, x, y, z]) / (abs(fd) + 1e-3))
+        for A in range(4):
+            def fun(e, x=x, y=y, z=z, A=A):
+                p = phi.copy()
+                p[A, x, y, z] += e
+                return oracle.energy(p, h, model)
+            fd = _richardson_derivative(fun, 1e-3)
+            worst = max(worst, abs(fd - h ** 3 * g[A, x, y, z]) / (abs(fd) + 1e-3))
     assert worst < 1e-8
+    # the single-site form agrees with the full gradient
+    for (x, y, z) in ((2, 2, 2), (3, 4, 2), (4, 4, 4)):
+        np.testing.assert_allclose(oracle.gradient_at(phi, h, model, x, y, z), g[:, x, y, z], rtol=1e-12,
+                                   atol=1e-12 * np.abs(g).max())
+
+
+def test_sextic_energy_of_the_hedgehog_against_radial_quadrature():
+    """E6 of the unrelaxed hedgehog f = pi (1 - tanh r) converges at fourth order
+    to 2 pi c6 int f'^2 sin^4 f / r^2 dr, the continuum value of c6 det^2 / 2 with
+    det = f' sin^2 f / r^2 for the hedgehog (Sec. 6 sextic term, halved)."""
+    from scipy import integrate
+    c6 = 1.3
+    f = lambda r: math.pi * (1 - math.tanh(r))
+    fp = lambda r: -math.pi / math.cosh(r) ** 2
+
+    def integrand(r):
+        return fp(r) ** 2 * math.sin(f(r)) ** 4 / (r * r) if r > 0 else 0.0
+    ref = 2 * math.pi * c6 * integrate.quad(integrand, 0.0, 40.0, limit=400, epsabs=1e-13, epsrel=1e-13)[0]
+    errs = {}
+    for h in (0.3, 0.2, 0.15):
+        n = int(round(2 * 5.5 / h)) + 4
+        n += n % 2
+        x = coords(n, h)
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        fr = math.pi * (1 - np.tanh(r))
+        phi = np.stack([np.cos(fr), np.sin(fr) * X / r, np.sin(fr) * Y / r, np.sin(fr) * Z / r])
+        inner = interior_mask((n, n, n))
+        phi[:, ~inner] = 0.0
+        phi[0, ~inner] = 1.0
+        errs[h] = oracle.energy_parts(phi, h, (1.0, 0.0, 0.0, 0.0, c6))[3] - ref
+    order = math.log(abs(errs[0.2] / errs[0.15])) / math.log(0.2 / 0.15)
+    assert 3.3 < order < 4.7, (errs, order)
+    assert abs(errs[0.15]) < 2e-2 * ref
 
 
 def test_potentials_on_a_uniform_field():
@@ -192,7 +230,7 @@ def test_potentials_on_a_uniform_field():
         return 0.5 * (2 * mx ** 2 * (1 - c) + my ** 2 * (1 - c * c) + mz ** 2 * (1 - c) ** 2
                       + 0.5 * mw ** 2 * (1 - c) ** 4)
 
-    e2, e4, e0 = oracle.energy_parts(phi, h, mass)
+    e2, e4, e0, _ = oracle.energy_parts(phi, h, mass)
     assert abs(e2) < 1e-13 and abs(e4) < 1e-13
     assert e0 == pytest.approx(h ** 3 * (n - 4) ** 3 * V(math.cos(alpha)), rel=1e-13)
     g = oracle.gradient(phi, h, mass)
@@ -244,7 +282,7 @@ def test_one_dimensional_reduction():
     phi = np.zeros((4, n, n, n))
     phi[0] = np.cos(theta)[:, None, None]
     phi[2] = np.sin(theta)[:, None, None]
-    E2, E4, E0 = oracle.energy_parts(phi, h, m)
+    E2, E4, E0, _ = oracle.energy_parts(phi, h, m)
     assert abs(E4) < 1e-13 * E2
     g = oracle.gradient(phi, h, m)
     # 1D: L f(i) = sum_k c_k f(i+k) / h^2 with the five-point weights
