@@ -70,16 +70,19 @@ typedef struct {
     double h;
 } skyr_lattice;
 
-/* Potential masses (Sec. 2.1 and the program's four potentials, Sec. 6), in this
- * library's energy normalisation (one half of the printed density):
+/* Model couplings (Sec. 2.1 and the program's four potentials and sextic term, Sec. 6),
+ * in this library's energy normalisation (one half of the printed density):
  *   V(phi0) = m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
+ *   e6      = (c6 / 2) det[phi, a_1, a_2, a_3]^2        (a_i the derivatives of phi)
  * m is the rescaled pion mass (m = 2 m_pi / (F_pi e)); m_y, m_z, m_w are the modified
- * pion mass, loosely bound and lightly bound potential masses (0 = absent). */
+ * pion mass, loosely bound and lightly bound potential masses; c6 >= 0 weighs the sextic
+ * (BPS-Skyrme) term, the squared baryon density up to (2 pi^2)^2.  0 = absent. */
 typedef struct {
     double m;
     double m_y;
     double m_z;
     double m_w;
+    double c6;
 } skyr_model;
 
 /* Flow mode (Sec. 3; the program's flow modes, Sec. 6).
@@ -154,12 +157,13 @@ typedef struct {
     double prof_lambda;          /* HEDGEHOG, RANDOM_PRODUCT profile length                  */
 } skyr_init_spec;
 
-/* Observables (Sec. 2.1, 5.6): E = E2 + E4 + E0; B = h^3 sum_I b with
+/* Observables (Sec. 2.1, 5.6): E = E2 + E4 + E0 + E6; B = h^3 sum_I b with
  * b = -(1/2 pi^2) det[phi, a_1, a_2, a_3] (the sign that gives the hedgehog with
- * f(0) = pi charge +1); virial = E2 - E4 + 3 E0 (zero for a Derrick-stationary
- * field); max_force = max over I of |F|, F = -(g - (g.phi) phi). */
+ * f(0) = pi charge +1); virial = E2 - E4 + 3 E0 - 3 E6 (dE/dlambda under
+ * x -> lambda x; zero for a Derrick-stationary field); max_force = max over I of
+ * |F|, F = -(g - (g.phi) phi); E6 = the sextic energy (0 when c6 = 0). */
 typedef struct {
-    double E, E2, E4, E0, B, virial, max_force;
+    double E, E2, E4, E0, B, virial, max_force, E6;
 } skyr_obs;
 
 /* State of an arrested Newton flow, carried across skyr_anf_step calls.

@@ -247,43 +247,47 @@ __global__ void copy_frozen_kernel(const T* __restrict__ src, T* __restrict__ ds
 }
 
 // Fixed-order reduction of the per-block partials: thread t sums blocks
-// t, t + 256, ... in order, then a fixed tree.  out = {E2, E4, E0, Bsum, maxF2}.
-__device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[6])
+// t, t + 256, ... in order, then a fixed tree.
+// out = {E2, E4, E0, Bsum, maxF2, power, E6}.
+constexpr int NRED = 7;
+__device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[NRED])
 {
-    __shared__ double red[256][6];
+    __shared__ double red[256][NRED];
     const int t = threadIdx.x;
-    double s[6] = {0, 0, 0, 0, 0, 0};
+    double s[NRED] = {0, 0, 0, 0, 0, 0, 0};
     for (int b = t; b < nblocks; b += 256) {
         const double* p = part + (size_t)b * NPART;
-        for (int i = 0; i < 6; ++i) s[i] = (i == P_F2) ? fmax(s[i], p[i]) : s[i] + p[i];
+        for (int i = 0; i < NRED; ++i) s[i] = (i == P_F2) ? fmax(s[i], p[i]) : s[i] + p[i];
     }
-    for (int i = 0; i < 6; ++i) red[t][i] = s[i];
+    for (int i = 0; i < NRED; ++i) red[t][i] = s[i];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
-            for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < NRED; ++i)
                 red[t][i] = (i == P_F2) ? fmax(red[t][i], red[t + w][i]) : red[t][i] + red[t + w][i];
         }
         __syncthreads();
     }
-    for (int i = 0; i < 6; ++i) out[i] = red[0][i];
+    for (int i = 0; i < NRED; ++i) out[i] = red[0][i];
 }
 
-// obs = {E, E2, E4, E0, B, virial, max_force}
+// obs = {E, E2, E4, E0, B, virial, max_force, E6}; the virial is the
+// derivative of E under x -> lambda x at lambda = 1, E2 - E4 + 3 E0 - 3 E6.
 __global__ void observe_kernel(const double* __restrict__ part, int nblocks, double h, double* __restrict__ obs)
 {
-    double s[6];
+    double s[NRED];
     reduce_partials(part, nblocks, s);
     if (threadIdx.x == 0) {
         const double h3 = h * h * h;
-        const double E2 = h3 * s[0], E4 = h3 * s[1], E0 = h3 * s[2];
-        obs[0] = E2 + E4 + E0;
+        const double E2 = h3 * s[P_E2], E4 = h3 * s[P_E4], E0 = h3 * s[P_E0], E6 = h3 * s[P_E6];
+        obs[0] = E2 + E4 + E0 + E6;
         obs[1] = E2;
         obs[2] = E4;
         obs[3] = E0;
-        obs[4] = -h3 * s[3] / (2.0 * M_PI * M_PI);
-        obs[5] = E2 - E4 + 3.0 * E0;
-        obs[6] = sqrt(s[4]);
+        obs[4] = -h3 * s[P_B] / (2.0 * M_PI * M_PI);
+        obs[5] = E2 - E4 + 3.0 * E0 - 3.0 * E6;
+        obs[6] = sqrt(s[P_F2]);
+        obs[7] = E6;
     }
 }
 
@@ -294,12 +298,12 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
 __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;  // uniform
-    double s[6];
+    double s[NRED];
     reduce_partials(part, ctl->nblocks, s);
     if (threadIdx.x != 0) return;
-    // the flow sweep sums the whole energy density in slot 0 (slots 1, 2 are zero)
-    const double E = ctl->h3 * s[0];
-    const double r = sqrt(s[4]);
+    // the flow sweep sums the whole energy density in slot 0 (slots 1, 2, 6 are zero)
+    const double E = ctl->h3 * s[P_E2];
+    const double r = sqrt(s[P_F2]);
     ctl->sweeps += 1;
     ctl->E = E;
     ctl->P = ctl->h3 * s[P_POW];
@@ -351,7 +355,7 @@ __global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, int nj
 // by models and flows that need it
 static bool needs_ext(const SweepArgs& a)
 {
-    return a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.gradient_flow != 0;
+    return a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.c6 != 0.0 || a.gradient_flow != 0;
 }
 
 template <typename T, int NW, int LW, int RY>
@@ -443,6 +447,7 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_
     a.m_y = model->m_y;
     a.m_z = model->m_z;
     a.m_w = model->m_w;
+    a.c6 = model->c6;
     a.dt = dt;
     return a;
 }
@@ -668,7 +673,7 @@ static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, co
     if (obs_out) {
         hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, L.blocks(), lat->h, obs);
         SKYR_HIP(hipGetLastError());
-        SKYR_HIP(hipMemcpyAsync(obs_out, obs, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipMemcpyAsync(obs_out, obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         SKYR_HIP(hipStreamSynchronize(s));
     }
     return SKYR_OK;
@@ -681,8 +686,8 @@ static skyr_status check_common(const skyr_lattice* lat, skyr_precision prec, co
     if (st != SKYR_OK) return st;
     if (!model || !phi || !work) return fail(SKYR_E_INVAL, "model, phi and work must be non-null");
     if (!std::isfinite(model->m) || !std::isfinite(model->m_y) || !std::isfinite(model->m_z) ||
-        !std::isfinite(model->m_w))
-        return fail(SKYR_E_INVAL, "masses must be finite");
+        !std::isfinite(model->m_w) || !std::isfinite(model->c6))
+        return fail(SKYR_E_INVAL, "masses and c6 must be finite");
     if (!aligned256(work)) return fail(SKYR_E_INVAL, "workspace must be 256-byte aligned");
     return SKYR_OK;
 }
@@ -693,7 +698,7 @@ skyr_status skyr_energy_gradient(const skyr_lattice* lat, skyr_precision prec, c
 {
     skyr_status st = check_common(lat, prec, model, phi, work);
     if (st != SKYR_OK) return st;
-    double o[7];
+    double o[8];
     st = run_gradient(lat, prec, model, phi, grad, projected ? 1 : 0, 0, parts ? o : nullptr, work, (hipStream_t)stream);
     if (st != SKYR_OK) return st;
     if (parts) {
@@ -704,6 +709,7 @@ skyr_status skyr_energy_gradient(const skyr_lattice* lat, skyr_precision prec, c
         parts->B = 0.0;
         parts->virial = o[5];
         parts->max_force = o[6];
+        parts->E6 = o[7];
     }
     return SKYR_OK;
 }
@@ -714,7 +720,7 @@ skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const
     skyr_status st = check_common(lat, prec, model, phi, work);
     if (st != SKYR_OK) return st;
     if (!out) return fail(SKYR_E_INVAL, "out must be non-null");
-    double o[7];
+    double o[8];
     st = run_gradient(lat, prec, model, phi, nullptr, 0, 1, o, work, (hipStream_t)stream);
     if (st != SKYR_OK) return st;
     out->E = o[0];
@@ -724,6 +730,7 @@ skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const
     out->B = o[4];
     out->virial = o[5];
     out->max_force = o[6];
+    out->E6 = o[7];
     return SKYR_OK;
 }
 

@@ -29,7 +29,7 @@ namespace skyr {
 
 // partial-sum slots per thread block (doubles)
 constexpr int NPART = 8;
-enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4, P_POW = 5 };
+enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4, P_POW = 5, P_E6 = 6 };
 
 // Control block of one flow, in device memory at the start of the workspace.
 struct Ctl {
@@ -73,6 +73,7 @@ struct SweepArgs {
     int baryon;        // accumulate the baryon density
     double h, dt;
     double m, m_y, m_z, m_w;  // potential masses
+    double c6;                // sextic (BPS-Skyrme) coefficient
     int gradient_flow;        // MODE_STEP: phi += dt F, no velocity
 };
 
@@ -161,6 +162,43 @@ template <typename T> __device__ __forceinline__ T det4(const T* c0, const T* c1
     return m01 * n23 - m02 * n13 + m03 * n12 + m12 * n03 - m13 * n02 + m23 * n01;
 }
 
+// det[c0 c1 c2 c3] and its derivatives with respect to each column (det is linear in
+// every column; the derivative with respect to column k is the cofactor vector),
+// from the 2x2 minors m of columns (c0, c1) and n of columns (c2, c3):
+//   det = m01 n23 - m02 n13 + m03 n12 + m12 n03 - m13 n02 + m23 n01
+template <typename T>
+__device__ __forceinline__ T det4_cofactors(const T* c0, const T* c1, const T* c2, const T* c3, T* d0, T* d1, T* d2,
+                                            T* d3)
+{
+    const T m01 = c0[0] * c1[1] - c0[1] * c1[0], m02 = c0[0] * c1[2] - c0[2] * c1[0];
+    const T m03 = c0[0] * c1[3] - c0[3] * c1[0], m12 = c0[1] * c1[2] - c0[2] * c1[1];
+    const T m13 = c0[1] * c1[3] - c0[3] * c1[1], m23 = c0[2] * c1[3] - c0[3] * c1[2];
+    const T n01 = c2[0] * c3[1] - c2[1] * c3[0], n02 = c2[0] * c3[2] - c2[2] * c3[0];
+    const T n03 = c2[0] * c3[3] - c2[3] * c3[0], n12 = c2[1] * c3[2] - c2[2] * c3[1];
+    const T n13 = c2[1] * c3[3] - c2[3] * c3[1], n23 = c2[2] * c3[3] - c2[3] * c3[2];
+    // d det / d m_ab and d det / d n_ab are the complementary minors with the signs above
+    const T M01 = n23, M02 = -n13, M03 = n12, M12 = n03, M13 = -n02, M23 = n01;
+    const T N23 = m01, N13 = -m02, N12 = m03, N03 = m12, N02 = -m13, N01 = m23;
+    // m_ab = c0_a c1_b - c0_b c1_a:  d/dc0_a = c1_b (and -c1_a for d/dc0_b); d/dc1 likewise
+    d0[0] = M01 * c1[1] + M02 * c1[2] + M03 * c1[3];
+    d0[1] = -M01 * c1[0] + M12 * c1[2] + M13 * c1[3];
+    d0[2] = -M02 * c1[0] - M12 * c1[1] + M23 * c1[3];
+    d0[3] = -M03 * c1[0] - M13 * c1[1] - M23 * c1[2];
+    d1[0] = -M01 * c0[1] - M02 * c0[2] - M03 * c0[3];
+    d1[1] = M01 * c0[0] - M12 * c0[2] - M13 * c0[3];
+    d1[2] = M02 * c0[0] + M12 * c0[1] - M23 * c0[3];
+    d1[3] = M03 * c0[0] + M13 * c0[1] + M23 * c0[2];
+    d2[0] = N01 * c3[1] + N02 * c3[2] + N03 * c3[3];
+    d2[1] = -N01 * c3[0] + N12 * c3[2] + N13 * c3[3];
+    d2[2] = -N02 * c3[0] - N12 * c3[1] + N23 * c3[3];
+    d2[3] = -N03 * c3[0] - N13 * c3[1] - N23 * c3[2];
+    d3[0] = -N01 * c2[1] - N02 * c2[2] - N03 * c2[3];
+    d3[1] = N01 * c2[0] - N12 * c2[2] - N13 * c2[3];
+    d3[2] = N02 * c2[0] + N12 * c2[1] - N23 * c2[3];
+    d3[3] = N03 * c2[0] + N13 * c2[1] + N23 * c2[2];
+    return m01 * n23 - m02 * n13 + m03 * n12 + m12 * n03 - m13 * n02 + m23 * n01;
+}
+
 template <typename T, int NW, int LW, int RY> struct Tile {
     static constexpr int RPW = 64 / LW;     // rows per wave
     static constexpr int R0 = NW * RPW;     // rows per row group
@@ -216,7 +254,9 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
     bool row_out[RY], yz_in[RY], y_near[RY], z_near;
     T c1h, c2h, d1h, d2h, hd1h, hd2h, dt;  // stencil weights with 1/h, 1/h^2 (and 1/2) folded in
     T m2, my2, mz2, mw2;                   // squared potential masses
+    T c6;                                  // sextic coefficient
     bool more_pot;                         // any of m_y, m_z, m_w nonzero
+    bool sextic;                           // c6 nonzero
     bool grad_flow;                        // gradient flow: phi += dt F, no velocity
 
     // registers carried along the march
@@ -227,7 +267,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
 
     // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
     // flow step keeps the total energy density in pe2 and leaves the others at zero
-    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0;
+    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0, pe6 = 0.0;
     T pp = T(0);  // power F . v of the incoming velocity (flow step; used by the power arrest rule)
     T pf2 = T(0);
 
@@ -363,29 +403,73 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
             // the flux vanishes outside I: zero the Gram entries it is built from
             const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
             const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
+            T e6 = T(0);
+            if constexpr (!EXT) {
 #pragma unroll
-            for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
-            if (full) {
+                for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
+                if (full) {
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
+                        sm.qz[pb][A][r][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
+                        // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
+                        acc[S_M1][A][k] -= c1h * qx;
+                        acc[S_P1][A][k] += c1h * qx;
+                        acc[S_M2][A][k] -= c2h * qx;
+                        acc[S_P2][A][k] += c2h * qx;
+                    }
+                }
+            } else {
+                T qx[4], qy[4], qz[4];
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
-                    sm.qz[pb][A][r][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
-                    // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
-                    acc[S_M1][A][k] -= c1h * qx;
-                    acc[S_P1][A][k] += c1h * qx;
-                    acc[S_M2][A][k] -= c2h * qx;
-                    acc[S_P2][A][k] += c2h * qx;
+                    qx[A] = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
+                    qy[A] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
+                    qz[A] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
                 }
+                if (sextic) {
+                    // e6 = c6 det^2 / 2, det = det[phi, a_x, a_y, a_z]: flux c6 det dDet/da_i
+                    // (zero outside I) and the local term c6 det dDet/dphi
+                    T C0[4], C1[4], C2[4], C3[4];
+                    const T det = det4_cofactors(c, ax, ay, az, C0, C1, C2, C3);
+                    const T dv = valid ? c6 * det : T(0);
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        qx[A] += dv * C1[A];
+                        qy[A] += dv * C2[A];
+                        qz[A] += dv * C3[A];
+                        acc[S_0][A][k] += dv * C0[A];
+                    }
+                    e6 = T(0.5) * c6 * det * det;
+                }
+#pragma unroll
+                for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = qy[A];
+                if (full) {
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        sm.qz[pb][A][r][zl] = qz[A];
+                        acc[S_M1][A][k] -= c1h * qx[A];
+                        acc[S_P1][A][k] += c1h * qx[A];
+                        acc[S_M2][A][k] -= c2h * qx[A];
+                        acc[S_P2][A][k] += c2h * qx[A];
+                    }
+                }
+            }
+            if (full) {
                 if (row_out[k] && j_out) {
                     const T e2 = T(-0.5) * cl;
                     const T e4 = T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
                     const T e0 = potential(c[0]);
                     if constexpr (MODE == MODE_STEP) {
-                        pe2 += (double)(e2 + e4 + e0);  // the flow needs the total energy only
+                        if constexpr (EXT)
+                            pe2 += (double)(e2 + e4 + e0 + e6);  // the flow needs the total energy only
+                        else
+                            pe2 += (double)(e2 + e4 + e0);
                     } else {
                         pe2 += (double)e2;
                         pe4 += (double)e4;
                         pe0 += (double)e0;
+                        if constexpr (EXT) pe6 += (double)e6;
                         if (baryon) pb_sum += (double)det4(c, ax, ay, az);
                     }
                 }
@@ -554,6 +638,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     sw.mz2 = T(a.m_z * a.m_z);
     sw.mw2 = T(a.m_w * a.m_w);
     sw.more_pot = a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0;
+    sw.c6 = T(a.c6);
+    sw.sextic = a.c6 != 0.0;
     sw.grad_flow = MODE == MODE_STEP && a.gradient_flow != 0;
 
     const int tid = threadIdx.x;
@@ -655,9 +741,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[6] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, (double)sw.pp};
+    double vals[7] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, (double)sw.pp, sw.pe6};
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 7; ++i) {
         double v = vals[i];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -668,16 +754,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) smem.red[wave][i] = vals[i];
+        for (int i = 0; i < 7; ++i) smem.red[wave][i] = vals[i];
     }
     __syncthreads();
     if (tid == 0) {
-        double sum[6] = {0, 0, 0, 0, 0, 0};
+        double sum[7] = {0, 0, 0, 0, 0, 0, 0};
         for (int wv = 0; wv < NW; ++wv) {
-            for (int i = 0; i < 6; ++i) sum[i] = (i == 4) ? fmax(sum[i], smem.red[wv][i]) : sum[i] + smem.red[wv][i];
+            for (int i = 0; i < 7; ++i) sum[i] = (i == 4) ? fmax(sum[i], smem.red[wv][i]) : sum[i] + smem.red[wv][i];
         }
         double* out = a.partials + (size_t)b * NPART;
-        for (int i = 0; i < 6; ++i) out[i] = sum[i];
+        for (int i = 0; i < 7; ++i) out[i] = sum[i];
     }
 }
 

@@ -49,9 +49,9 @@ class Lattice(ctypes.Structure):
 
 
 class Model(ctypes.Structure):
-    """Potential masses: the pion mass m and the optional m_y, m_z, m_w."""
+    """Couplings: the pion mass m, the optional masses m_y, m_z, m_w and the sextic weight c6."""
     _fields_ = [("m", ctypes.c_double), ("m_y", ctypes.c_double), ("m_z", ctypes.c_double),
-                ("m_w", ctypes.c_double)]
+                ("m_w", ctypes.c_double), ("c6", ctypes.c_double)]
 
 
 class Flow(ctypes.Structure):
@@ -73,7 +73,7 @@ class InitSpec(ctypes.Structure):
 
 
 class Obs(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_double) for k in ("E", "E2", "E4", "E0", "B", "virial", "max_force")]
+    _fields_ = [(k, ctypes.c_double) for k in ("E", "E2", "E4", "E0", "B", "virial", "max_force", "E6")]
 
     def as_dict(self) -> dict:
         return {k: float(getattr(self, k)) for k, _ in self._fields_}

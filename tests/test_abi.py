@@ -31,10 +31,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     assert ctypes.sizeof(skyr.Lattice) == 24
-    assert ctypes.sizeof(skyr.Model) == 32
+    assert ctypes.sizeof(skyr.Model) == 40
     assert ctypes.sizeof(skyr.Flow) == 32
     assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16
-    assert ctypes.sizeof(skyr.Obs) == 56
+    assert ctypes.sizeof(skyr.Obs) == 64
     assert ctypes.sizeof(skyr.AnfState) == 4 * 8 + 3 * 8 + 4 * 4
 
 

@@ -1,7 +1,7 @@
-"""GPU parity of the flow modes and potentials of the program (Sec. 6): the
+"""GPU parity of the flow modes and model terms of the program (Sec. 6): the
 modified pion mass, loosely and lightly bound potentials on top of the pion
-mass, the plain Newton flow and the first-order gradient flow, against the FP64
-oracle on identical inputs."""
+mass, the sextic (BPS-Skyrme) term, the plain Newton flow and the first-order
+gradient flow, against the FP64 oracle on identical inputs."""
 import numpy as np
 import pytest
 
@@ -13,6 +13,8 @@ torch = pytest.importorskip("torch")
 
 DEV = "cuda:0"
 MASS = (0.9, 0.7, 1.3, 0.6)  # m, m_y, m_z, m_w
+SEXTIC = (1.0, 0.0, 0.0, 0.0, 0.1)  # the pion mass and the sextic term alone
+ALL = MASS + (0.1,)  # m, m_y, m_z, m_w, c6
 
 
 @pytest.fixture(scope="module")
@@ -105,3 +107,45 @@ def test_arrested_flow_with_potentials_matches_oracle(skyr):
     ref, rvel, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, MASS, dt, 0.0, 80)
     assert st.arrests == rst.arrests
     assert np.abs(phi - ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("model", [SEXTIC, ALL], ids=["sextic", "all"])
+@pytest.mark.parametrize("shape", [(23, 29, 40), (40, 40, 40)])
+def test_gradient_energy_and_observables_with_sextic(skyr, prec, model, shape):
+    """The sextic term (alone and with every potential): gradient element by
+    element, E6 and E, the charge and the virial E2 - E4 + 3 E0 - 3 E6."""
+    h = 0.2
+    phi = random_unit_field(shape, 37, 0.6)
+    if prec == 1:
+        phi = phi.astype(np.float32).astype(np.float64)
+    lat = _lat(skyr, shape, h)
+    t = torch.tensor(phi, dtype=skyr.field_dtype(prec), device=DEV)
+    g = skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    parts = skyr.energy_gradient(lat, prec, skyr.Model(*model), t, work, grad=g, projected=False)
+    ref = oracle.gradient(phi, h, model)
+    E2, E4, E0, E6 = oracle.energy_parts(phi, h, model)
+    assert E6 > 0.1 * abs(E2)  # the term is not negligible on this field
+    tol_g, tol_e = (1e-12, 1e-12) if prec == 0 else (2e-4, 2e-6)
+    assert _rel_inf(g.double().cpu().numpy(), ref) <= tol_g
+    assert parts["E6"] == pytest.approx(E6, rel=tol_e)
+    assert parts["E"] == pytest.approx(E2 + E4 + E0 + E6, rel=tol_e)
+    obs = skyr.observables(lat, prec, skyr.Model(*model), t, work)
+    ro = oracle.observables(phi, h, model)
+    for k in ("E", "E2", "E4", "E0", "E6"):
+        assert obs[k] == pytest.approx(ro[k], rel=tol_e), k
+    assert obs["B"] == pytest.approx(ro["B"], rel=10 * tol_e, abs=10 * tol_e * abs(ro["E"]))
+    assert obs["virial"] == pytest.approx(ro["virial"], rel=10 * tol_e, abs=10 * tol_e * abs(ro["E"]))
+
+
+def test_arrested_flow_with_sextic_matches_oracle(skyr):
+    """The arrested Newton flow with the sextic term and every potential:
+    80 steps with resets, fields and velocities agree with the oracle."""
+    n, h, dt = 24, 0.25, 0.04
+    model = MASS + (0.5,)
+    ref0, phi, vel, st = _flow(skyr, n, h, model, dt, "energy", 80)
+    ref, rvel, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, model, dt, 0.0, 80)
+    assert st.arrests == rst.arrests
+    assert np.abs(phi - ref).max() < 1e-10
+    assert np.abs(vel - rvel).max() < 1e-9
