@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
 of the benchmark import this package; the product library never does.  It
 shares no code with the HIP path: the arithmetic lives in ``skyr_oracle.c``
 (compiled with gcc, no fast-math, no FMA contraction) and this module only
-marshals numpy arrays into it.
+marshals numpy arrays into it; ``moments.py`` evaluates the moment observables
+of Sec. 5 (centre of mass, radius, inertia tensors, quadrupole, D-term) in
+numpy on 2x2 complex matrices.
 
 Paper: arXiv:2604.25876 (cuSkyrmion).  Each wrapped routine names the passage
 it follows in the C source.  Field arrays are float64 of shape (4, n0, n1, n2),
