@@ -708,26 +708,50 @@ typedef struct {
 } ora_constituent;
 
 /* Sec. 4.1: unit vector n_R for R = p/q at the direction of x, in homogeneous
- * form.  With u = x1 + i x2 and w = r + x3, z = u/w; P(u,w) = sum p_k u^k
- * w^(B-k) and Q likewise, and
+ * form.  The point z = tan(theta/2) e^{i phi} of the Riemann sphere is written
+ * z = u / w with two charts: u = x1 + i x2, w = r + x3 on the upper half
+ * (x3 >= 0), and u = r - x3, w = x1 - i x2 on the lower half, which reaches the
+ * south pole z = infinity (u = 2r, w = 0) where the first chart gives 0/0.
+ * With P(u,w) = sum p_k u^k w^(B-k) and Q likewise,
  *   n_R = (2 Re(P conj Q), 2 Im(P conj Q), |Q|^2 - |P|^2) / (|P|^2 + |Q|^2),
- * which is (2 Re R, 2 Im R, 1 - |R|^2)/(1 + |R|^2) multiplied through by |Q|^2. */
-static void rational_map_direction(const ora_constituent *c, const double x[3], double nhat[3])
+ * which is (2 Re R, 2 Im R, 1 - |R|^2)/(1 + |R|^2) multiplied through by |Q|^2
+ * (a common factor of (u, w) cancels).  At x = 0 the direction is undefined;
+ * the north pole's is taken (the profile there gives f = prof_a). */
+static void cpow_mul(double *re, double *im, double br, double bi, int e)
 {
+    for (int k = 0; k < e; k++) {
+        double nr = *re * br - *im * bi, ni = *re * bi + *im * br;
+        *re = nr;
+        *im = ni;
+    }
+}
+
+static void rational_map_direction(const ora_constituent *c, const double x_in[3], double nhat[3])
+{
+    double x[3] = {x_in[0], x_in[1], x_in[2]};
     double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    double ur = x[0], ui = x[1], w = r + x[2];
+    if (r == 0.0) {
+        x[2] = 1.0;
+        r = 1.0;
+    }
+    double ur, ui, wr, wi;
+    if (x[2] >= 0.0) {
+        ur = x[0];
+        ui = x[1];
+        wr = r + x[2];
+        wi = 0.0;
+    } else {
+        ur = r - x[2];
+        ui = 0.0;
+        wr = x[0];
+        wi = -x[1];
+    }
     double Pr = 0, Pi = 0, Qr = 0, Qi = 0;
     for (int k = 0; k <= c->degree; k++) {
-        /* u^k (complex power) times w^(B-k) (real power) */
+        /* u^k w^(B-k) */
         double tr = 1.0, ti = 0.0;
-        for (int e = 0; e < k; e++) {
-            double nr = tr * ur - ti * ui, ni = tr * ui + ti * ur;
-            tr = nr;
-            ti = ni;
-        }
-        double wp = pow(w, (double)(c->degree - k));
-        tr *= wp;
-        ti *= wp;
+        cpow_mul(&tr, &ti, ur, ui, k);
+        cpow_mul(&tr, &ti, wr, wi, c->degree - k);
         Pr += c->p[k][0] * tr - c->p[k][1] * ti;
         Pi += c->p[k][0] * ti + c->p[k][1] * tr;
         Qr += c->q[k][0] * tr - c->q[k][1] * ti;

@@ -570,6 +570,41 @@ def test_hedgehog_is_rational_map_z():
     assert np.all(phi[0, ~I] == 1.0) and np.all(phi[1:, ~I] == 0.0)
 
 
+def test_rational_maps_on_every_direction_including_the_south_pole():
+    """Sec. 4.1 evaluated directly with complex numbers: z = (x1 + i x2)/(r + x3),
+    R = p(z)/q(z), n_R = (2 Re R, 2 Im R, 1 - |R|^2)/(1 + |R|^2), and on the
+    negative x3 axis (z = infinity) R = p_B/q_B (the hedgehog's q_1 = 0 gives
+    n_R = (0, 0, -1) there).  An odd lattice puts sites on
+    that axis and at the centre, where the field must stay finite (the profile
+    there gives f = pi, so phi = (-1, 0, 0, 0) to rounding)."""
+    n, h = 11, 0.3
+    x = coords(n, h)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    I = interior_mask((n, n, n))
+    s = 2.0 * math.sqrt(3.0) * 1j
+    for c, p, q in ((oracle.hedgehog(prof_lambda=0.9), [0, 1], [1, 0]),
+                    (oracle.cube_b4(prof_lambda=0.9), [1, 0, s, 0, 1], [1, 0, -s, 0, 1])):
+        phi = oracle.init_product((n, n, n), h, [c])
+        assert np.all(np.isfinite(phi))
+        f = math.pi * np.exp(-r / 0.9)
+        south = (np.abs(X) + np.abs(Y) == 0) & (Z < 0)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            z = (X + 1j * Y) / (r + Z)
+            R = np.polyval(p[::-1], z) / np.polyval(q[::-1], z)
+        nR = np.stack([2 * R.real, 2 * R.imag, 1 - np.abs(R) ** 2]) / (1 + np.abs(R) ** 2)
+        pB, qB = complex(p[-1]), complex(q[-1])  # R(infinity) = p_B / q_B (infinity when q_B = 0)
+        n_inf = np.array([2 * (pB * qB.conjugate()).real, 2 * (pB * qB.conjugate()).imag,
+                          abs(qB) ** 2 - abs(pB) ** 2]) / (abs(pB) ** 2 + abs(qB) ** 2)
+        nR[:, south] = n_inf[:, None]
+        ref = np.concatenate([np.cos(f)[None], np.sin(f) * nR])
+        keep = I & (r > 0)
+        np.testing.assert_allclose(phi[:, keep], ref[:, keep], atol=1e-13)
+        assert south[I].sum() >= 2
+        centre = (r == 0)
+        np.testing.assert_allclose(phi[:, centre].ravel(), [-1.0, 0.0, 0.0, 0.0], atol=1e-15)
+
+
 def test_product_and_isorotation_against_pauli_matrices():
     """The quaternion product and D(A) used for the product ansatz agree with
     explicit 2x2 matrix products U = U1 (A U2 A^dagger) (Sec. 4.2, Sec. 5.3)."""
