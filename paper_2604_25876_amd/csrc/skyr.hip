@@ -151,24 +151,36 @@ struct DevConstituent {
     double prof_a, prof_lambda;
 };
 
-// n_R of R = p/q at direction d (Sec. 4.1) in homogeneous form: with
-// u = x1 + i x2 and w = r + x3 (z = u / w), P(u, w) = sum_k p_k u^k w^(B-k),
+// n_R of R = p/q at direction d (Sec. 4.1) in homogeneous form, z = u / w:
+// u = x1 + i x2, w = r + x3 on the upper half (x3 >= 0); u = r - x3,
+// w = x1 - i x2 on the lower half, which reaches the south pole z = infinity
+// (w = 0) where the first pair is 0/0.  With P(u, w) = sum_k p_k u^k w^(B-k),
 // n_R = (2 Re(P conj Q), 2 Im(P conj Q), |Q|^2 - |P|^2) / (|P|^2 + |Q|^2).
-__device__ static void rm_direction(const DevConstituent& c, const double d[3], double nh[3])
+// At d = 0 the direction is undefined and the north pole's is used.
+__device__ static void rm_direction(const DevConstituent& c, const double d_in[3], double nh[3])
 {
-    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double ur = d[0], ui = d[1], w = r + d[2];
+    double d0 = d_in[0], d1 = d_in[1], d2 = d_in[2];
+    double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (r == 0.0) {
+        d2 = 1.0;
+        r = 1.0;
+    }
+    const bool upper = d2 >= 0.0;
+    const double ur = upper ? d0 : r - d2, ui = upper ? d1 : 0.0;
+    const double wr = upper ? r + d2 : d0, wi = upper ? 0.0 : -d1;
     double Pr = 0, Pi = 0, Qr = 0, Qi = 0;
+    double wkr = 1.0, wki = 0.0;  // w^(B-k)
     // homogeneous Horner scheme: P <- P u + p_k w^(B-k), k = B .. 0
     for (int k = c.degree; k >= 0; --k) {
         const double nPr = Pr * ur - Pi * ui, nPi = Pr * ui + Pi * ur;
         const double nQr = Qr * ur - Qi * ui, nQi = Qr * ui + Qi * ur;
-        double wp = 1.0;
-        for (int e = 0; e < c.degree - k; ++e) wp *= w;
-        Pr = nPr + c.p[k][0] * wp;
-        Pi = nPi + c.p[k][1] * wp;
-        Qr = nQr + c.q[k][0] * wp;
-        Qi = nQi + c.q[k][1] * wp;
+        Pr = nPr + (c.p[k][0] * wkr - c.p[k][1] * wki);
+        Pi = nPi + (c.p[k][0] * wki + c.p[k][1] * wkr);
+        Qr = nQr + (c.q[k][0] * wkr - c.q[k][1] * wki);
+        Qi = nQi + (c.q[k][0] * wki + c.q[k][1] * wkr);
+        const double tr = wkr * wr - wki * wi, ti = wkr * wi + wki * wr;
+        wkr = tr;
+        wki = ti;
     }
     const double cr = Pr * Qr + Pi * Qi, ci = Pi * Qr - Pr * Qi;
     const double p2 = Pr * Pr + Pi * Pi, q2 = Qr * Qr + Qi * Qi;

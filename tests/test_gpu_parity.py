@@ -74,6 +74,25 @@ def test_init_matches_oracle(skyr, prec, desc):
     assert np.abs(got - ref).max() < tol
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_init_on_an_odd_lattice_matches_oracle(skyr, prec):
+    """Odd lattice, constituents centred on sites: sites at each centre and on
+    the negative x3 axis through it (z = infinity of the rational map, Sec. 4.1)
+    stay finite and agree with the oracle."""
+    n, h = 41, 0.2
+    lat = skyr.Lattice.cube(n, h)
+    q = (0.6, 0.0, 0.8, 0.0)
+    cs = [skyr.cube_b4(X=(0.0, 0.0, 0.0), prof_lambda=1.2), skyr.constituent(1, [0, 1], [1], X=(1.0, -0.4, 0.6), quat=q)]
+    spec, keep = skyr.init_spec(skyr.INIT_PRODUCT, cs)
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    got = phi.double().cpu().numpy()
+    ref = oracle.init_product((n, n, n), h, [oracle.cube_b4(prof_lambda=1.2),
+                                             oracle.constituent(1, [0, 1], [1], X=(1.0, -0.4, 0.6), quat=q)])
+    assert np.all(np.isfinite(ref)) and np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() < (1e-13 if prec == 0 else 1e-7)
+
+
 def test_random_constituents_match_oracle(skyr):
     for seed, B in ((1, 10), (2**63 + 12345, 12), (7, 1)):
         a = skyr.random_constituents(seed, B, 3.0)
