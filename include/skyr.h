@@ -189,8 +189,9 @@ SKYR_API const char* skyr_version(void);
 /* Thread-local description of the last error of the calling thread ("" if none). */
 SKYR_API const char* skyr_last_error(void);
 
-/* Bytes of device workspace needed by skyr_energy_gradient, skyr_anf_step and
- * skyr_observables for this lattice and precision (0 on invalid arguments).
+/* Bytes of device workspace needed by skyr_energy_gradient, skyr_anf_step,
+ * skyr_observables and skyr_moments for this lattice and precision (0 on
+ * invalid arguments).
  * The workspace holds the flow's control block and one block of partial sums
  * per thread block; it must be 256-byte aligned and not shared by calls that
  * overlap in time. */
@@ -253,6 +254,36 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
  * (Sec. 2.1 eq. B0_components, Sec. 5.6 eq. Virial).  Synchronises `stream`. */
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                              const void* phi, skyr_obs* out, void* work, void* stream);
+
+/* Moment observables of a field (Sec. 5), in the printed (un-halved)
+ * normalisation of the Lagrangian, integrals as h^3 sums over the interior I
+ * with a_i the fourth-order first differences, coordinates x = (idx - (n-1)/2) h:
+ *   B       h^3 sum b (charge density b as in skyr_obs)
+ *   E       the total static energy in the printed normalisation (2 x skyr_obs.E)
+ *   X       centre of mass, (1/B) h^3 sum x b (eq. CoM); r = x - X below
+ *   R       RMS radius, ((1/B) h^3 sum |r|^2 b)^(1/2) (eq. RMS radius)
+ *   U, V, W isospin, spin and mixed inertia tensors (eqs. U, V, W inertia tensor),
+ *           with L_i = U^dagger d_i U, T_j = (i/2) U^dagger [tau^j, U]; row-major
+ *   Q       isospin-0 quadrupole, rho = b/2 (eq. Q tensor); row-major
+ *   D       monopole D-term (eq. D-term) with the static stress tensor of eq. Stress tensor
+ * The tensors contain the quadratic and quartic terms of the printed formulas
+ * only (the sextic term and potentials of Sec. 6 do not enter them). */
+typedef struct {
+    double B, E;
+    double X[3];
+    double R;
+    double U[9], V[9], W[9], Q[9];
+    double D;
+} skyr_moment_obs;
+
+/* Compute skyr_moment_obs of phi: one observables sweep for E, then two FP64
+ * passes over I (the charge and its first moments, then the tensor densities in
+ * the centre-of-mass frame), reduced in a fixed order on the device.
+ *   work  device workspace of skyr_workspace_bytes(lat, prec) bytes
+ * Returns SKYR_E_NONFINITE, with *out filled, when |B| < 1e-6 (no centre of
+ * mass) or a result is not finite.  Synchronises `stream`. */
+SKYR_API skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                  const void* phi, skyr_moment_obs* out, void* work, void* stream);
 
 /* Batches: many independent flows (uneven lattices, charges, masses and
  * precisions) advanced together.  Per sweep slot, one persistent launch per

@@ -18,6 +18,7 @@
 
 #include "../../include/skyr.h"
 #include "sweep.hpp"
+#include "moments.hpp"
 
 namespace skyr {
 
@@ -117,14 +118,22 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
 }
 
 constexpr size_t CTL_BYTES = 256;
-constexpr size_t OBS_BYTES = 256;
+// observables (8 doubles), then the moments' centre (4 doubles at +64) and result (at +128)
+constexpr size_t OBS_BYTES = 512;
+constexpr size_t MOM_CENTRE_OFFSET = 64;
+constexpr size_t MOM_OUT_OFFSET = 128;
+static_assert(MOM_OUT_OFFSET + MOM_OUT_DOUBLES * sizeof(double) <= OBS_BYTES, "moment result must fit");
+static_assert(sizeof(skyr_moment_obs) == MOM_OUT_DOUBLES * sizeof(double), "moment record layout");
 
-// enough partial-sum slots for every shape and slab length >= the shortest supported
+// enough partial-sum slots for every shape and slab length >= the shortest
+// supported, and for the moment passes
 static size_t workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
 {
     int most = 0;
     for (int v = 0; v < shape_count(prec); ++v) most = std::max(most, plan_with(lat, prec, v, kMinChunk).blocks());
-    return CTL_BYTES + OBS_BYTES + (size_t)most * NPART * sizeof(double);
+    const size_t sweep_part = (size_t)most * NPART * sizeof(double);
+    const size_t mom_part = (size_t)MOM_MAX_BLOCKS * MOM_NACC * sizeof(double);
+    return CTL_BYTES + OBS_BYTES + std::max(sweep_part, mom_part);
 }
 
 static skyr_status check_lattice(const skyr_lattice* lat, skyr_precision prec)
@@ -743,6 +752,52 @@ skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const
     out->virial = o[5];
     out->max_force = o[6];
     out->E6 = o[7];
+    return SKYR_OK;
+}
+
+skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
+                         skyr_moment_obs* out, void* work, void* stream)
+{
+    skyr_status st = check_common(lat, prec, model, phi, work);
+    if (st != SKYR_OK) return st;
+    if (!out) return fail(SKYR_E_INVAL, "out must be non-null");
+    hipStream_t s = (hipStream_t)stream;
+    double o[8];
+    st = run_gradient(lat, prec, model, phi, nullptr, 0, 1, o, work, s);  // E on the device at obs[0]
+    if (st != SKYR_OK) return st;
+    char* w = (char*)work;
+    MomArgs m;
+    m.phi = phi;
+    m.n0 = lat->n[0];
+    m.n1 = lat->n[1];
+    m.n2 = lat->n[2];
+    m.h = lat->h;
+    m.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+    m.obs = (const double*)(w + CTL_BYTES);
+    m.centre = (double*)(w + CTL_BYTES + MOM_CENTRE_OFFSET);
+    m.out = (double*)(w + CTL_BYTES + MOM_OUT_OFFSET);
+    const long long nI = (long long)(lat->n[0] - 4) * (lat->n[1] - 4) * (lat->n[2] - 4);
+    const int nb = (int)std::min<long long>(MOM_MAX_BLOCKS, (nI + MOM_THREADS - 1) / MOM_THREADS);
+    if (prec == SKYR_F64)
+        hipLaunchKernelGGL((moments_kernel<double, MOM_PASS_CENTRE>), dim3(nb), dim3(MOM_THREADS), 0, s, m);
+    else
+        hipLaunchKernelGGL((moments_kernel<float, MOM_PASS_CENTRE>), dim3(nb), dim3(MOM_THREADS), 0, s, m);
+    SKYR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(moments_centre_kernel, dim3(1), dim3(MOM_THREADS), 0, s, m, nb);
+    SKYR_HIP(hipGetLastError());
+    if (prec == SKYR_F64)
+        hipLaunchKernelGGL((moments_kernel<double, MOM_PASS_TENSORS>), dim3(nb), dim3(MOM_THREADS), 0, s, m);
+    else
+        hipLaunchKernelGGL((moments_kernel<float, MOM_PASS_TENSORS>), dim3(nb), dim3(MOM_THREADS), 0, s, m);
+    SKYR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(moments_finish_kernel, dim3(1), dim3(MOM_THREADS), 0, s, m, nb);
+    SKYR_HIP(hipGetLastError());
+    SKYR_HIP(hipMemcpyAsync(out, m.out, sizeof(skyr_moment_obs), hipMemcpyDeviceToHost, s));
+    SKYR_HIP(hipStreamSynchronize(s));
+    if (!(std::fabs(out->B) >= 1e-6)) return fail(SKYR_E_NONFINITE, "|B| < 1e-6: the centre of mass is undefined");
+    const double* v = &out->B;
+    for (int k = 0; k < MOM_OUT_DOUBLES; ++k)
+        if (!std::isfinite(v[k])) return fail(SKYR_E_NONFINITE, "a moment observable is not finite");
     return SKYR_OK;
 }
 

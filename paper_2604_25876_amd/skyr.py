@@ -79,6 +79,22 @@ class Obs(ctypes.Structure):
         return {k: float(getattr(self, k)) for k, _ in self._fields_}
 
 
+class MomentObs(ctypes.Structure):
+    """Mirror of skyr_moment_obs: B, E (printed normalisation), X, R and the
+    row-major 3x3 tensors U, V, W, Q, then D."""
+    _fields_ = [("B", ctypes.c_double), ("E", ctypes.c_double), ("X", ctypes.c_double * 3), ("R", ctypes.c_double),
+                ("U", ctypes.c_double * 9), ("V", ctypes.c_double * 9), ("W", ctypes.c_double * 9),
+                ("Q", ctypes.c_double * 9), ("D", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        import numpy as np
+        out = {k: float(getattr(self, k)) for k in ("B", "E", "R", "D")}
+        out["X"] = np.array(list(self.X))
+        for k in ("U", "V", "W", "Q"):
+            out[k] = np.array(list(getattr(self, k))).reshape(3, 3)
+        return out
+
+
 class AnfState(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("arrests", ctypes.c_int64), ("redo_sweeps", ctypes.c_int64),
                 ("sweeps", ctypes.c_int64), ("E_prev", ctypes.c_double), ("E", ctypes.c_double),
@@ -106,6 +122,8 @@ _SIGNATURES = {
     "skyr_anf_step": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState), ctypes.c_int64, _P,
                                      _P]),
+    "skyr_moments": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
+                                    ctypes.POINTER(MomentObs), _P, _P]),
     "skyr_observables": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
                                         ctypes.POINTER(Obs), _P, _P]),
     "skyr_tile_variants": (ctypes.c_int32, [ctypes.c_int]),
@@ -273,6 +291,16 @@ def observables(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -
     return obs.as_dict()
 
 
+def moments(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> dict:
+    """Centre of mass, RMS radius, inertia tensors U, V, W, quadrupole Q and
+    D-term of phi (skyr_moments); tensors as 3x3 numpy arrays."""
+    out = MomentObs()
+    _check(lib().skyr_moments(ctypes.byref(lat), prec, ctypes.byref(model),
+                              _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), ctypes.byref(out),
+                              _dev_ptr(work), _stream(stream)))
+    return out.as_dict()
+
+
 def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.pi,
             prof_lambda: float = 1.0) -> Constituent:
     """R(z) = (z^4 + 2 sqrt3 i z^2 + 1) / (z^4 - 2 sqrt3 i z^2 + 1): the O_h map of Table RMA."""
@@ -282,14 +310,17 @@ def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.p
 
 def spec_from_description(init: dict):
     """InitSpec (and its keepalive) for an initial-data description
-    {"kind": "hedgehog" | "cube_b4" | "random_product", ...}."""
+    {"kind": "hedgehog" | "cube_b4" | "random_product", ...}; a cube_b4 takes an
+    optional centre "X" and isorotation quaternion "quat"."""
     kind = init["kind"]
     lam = float(init.get("prof_lambda", 1.0))
     a = float(init.get("prof_a", math.pi))
     if kind == "hedgehog":
         return init_spec(INIT_HEDGEHOG, prof_a=a, prof_lambda=lam)
     if kind == "cube_b4":
-        return init_spec(INIT_RATIONAL_MAP, [cube_b4(prof_a=a, prof_lambda=lam)])
+        return init_spec(INIT_RATIONAL_MAP, [cube_b4(X=tuple(init.get("X", (0.0, 0.0, 0.0))),
+                                                     quat=tuple(init.get("quat", (1.0, 0.0, 0.0, 0.0))),
+                                                     prof_a=a, prof_lambda=lam)])
     if kind == "random_product":
         return init_spec(INIT_RANDOM_PRODUCT, B=int(init["B"]), seed=int(init["seed"]),
                          ball_radius=float(init.get("radius", 3.0)), prof_a=a, prof_lambda=lam)

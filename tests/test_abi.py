@@ -36,6 +36,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16
     assert ctypes.sizeof(skyr.Obs) == 64
     assert ctypes.sizeof(skyr.AnfState) == 4 * 8 + 3 * 8 + 4 * 4
+    assert ctypes.sizeof(skyr.MomentObs) == 43 * 8
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -47,7 +48,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     names = {"skyr_lattice": skyr.Lattice, "skyr_model": skyr.Model, "skyr_flow": skyr.Flow,
              "skyr_constituent": skyr.Constituent, "skyr_init_spec": skyr.InitSpec, "skyr_obs": skyr.Obs,
-             "skyr_anf_state": skyr.AnfState}
+             "skyr_anf_state": skyr.AnfState, "skyr_moment_obs": skyr.MomentObs}
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "skyr.h"\nint main(void){\n' +
                    "".join(f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n")
@@ -62,7 +63,7 @@ def test_workspace_bytes():
     lat = skyr.Lattice.cube(256, 0.1)
     for prec in (skyr.F64, skyr.F32_BULK):
         b = skyr.workspace_bytes(lat, prec)
-        assert b >= 512 and b % 64 == 0
+        assert b >= 512 + 1024 * 32 * 8 and b % 64 == 0  # control, observables, moment partial sums
     assert skyr.workspace_bytes(skyr.Lattice.cube(4, 0.1), skyr.F64) == 0
     assert skyr.workspace_bytes(skyr.Lattice.cube(40, -1.0), skyr.F64) == 0
     assert skyr.workspace_bytes(lat, 7) == 0
