@@ -124,6 +124,27 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, m
         traffic=recorded_traffic(prec_name, tile))
 
 
+def time_moments(skyr, torch, w, prec_name, reps=5):
+    """Wall time of skyr_moments (an observables sweep, then the two FP64
+    moment passes; each call synchronises) on the workload's initial field."""
+    prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
+    lat = skyr.Lattice.cube(w["n"], w["h"])
+    spec, keep = skyr.spec_from_description(w["init"])
+    dev = torch.device("cuda:0")
+    phi = skyr.new_field(lat, prec, dev)
+    skyr.init_field(lat, prec, spec, phi)
+    work = skyr.new_workspace(lat, prec, dev)
+    model = skyr.Model(w["m"])
+    res = skyr.moments(lat, prec, model, phi, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = skyr.moments(lat, prec, model, phi, work)
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    interior = (w["n"] - 4) ** 3
+    return {"ms_per_call": ms, "interior_sites_per_s": interior / (ms / 1e3), "B": res["B"], "R": res["R"]}
+
+
 def sweep_tiles(skyr, torch, w, prec_name, steps=20):
     """Time every compiled shape and slab length on the workload (flow steps
     from the initial field); one line per candidate."""
@@ -316,10 +337,12 @@ def main():
     print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
     r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup, tiles["f64"])
     print(f"# f64: {r64}", file=sys.stderr, flush=True)
-    # the kernel variant with the program's other potentials and the sextic term (Sec. 6), FP32-bulk
+    # the kernel variant with the program's other potentials and the sextic term (Sec. 7.7), FP32-bulk
     ext_model = (W["m"], 0.5, 0.5, 0.5, 0.1)
     rext = run_flow(skyr, torch, W, "f32", max(args.steps // 5, 20), args.warmup, tiles["f32"], masses=ext_model)
     print(f"# f32-bulk, four potentials and sextic term: {rext}", file=sys.stderr, flush=True)
+    moments = {p: time_moments(skyr, torch, W, p) for p in ("f32", "f64")}
+    print(f"# moments: {moments}", file=sys.stderr, flush=True)
     batch = serve = None
     if not args.no_batch:
         from skyr_inputs import batch_jobs
@@ -356,6 +379,7 @@ def main():
         "f32_extended_model": {"m_my_mz_mw_c6": list(ext_model), "value": rext["site_updates_per_s"],
                                "sweep_kernel_avg_us": rext["sweep_kernel_avg_us"], "steps": rext["steps"],
                                "E": rext["E"]},
+        "moments": moments,
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

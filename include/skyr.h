@@ -70,7 +70,7 @@ typedef struct {
     double h;
 } skyr_lattice;
 
-/* Model couplings (Sec. 2.1 and the program's four potentials and sextic term, Sec. 6),
+/* Model couplings (Sec. 2.1 and the program's four potentials and sextic term, Sec. 7.7),
  * in this library's energy normalisation (one half of the printed density):
  *   V(phi0) = m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
  *   e6      = (c6 / 2) det[phi, a_1, a_2, a_3]^2        (a_i the derivatives of phi)
@@ -85,7 +85,7 @@ typedef struct {
     double c6;
 } skyr_model;
 
-/* Flow mode (Sec. 3; the program's flow modes, Sec. 6).
+/* Flow mode (Sec. 3; the program's flow modes, Sec. 7.5).
  *   SKYR_ARREST_ENERGY  arrested Newton flow with the paper's rule: arrest at step k
  *                       when E_k > E_{k-1} (strict; E_{-1} = +inf).
  *   SKYR_ARREST_POWER   arrested Newton flow, arresting when the power
@@ -132,8 +132,12 @@ typedef enum {
 
 /* One constituent of a product (Sec. 4.1, 4.2): the degree-`degree` rational
  * map R = p/q (p(z) = sum_k p[k] z^k, complex coefficients as (re, im)),
- * profile f(r) = prof_a exp(-r / prof_lambda), centre X, and isorotation by the
- * unit quaternion quat = (a0, a1, a2, a3), A = a0 + i a.tau, U -> A U A^dagger. */
+ * profile f(r) = prof_a exp(-r / prof_lambda), centre X, isorotation by the
+ * unit quaternion quat = (a0, a1, a2, a3), A = a0 + i a.tau, U -> A U A^dagger,
+ * and spatial orientation by the unit quaternion orient = B (Sec. 5.3): the
+ * constituent is A U_R(D(B)^T (x - X)) A^dagger with D(B)_ij =
+ * (1/2) Tr(tau^i B tau^j B^dagger), i.e. turned by the rotation D(B) about its
+ * centre; orient = (0, 0, 0, 0) means no rotation. */
 typedef struct {
     int32_t degree; /* 1..8 */
     int32_t _pad;
@@ -143,6 +147,7 @@ typedef struct {
     double quat[4];
     double prof_a;
     double prof_lambda;
+    double orient[4];
 } skyr_constituent;
 
 typedef struct {
@@ -207,6 +212,12 @@ SKYR_API size_t skyr_workspace_bytes(const skyr_lattice* lat, skyr_precision pre
 SKYR_API skyr_status skyr_random_constituents(uint64_t seed, int32_t B, double radius, double prof_a, double prof_lambda,
                                      skyr_constituent* out);
 
+/* Orientation quaternion B for the Euler angles of the program's configuration
+ * files (Sec. 7.3.1: a rotation about z, then about y, then about z, in radians):
+ * D(B) = R_z(a[0]) R_y(a[1]) R_z(a[2]), with R_n(t) the right-handed rotation by
+ * t about axis n and D as in skyr_constituent.  out: 4 doubles, b0 >= 0. */
+SKYR_API void skyr_orientation_zyz(const double angles[3], double out[4]);
+
 /* Fill phi (device, layout above) with initial data (Sec. 4): the product
  * U = prod_k A_k U_k(x - X_k) A_k^dagger (eq. Product ansatz) of rational-map
  * fields U_k = exp(i f(r) n_R . tau) (Sec. 4.1), evaluated in double and
@@ -267,7 +278,7 @@ SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision pr
  *   Q       isospin-0 quadrupole, rho = b/2 (eq. Q tensor); row-major
  *   D       monopole D-term (eq. D-term) with the static stress tensor of eq. Stress tensor
  * The tensors contain the quadratic and quartic terms of the printed formulas
- * only (the sextic term and potentials of Sec. 6 do not enter them). */
+ * only (the sextic term and potentials of Sec. 7.7 do not enter them). */
 typedef struct {
     double B, E;
     double X[3];

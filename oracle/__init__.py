@@ -57,7 +57,7 @@ class Constituent(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("_pad", ctypes.c_int32),
                 ("p", (ctypes.c_double * 2) * 9), ("q", (ctypes.c_double * 2) * 9),
                 ("X", ctypes.c_double * 3), ("quat", ctypes.c_double * 4),
-                ("prof_a", ctypes.c_double), ("prof_lambda", ctypes.c_double)]
+                ("prof_a", ctypes.c_double), ("prof_lambda", ctypes.c_double), ("orient", ctypes.c_double * 4)]
 
 
 def _load():
@@ -270,8 +270,9 @@ def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, 
 
 # ------------------------------------------------------------------------ init
 def constituent(degree: int, p, q, X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.pi,
-                prof_lambda: float = 1.0) -> Constituent:
-    """Build a constituent from complex coefficient lists p, q (index = power of z)."""
+                prof_lambda: float = 1.0, orient=None) -> Constituent:
+    """Build a constituent from complex coefficient lists p, q (index = power of z);
+    orient: quaternion of its spatial rotation (None: unturned)."""
     c = Constituent()
     c.degree = int(degree)
     for k, v in enumerate(p):
@@ -281,18 +282,21 @@ def constituent(degree: int, p, q, X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0),
     c.X[:] = list(map(float, X))
     c.quat[:] = list(map(float, quat))
     c.prof_a, c.prof_lambda = float(prof_a), float(prof_lambda)
+    c.orient[:] = [0.0] * 4 if orient is None else list(map(float, orient))
     return c
 
 
-def hedgehog(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a=math.pi, prof_lambda=1.0) -> Constituent:
+def hedgehog(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a=math.pi, prof_lambda=1.0,
+             orient=None) -> Constituent:
     """R(z) = z (Table RMA, B = 1)."""
-    return constituent(1, [0, 1], [1], X, quat, prof_a, prof_lambda)
+    return constituent(1, [0, 1], [1], X, quat, prof_a, prof_lambda, orient)
 
 
-def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a=math.pi, prof_lambda=1.0) -> Constituent:
+def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a=math.pi, prof_lambda=1.0,
+            orient=None) -> Constituent:
     """R(z) = (z^4 + 2 sqrt3 i z^2 + 1)/(z^4 - 2 sqrt3 i z^2 + 1) (Table RMA, B = 4, O_h)."""
     s = 2.0 * math.sqrt(3.0) * 1j
-    return constituent(4, [1, 0, s, 0, 1], [1, 0, -s, 0, 1], X, quat, prof_a, prof_lambda)
+    return constituent(4, [1, 0, s, 0, 1], [1, 0, -s, 0, 1], X, quat, prof_a, prof_lambda, orient)
 
 
 def init_product(shape, h: float, constituents) -> np.ndarray:

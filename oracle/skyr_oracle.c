@@ -154,7 +154,7 @@ static double dot4(const double *u, const double *v)
 
 static double det4(const double c0[4], const double c1[4], const double c2[4], const double c3[4]);
 
-/* Sextic (BPS-Skyrme) term at one interior site (Sec. 6: c6 4 pi^4 (B0)^2 in the
+/* Sextic (BPS-Skyrme) term at one interior site (Sec. 7.7: c6 4 pi^4 (B0)^2 in the
  * printed normalisation, halved here, with B0 = b = -(1/2 pi^2) det[phi, a_1, a_2, a_3]):
  *   e6 = c6 det^2 / 2.
  * det is linear in each column, so its derivative with respect to column k is the
@@ -183,7 +183,7 @@ static void laplacian_at(const double *phi, const int n[3], double h, int x, int
     }
 }
 
-/* Potential density of phi0 (Sec. 6, the four potentials of the program, in this
+/* Potential density of phi0 (Sec. 7.7, the four potentials of the program, in this
  * energy's normalisation, i.e. halved):
  *   V = m_x^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2 + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4
  * mass = {m_x, m_y, m_z, m_w, c6} (the model constants); m_x is the pion mass m of Sec. 2.1. */
@@ -615,7 +615,7 @@ ORA_API double ora_power(const int n[3], double h, const double *gT, const doubl
  *             stop if max|F_n| < tol;
  *             v_{n+1} = v_n + dt F_n; phi_{n+1} = normalise(phi_n + dt v_{n+1}).
  * arrest = 0 gives the plain Newton flow (no resets); arrest = 3 the gradient
- * flow (Sec. 6, the program's flow modes): phi_{n+1} = normalise(phi_n + dt F_n),
+ * flow (Sec. 7.5, the program's flow modes): phi_{n+1} = normalise(phi_n + dt F_n),
  * the velocity stays zero.
  * E_trace / arrest_trace (nullable) receive E_n and the reset flag for each
  * evaluated step, indexed from the step count on entry.
@@ -696,7 +696,9 @@ ORA_API int64_t ora_anf(const int n[3], double h, const double *mass, double dt,
 
 /* One constituent of a product: a degree-B rational map (B = 1 is the
  * hedgehog R = z) with profile f(r) = prof_a * exp(-r / prof_lambda), centred
- * at X and isorotated by the unit quaternion q = (q0, q1, q2, q3). */
+ * at X, isorotated by the unit quaternion q = (q0, q1, q2, q3) and turned in
+ * space by the rotation D(orient) about X (Sec. 5.3: U(r) -> U(D^-1 r));
+ * orient = 0 means unturned. */
 typedef struct {
     int32_t degree;      /* polynomial degree of p and q */
     int32_t _pad;
@@ -705,6 +707,7 @@ typedef struct {
     double X[3];
     double quat[4];
     double prof_a, prof_lambda;
+    double orient[4];
 } ora_constituent;
 
 /* Sec. 4.1: unit vector n_R for R = p/q at the direction of x, in homogeneous
@@ -792,6 +795,14 @@ static void su2_mul(const double a[4], const double b[4], double out[4])
 static void constituent_field(const ora_constituent *c, const double x[3], double U[4])
 {
     double d[3] = {x[0] - c->X[0], x[1] - c->X[1], x[2] - c->X[2]};
+    if (c->orient[0] != 0.0 || c->orient[1] != 0.0 || c->orient[2] != 0.0 || c->orient[3] != 0.0) {
+        /* D(B)^-1 = D(B^dagger), B^dagger = (b0, -b) */
+        double binv[4] = {c->orient[0], -c->orient[1], -c->orient[2], -c->orient[3]}, dd[3];
+        isorotate(binv, d, dd);
+        d[0] = dd[0];
+        d[1] = dd[1];
+        d[2] = dd[2];
+    }
     double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double f = c->prof_a * exp(-r / c->prof_lambda);
     double nhat[3], rot[3];

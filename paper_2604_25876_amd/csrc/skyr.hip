@@ -158,6 +158,8 @@ struct DevConstituent {
     double p[9][2], q[9][2];
     double X[3], quat[4];
     double prof_a, prof_lambda;
+    double orient[4];  // spatial orientation B (identity when rotated == 0)
+    int rotated;
 };
 
 // n_R of R = p/q at direction d (Sec. 4.1) in homogeneous form, z = u / w:
@@ -215,7 +217,20 @@ __global__ void init_kernel(T* __restrict__ phi, int n0, int n1, int n2, double 
         const double x[3] = {(ix - 0.5 * (n0 - 1)) * h, (iy - 0.5 * (n1 - 1)) * h, (iz - 0.5 * (n2 - 1)) * h};
         for (int k = 0; k < nc; ++k) {
             const DevConstituent& c = cs[k];
-            const double d[3] = {x[0] - c.X[0], x[1] - c.X[1], x[2] - c.X[2]};
+            double d[3] = {x[0] - c.X[0], x[1] - c.X[1], x[2] - c.X[2]};
+            if (c.rotated) {
+                // d <- D(B)^T d = D(B^dagger) d: with b -> -b in
+                // D(B) v = (b0^2 - |b|^2) v + 2 (b.v) b - 2 b0 (b x v)
+                const double b0 = c.orient[0], b1 = c.orient[1], b2 = c.orient[2], b3 = c.orient[3];
+                const double kb = b0 * b0 - (b1 * b1 + b2 * b2 + b3 * b3);
+                const double bd = b1 * d[0] + b2 * d[1] + b3 * d[2];
+                const double e0 = kb * d[0] + 2.0 * bd * b1 + 2.0 * b0 * (b2 * d[2] - b3 * d[1]);
+                const double e1 = kb * d[1] + 2.0 * bd * b2 + 2.0 * b0 * (b3 * d[0] - b1 * d[2]);
+                const double e2 = kb * d[2] + 2.0 * bd * b3 + 2.0 * b0 * (b1 * d[1] - b2 * d[0]);
+                d[0] = e0;
+                d[1] = e1;
+                d[2] = e2;
+            }
             const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             const double f = c.prof_a * exp(-r / c.prof_lambda);
             double nh[3];
@@ -599,6 +614,29 @@ skyr_status skyr_random_constituents(uint64_t seed, int32_t B, double radius, do
     return SKYR_OK;
 }
 
+// B(n, t) = cos(t/2) - i sin(t/2) n.tau has D(B) = the right-handed rotation by
+// t about n (D(B) v = (b0^2 - |b|^2) v + 2 (b.v) b - 2 b0 (b x v) with
+// b = -sin(t/2) n is Rodrigues' formula), and D(B1 B2) = D(B1) D(B2).
+void skyr_orientation_zyz(const double angles[3], double out[4])
+{
+    const double cz1 = std::cos(0.5 * angles[0]), sz1 = std::sin(0.5 * angles[0]);
+    const double cy = std::cos(0.5 * angles[1]), sy = std::sin(0.5 * angles[1]);
+    const double cz2 = std::cos(0.5 * angles[2]), sz2 = std::sin(0.5 * angles[2]);
+    // quaternion product (a0 + i a.tau)(c0 + i c.tau) = (a0 c0 - a.c) + i (a0 c + c0 a - a x c).tau
+    auto mul = [](const double a[4], const double c[4], double o[4]) {
+        o[0] = a[0] * c[0] - (a[1] * c[1] + a[2] * c[2] + a[3] * c[3]);
+        o[1] = a[0] * c[1] + c[0] * a[1] - (a[2] * c[3] - a[3] * c[2]);
+        o[2] = a[0] * c[2] + c[0] * a[2] - (a[3] * c[1] - a[1] * c[3]);
+        o[3] = a[0] * c[3] + c[0] * a[3] - (a[1] * c[2] - a[2] * c[1]);
+    };
+    const double Bz1[4] = {cz1, 0.0, 0.0, -sz1}, By[4] = {cy, 0.0, -sy, 0.0}, Bz2[4] = {cz2, 0.0, 0.0, -sz2};
+    double t[4];
+    mul(Bz1, By, t);
+    mul(t, Bz2, out);
+    if (out[0] < 0.0)
+        for (int k = 0; k < 4; ++k) out[k] = -out[k];
+}
+
 skyr_status skyr_init_field(const skyr_lattice* lat, skyr_precision prec, const skyr_init_spec* spec, void* phi,
                             void* stream)
 {
@@ -619,6 +657,8 @@ skyr_status skyr_init_field(const skyr_lattice* lat, skyr_precision prec, const 
         std::memcpy(d.quat, c.quat, sizeof d.quat);
         d.prof_a = c.prof_a;
         d.prof_lambda = c.prof_lambda;
+        std::memcpy(d.orient, c.orient, sizeof d.orient);
+        d.rotated = c.orient[0] != 0.0 || c.orient[1] != 0.0 || c.orient[2] != 0.0 || c.orient[3] != 0.0;
         return true;
     };
     switch (spec->kind) {

@@ -275,7 +275,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
 
     // potential density V(phi0) and dV/dphi0: m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2
     // + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4 (the program's four potentials,
-    // Sec. 6, halved to this energy's normalisation)
+    // Sec. 7.7, halved to this energy's normalisation)
     __device__ __forceinline__ T potential(T p0) const
     {
         const T u = T(1) - p0;

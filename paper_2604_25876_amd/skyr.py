@@ -63,7 +63,7 @@ class Constituent(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("_pad", ctypes.c_int32),
                 ("p", (ctypes.c_double * 2) * 9), ("q", (ctypes.c_double * 2) * 9),
                 ("X", ctypes.c_double * 3), ("quat", ctypes.c_double * 4),
-                ("prof_a", ctypes.c_double), ("prof_lambda", ctypes.c_double)]
+                ("prof_a", ctypes.c_double), ("prof_lambda", ctypes.c_double), ("orient", ctypes.c_double * 4)]
 
 
 class InitSpec(ctypes.Structure):
@@ -122,6 +122,7 @@ _SIGNATURES = {
     "skyr_anf_step": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState), ctypes.c_int64, _P,
                                      _P]),
+    "skyr_orientation_zyz": (None, [ctypes.POINTER(ctypes.c_double * 3), ctypes.POINTER(ctypes.c_double * 4)]),
     "skyr_moments": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
                                     ctypes.POINTER(MomentObs), _P, _P]),
     "skyr_observables": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
@@ -220,7 +221,9 @@ def new_workspace(lat: Lattice, prec: int, device="cuda"):
 
 
 def constituent(degree: int, p, q, X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.pi,
-                prof_lambda: float = 1.0) -> Constituent:
+                prof_lambda: float = 1.0, orient=None) -> Constituent:
+    """A rational-map constituent; orient: spatial orientation quaternion
+    (None = unrotated), e.g. from orientation_zyz."""
     c = Constituent()
     c.degree = int(degree)
     for k, v in enumerate(p):
@@ -230,7 +233,15 @@ def constituent(degree: int, p, q, X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0),
     c.X[:] = [float(v) for v in X]
     c.quat[:] = [float(v) for v in quat]
     c.prof_a, c.prof_lambda = float(prof_a), float(prof_lambda)
+    c.orient[:] = [0.0] * 4 if orient is None else [float(v) for v in orient]
     return c
+
+
+def orientation_zyz(a1: float, a2: float, a3: float) -> tuple:
+    """Quaternion B with D(B) = R_z(a1) R_y(a2) R_z(a3) (skyr_orientation_zyz)."""
+    ang, out = (ctypes.c_double * 3)(a1, a2, a3), (ctypes.c_double * 4)()
+    lib().skyr_orientation_zyz(ang, out)
+    return tuple(out)
 
 
 def random_constituents(seed: int, B: int, radius: float = 3.0, prof_a: float = math.pi,
@@ -302,10 +313,10 @@ def moments(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> di
 
 
 def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.pi,
-            prof_lambda: float = 1.0) -> Constituent:
+            prof_lambda: float = 1.0, orient=None) -> Constituent:
     """R(z) = (z^4 + 2 sqrt3 i z^2 + 1) / (z^4 - 2 sqrt3 i z^2 + 1): the O_h map of Table RMA."""
     s = 2.0 * math.sqrt(3.0) * 1j
-    return constituent(4, [1, 0, s, 0, 1], [1, 0, -s, 0, 1], X, quat, prof_a, prof_lambda)
+    return constituent(4, [1, 0, s, 0, 1], [1, 0, -s, 0, 1], X, quat, prof_a, prof_lambda, orient)
 
 
 def spec_from_description(init: dict):

@@ -33,7 +33,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(skyr.Lattice) == 24
     assert ctypes.sizeof(skyr.Model) == 40
     assert ctypes.sizeof(skyr.Flow) == 32
-    assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16
+    assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16 + 4 * 8
     assert ctypes.sizeof(skyr.Obs) == 64
     assert ctypes.sizeof(skyr.AnfState) == 4 * 8 + 3 * 8 + 4 * 4
     assert ctypes.sizeof(skyr.MomentObs) == 43 * 8
@@ -141,3 +141,25 @@ def test_random_constituents_match_oracle_draws():
         for ca, cb in zip(a, b):
             assert list(ca.X) == list(cb.X)
             assert list(ca.quat) == pytest.approx(list(cb.quat), abs=1e-15)
+
+
+def test_orientation_zyz_is_the_product_of_axis_rotations():
+    """skyr_orientation_zyz(a, b, c) = B with the printed D(B)_ij =
+    (1/2) Tr(tau^i B tau^j B^dagger) equal to R_z(a) R_y(b) R_z(c)."""
+    import numpy as np
+    pauli = [np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+
+    def rz(t):
+        return np.array([[math.cos(t), -math.sin(t), 0], [math.sin(t), math.cos(t), 0], [0, 0, 1]])
+
+    def ry(t):
+        return np.array([[math.cos(t), 0, math.sin(t)], [0, 1, 0], [-math.sin(t), 0, math.cos(t)]])
+
+    rng = np.random.default_rng(11)
+    for a in [(1.57079, 1.57079, -1.57079), (3.14159, 0.0, 0.0)] + [tuple(rng.uniform(-4, 4, 3)) for _ in range(4)]:
+        B = skyr.orientation_zyz(*a)
+        assert abs(sum(v * v for v in B) - 1.0) < 1e-14 and B[0] >= 0.0
+        Bm = B[0] * np.eye(2) + 1j * sum(B[k + 1] * pauli[k] for k in range(3))
+        D = np.array([[0.5 * np.trace(pauli[i] @ Bm @ pauli[j] @ Bm.conj().T).real for j in range(3)]
+                      for i in range(3)])
+        np.testing.assert_allclose(D, rz(a[0]) @ ry(a[1]) @ rz(a[2]), atol=1e-14)

@@ -1,4 +1,4 @@
-"""GPU parity of the flow modes and model terms of the program (Sec. 6): the
+"""GPU parity of the flow modes and model terms of the program (Sec. 7.5 and 7.7): the
 modified pion mass, loosely and lightly bound potentials on top of the pion
 mass, the sextic (BPS-Skyrme) term, the plain Newton flow and the first-order
 gradient flow, against the FP64 oracle on identical inputs."""

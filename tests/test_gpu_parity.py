@@ -93,6 +93,27 @@ def test_init_on_an_odd_lattice_matches_oracle(skyr, prec):
     assert np.abs(got - ref).max() < (1e-13 if prec == 0 else 1e-7)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_oriented_constituents_match_oracle(skyr, prec):
+    """Constituents turned in space (Sec. 5.3) by Euler angles (Sec. 7.3.1):
+    the two-cube chain of the program's example configuration and a turned,
+    isorotated hedgehog, against the oracle on the same quaternions."""
+    n, h = 48, 0.2
+    lat = skyr.Lattice.cube(n, h)
+    B = skyr.orientation_zyz(1.57079, 1.57079, -1.57079)
+    Bh = skyr.orientation_zyz(0.3, -1.1, 2.0)
+    q = (0.6, 0.0, 0.8, 0.0)
+    lib_cs = [skyr.cube_b4(X=(-1.5, 0.0, 0.0)), skyr.cube_b4(X=(1.5, 0.0, 0.0), orient=B),
+              skyr.constituent(1, [0, 1], [1], X=(0.3, 2.1, -0.7), quat=q, orient=Bh)]
+    ora_cs = [oracle.cube_b4(X=(-1.5, 0.0, 0.0)), oracle.cube_b4(X=(1.5, 0.0, 0.0), orient=B),
+              oracle.constituent(1, [0, 1], [1], X=(0.3, 2.1, -0.7), quat=q, orient=Bh)]
+    spec, keep = skyr.init_spec(skyr.INIT_PRODUCT, lib_cs)
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    ref = oracle.init_product((n, n, n), h, ora_cs)
+    assert np.abs(phi.double().cpu().numpy() - ref).max() < (1e-13 if prec == 0 else 1e-7)
+
+
 def test_random_constituents_match_oracle(skyr):
     for seed, B in ((1, 10), (2**63 + 12345, 12), (7, 1)):
         a = skyr.random_constituents(seed, B, 3.0)

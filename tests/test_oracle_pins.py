@@ -183,7 +183,7 @@ def test_gradient_bruteforce_with_all_potentials_and_sextic():
 def test_sextic_energy_of_the_hedgehog_against_radial_quadrature():
     """E6 of the unrelaxed hedgehog f = pi (1 - tanh r) converges at fourth order
     to 2 pi c6 int f'^2 sin^4 f / r^2 dr, the continuum value of c6 det^2 / 2 with
-    det = f' sin^2 f / r^2 for the hedgehog (Sec. 6 sextic term, halved)."""
+    det = f' sin^2 f / r^2 for the hedgehog (Sec. 7.7 sextic term, halved)."""
     from scipy import integrate
     c6 = 1.3
     f = lambda r: math.pi * (1 - math.tanh(r))
@@ -213,7 +213,7 @@ def test_sextic_energy_of_the_hedgehog_against_radial_quadrature():
 def test_potentials_on_a_uniform_field():
     """A field that is the same at every site (frozen layers included) has no
     derivatives: E2 = E4 = 0 and E0 = h^3 (n-4)^3 V(phi0), with V the sum of the
-    program's four potentials (Sec. 6: 2 m_x^2 (1-phi0), m_y^2 (1-phi0^2),
+    program's four potentials (Sec. 7.7: 2 m_x^2 (1-phi0), m_y^2 (1-phi0^2),
     m_z^2 (1-phi0)^2, m_w^2 (1-phi0)^4 / 2), halved to this energy's
     normalisation; deep inside, the gradient is dV/dphi0 on the phi0 component
     (checked against a central difference of V)."""
@@ -498,7 +498,7 @@ def test_power_rule_trace_and_same_minimum():
 
 
 def test_gradient_flow_is_first_order_descent():
-    """Gradient flow (Sec. 6, the program's third flow mode): one step
+    """Gradient flow (Sec. 7.5, the program's third flow mode): one step
     phi' = normalise(phi + dt F) lowers the energy by dt h^3 sum |F|^2 to first
     order in dt (the ratio tends to 1 linearly), and the velocity stays zero."""
     n, h, m = 16, 0.25, 1.0
@@ -603,6 +603,28 @@ def test_rational_maps_on_every_direction_including_the_south_pole():
         assert south[I].sum() >= 2
         centre = (r == 0)
         np.testing.assert_allclose(phi[:, centre].ravel(), [-1.0, 0.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_spatial_orientation_turns_the_constituent():
+    """Sec. 5.3: a constituent turned by D(B) is U(D(B)^-1 (x - X)).  B for
+    the right-handed quarter turn about z is checked against the printed
+    D(B)_ij = (1/2) Tr(tau^i B tau^j B^dagger); on a cubic lattice the turned
+    cube is then the unturned array with (x, y) -> (y, -x) read off exactly."""
+    c45 = math.cos(math.pi / 4)
+    B = np.array([c45, 0.0, 0.0, -c45])
+    Bm = B[0] * PAULI[0] + 1j * sum(B[k] * PAULI[k] for k in (1, 2, 3))
+    D = np.array([[0.5 * np.trace(PAULI[i] @ Bm @ PAULI[j] @ Bm.conj().T).real for j in (1, 2, 3)]
+                  for i in (1, 2, 3)])
+    np.testing.assert_allclose(D, [[0, -1, 0], [1, 0, 0], [0, 0, 1]], atol=1e-15)
+    n, h = 14, 0.3
+    q = (0.8, 0.0, 0.6, 0.0)
+    plain = oracle.init_product((n, n, n), h, [oracle.cube_b4(prof_lambda=1.1, quat=q)])
+    turned = oracle.init_product((n, n, n), h, [oracle.cube_b4(prof_lambda=1.1, quat=q, orient=B)])
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    # phi'(x, y, z) = phi(D^-1 x) = phi(y, -x, z): index (i, j) reads (j, n - 1 - i)
+    ref = plain[:, j, n - 1 - i, :]
+    np.testing.assert_allclose(turned, ref, atol=1e-13)
+    assert np.abs(turned - plain).max() > 0.1
 
 
 def test_product_and_isorotation_against_pauli_matrices():
