@@ -83,7 +83,7 @@ def _load():
         "ora_observables": (None, [i3, d, dp, dp, dp]),
         "ora_update_at": (None, [dp, dp, dp, d, ctypes.c_int, dp, dp]),
         "ora_power": (d, [i3, d, dp, dp]),
-        "ora_anf": (i64, [i3, d, dp, d, d, i64, ctypes.c_int, dp, dp, ctypes.POINTER(AnfState), dp,
+        "ora_anf": (i64, [i3, d, dp, d, d, i64, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.POINTER(AnfState), dp,
                           ctypes.POINTER(i32)]),
         "ora_init_product": (None, [i3, d, i32, ctypes.POINTER(Constituent), dp]),
         "ora_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, i64]),
@@ -209,7 +209,8 @@ def gradient_at(phi, h: float, m: float, x: int, y: int, z: int) -> np.ndarray:
 
 def gradient_literal(phi, h: float, m: float) -> np.ndarray:
     """The paper's printed Euler-Lagrange expression (halved), five-point second
-    derivatives and D_i D_j mixed derivatives; zero within 4 layers of a face."""
+    derivatives and D_i D_j mixed derivatives, on the interior (zero on the
+    frozen layers)."""
     phi = _field(phi)
     g = np.empty_like(phi)
     _load().ora_gradient_literal(_dims(phi.shape[1:]), h, _mass(m), _ptr(phi), _ptr(g))
@@ -243,16 +244,20 @@ def observables(phi, h: float, m) -> dict:
 
 # ------------------------------------------------------------------------ ANF
 def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, state: AnfState | None = None,
-        arrest: bool = True, trace: bool = False, rule: str = "energy"):
+        arrest: bool = True, trace: bool = False, rule: str = "energy", form: str = "exact"):
     """Arrested Newton flow, in place on (phi, vel), until state.steps reaches
     target_steps, max|F| < tol, or a non-finite value.  rule = "energy"
     (arrest when E_n > E_{n-1}), "power" (arrest when h^3 sum F_n . v_n < 0)
     or "gradient" (the first-order gradient flow, no velocity); arrest=False
     with an arrest rule gives the plain Newton flow.  m: the pion mass, or the
-    four potential masses (m_x, m_y, m_z, m_w).
+    four potential masses (m_x, m_y, m_z, m_w).  form = "exact" (the derivative
+    of the discrete energy) or "printed" (the printed Euler-Lagrange expression,
+    gradient_literal) for the force.
     Returns (phi, vel, state, E_trace, arrest_trace); traces are None unless trace."""
     if rule not in ("energy", "power", "gradient"):
         raise ValueError(f"unknown flow rule {rule!r}")
+    if form not in ("exact", "printed"):
+        raise ValueError(f"unknown gradient form {form!r}")
     phi = _field(phi).copy()
     vel = _field(vel).copy()
     st = AnfState.fresh() if state is None else state
@@ -260,7 +265,8 @@ def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, 
     Et = np.full(n_max, np.nan) if trace else None
     At = np.zeros(n_max, dtype=np.int32) if trace else None
     mode = 3 if rule == "gradient" else (0 if not arrest else (1 if rule == "energy" else 2))
-    nev = _load().ora_anf(_dims(phi.shape[1:]), h, _mass(m), dt, tol, int(target_steps), mode, _ptr(phi),
+    nev = _load().ora_anf(_dims(phi.shape[1:]), h, _mass(m), dt, tol, int(target_steps), mode,
+                          int(form == "printed"), _ptr(phi),
                           _ptr(vel), ctypes.byref(st), _ptr(Et) if trace else None,
                           At.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if trace else None)
     if trace:

@@ -621,8 +621,10 @@ ORA_API double ora_power(const int n[3], double h, const double *gT, const doubl
  * evaluated step, indexed from the step count on entry.
  * Returns the number of evaluated steps.
  */
+ORA_API void ora_gradient_literal(const int n[3], double h, const double *mass, const double *phi, double *g);
+
 ORA_API int64_t ora_anf(const int n[3], double h, const double *mass, double dt, double tol, int64_t target_steps, int arrest,
-                        double *phi, double *vel, ora_anf_state *st, double *E_trace, int32_t *arrest_trace)
+                        int printed, double *phi, double *vel, ora_anf_state *st, double *E_trace, int32_t *arrest_trace)
 {
     const size_t N3 = n_sites(n);
     double *g = malloc(4 * N3 * sizeof(double));
@@ -630,7 +632,10 @@ ORA_API int64_t ora_anf(const int n[3], double h, const double *mass, double dt,
     int64_t evaluated = 0;
     while (st->steps < target_steps) {
         double E = ora_energy(n, h, mass, phi);
-        ora_gradient(n, h, mass, phi, g);
+        if (printed)
+            ora_gradient_literal(n, h, mass, phi, g);
+        else
+            ora_gradient(n, h, mass, phi, g);
         double r = ora_project(n, phi, g, gT);
         int reset = 0;
         if (arrest == 1) reset = E > st->E_prev;
@@ -910,30 +915,37 @@ ORA_API void ora_random_constituents(uint64_t seed, int32_t B, double radius, do
 /* ------------------------------------------------------------------------ */
 /* the paper-literal Euler-Lagrange expression (eq. Sigma model EL         */
 /* equations, halved), evaluated with the five-point second derivative and */
-/* mixed derivatives D_i D_j.  Not the flow's gradient: used to show that  */
-/* it agrees with the exact discrete gradient to O(h^4) on smooth fields.  */
+/* the mixed derivatives D_i D_j (the product of two first-difference      */
+/* stencils, Sec. 3), on every interior site; the frozen layers supply the */
+/* values the stencils reach.  The program's form of the force (the        */
+/* library's optional printed-form flow).                                  */
 /* ------------------------------------------------------------------------ */
 
 ORA_API void ora_gradient_literal(const int n[3], double h, const double *mass, const double *phi, double *g)
 {
     const size_t N3 = n_sites(n);
+    /* a_i on every site whose i-th coordinate admits the stencil (2 .. n_i - 3),
+     * whatever its other coordinates: D_j D_i at an interior site reads a_i at
+     * distance <= 2 along j only */
     double *a = malloc(12 * N3 * sizeof(double));
-    /* first derivatives on sites at least 2 layers in: needed for D_i D_j */
     memset(a, 0, 12 * N3 * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int x = 0; x < n[0]; x++)
+        for (int y = 0; y < n[1]; y++)
+            for (int z = 0; z < n[2]; z++) {
+                const int c[3] = {x, y, z};
+                size_t s = site(n, x, y, z);
+                for (int i = 0; i < 3; i++) {
+                    if (c[i] < 2 || c[i] > n[i] - 3) continue;
+                    for (int A = 0; A < 4; A++)
+                        a[((size_t)i * 4 + A) * N3 + s] = d1(phi + (size_t)A * N3, n, i, x, y, z, h);
+                }
+            }
+    memset(g, 0, 4 * N3 * sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int x = 2; x <= n[0] - 3; x++)
         for (int y = 2; y <= n[1] - 3; y++)
             for (int z = 2; z <= n[2] - 3; z++) {
-                size_t s = site(n, x, y, z);
-                for (int i = 0; i < 3; i++)
-                    for (int A = 0; A < 4; A++)
-                        a[((size_t)i * 4 + A) * N3 + s] = d1(phi + (size_t)A * N3, n, i, x, y, z, h);
-            }
-    memset(g, 0, 4 * N3 * sizeof(double));
-#pragma omp parallel for schedule(static)
-    for (int x = 4; x <= n[0] - 5; x++)
-        for (int y = 4; y <= n[1] - 5; y++)
-            for (int z = 4; z <= n[2] - 5; z++) {
                 size_t s = site(n, x, y, z);
                 double d[3][4], dd[3][3][4];
                 for (int i = 0; i < 3; i++)
