@@ -83,7 +83,20 @@ typedef struct {
     double m_z;
     double m_w;
     double c6;
+    int32_t form;  /* a skyr_gradient_form */
+    int32_t _pad;
 } skyr_model;
+
+/* Form of the force (Sec. 3).
+ *   SKYR_FORM_EXACT    the exact derivative of the discrete energy E_h (default;
+ *                      the flow descends E_h and its fixed points are those of E_h)
+ *   SKYR_FORM_PRINTED  the paper's printed Euler-Lagrange expression, halved, with
+ *                      the five-point second difference and D_i D_j mixed
+ *                      derivatives on every interior site (a one-stage stencil);
+ *                      agrees with the exact form to O(h^4).  The energy, charge
+ *                      and arrest test are unchanged.  Not available with the
+ *                      sextic term (c6 != 0), in batches or for the autotuner. */
+typedef enum { SKYR_FORM_EXACT = 0, SKYR_FORM_PRINTED = 1 } skyr_gradient_form;
 
 /* Flow mode (Sec. 3; the program's flow modes, Sec. 7.5).
  *   SKYR_ARREST_ENERGY  arrested Newton flow with the paper's rule: arrest at step k

@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 SOURCES = [PKG / "csrc" / "skyr.hip"]
-DEPS = SOURCES + [PKG / "csrc" / "sweep.hpp", PKG / "csrc" / "moments.hpp", ROOT / "include" / "skyr.h"]
+DEPS = SOURCES + [PKG / "csrc" / "sweep.hpp", PKG / "csrc" / "moments.hpp", PKG / "csrc" / "formp.hpp", ROOT / "include" / "skyr.h"]
 LIB = PKG / "libskyr.so"
 
 HIPCC_FLAGS = [

@@ -19,6 +19,7 @@
 #include "../../include/skyr.h"
 #include "sweep.hpp"
 #include "moments.hpp"
+#include "formp.hpp"
 
 namespace skyr {
 
@@ -131,6 +132,7 @@ static size_t workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
 {
     int most = 0;
     for (int v = 0; v < shape_count(prec); ++v) most = std::max(most, plan_with(lat, prec, v, kMinChunk).blocks());
+    most = std::max(most, formp_blocks(lat->n[0], lat->n[1], lat->n[2]));
     const size_t sweep_part = (size_t)most * NPART * sizeof(double);
     const size_t mom_part = (size_t)MOM_MAX_BLOCKS * MOM_NACC * sizeof(double);
     return CTL_BYTES + OBS_BYTES + std::max(sweep_part, mom_part);
@@ -429,6 +431,35 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
 #undef SKYR_CASE32
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+static void launch_printed(int mode, bool ext, dim3 grid, dim3 block, const SweepArgs& args, hipStream_t s)
+{
+    if (mode == MODE_STEP) {
+        if (ext)
+            hipLaunchKernelGGL((formp_kernel<T, MODE_STEP, true>), grid, block, 0, s, args);
+        else
+            hipLaunchKernelGGL((formp_kernel<T, MODE_STEP, false>), grid, block, 0, s, args);
+    } else {
+        if (ext)
+            hipLaunchKernelGGL((formp_kernel<T, MODE_GRAD, true>), grid, block, 0, s, args);
+        else
+            hipLaunchKernelGGL((formp_kernel<T, MODE_GRAD, false>), grid, block, 0, s, args);
+    }
+}
+
+// The printed-form sweep: one launch over formp_blocks() blocks.
+static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattice* lat, SweepArgs args, hipStream_t s)
+{
+    args.xchunk = FP_XCHUNK;
+    const dim3 grid(formp_blocks(lat->n[0], lat->n[1], lat->n[2])), block(FP_THREADS);
+    const bool ext = needs_ext(args);
+    if (prec == SKYR_F64)
+        launch_printed<double>(mode, ext, grid, block, args, s);
+    else
+        launch_printed<float>(mode, ext, grid, block, args, s);
+    return hipGetLastError();
 }
 
 // The batched sweep uses the first compiled shape of each precision.
@@ -730,9 +761,14 @@ static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, co
     a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
     double* obs = (double*)(w + CTL_BYTES);
     if (grad) SKYR_HIP(fill(grad, 4 * sites(lat), prec, 0.0, s));
-    SKYR_HIP(sweep(prec, MODE_GRAD, L, a, s));
+    const bool printed = model->form == SKYR_FORM_PRINTED;
+    if (printed)
+        SKYR_HIP(sweep_printed(prec, MODE_GRAD, lat, a, s));
+    else
+        SKYR_HIP(sweep(prec, MODE_GRAD, L, a, s));
     if (obs_out) {
-        hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, L.blocks(), lat->h, obs);
+        const int nb = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2]) : L.blocks();
+        hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, nb, lat->h, obs);
         SKYR_HIP(hipGetLastError());
         SKYR_HIP(hipMemcpyAsync(obs_out, obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         SKYR_HIP(hipStreamSynchronize(s));
@@ -749,6 +785,10 @@ static skyr_status check_common(const skyr_lattice* lat, skyr_precision prec, co
     if (!std::isfinite(model->m) || !std::isfinite(model->m_y) || !std::isfinite(model->m_z) ||
         !std::isfinite(model->m_w) || !std::isfinite(model->c6))
         return fail(SKYR_E_INVAL, "masses and c6 must be finite");
+    if (model->form != SKYR_FORM_EXACT && model->form != SKYR_FORM_PRINTED)
+        return fail(SKYR_E_INVAL, "unknown gradient form");
+    if (model->form == SKYR_FORM_PRINTED && model->c6 != 0.0)
+        return fail(SKYR_E_INVAL, "the printed form has no sextic term");
     if (!aligned256(work)) return fail(SKYR_E_INVAL, "workspace must be 256-byte aligned");
     return SKYR_OK;
 }
@@ -878,7 +918,8 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     h.sweeps = st->sweeps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
     h.flow_mode = flow->mode;
-    h.nblocks = L.blocks();
+    const bool printed = model->form == SKYR_FORM_PRINTED;
+    h.nblocks = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2]) : L.blocks();
     h.E_prev = st->E_prev;
     h.E = st->E;
     h.max_force = st->max_force;
@@ -904,7 +945,10 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     for (;;) {
         for (int64_t i = 0; i < group; ++i) {
             SKYR_HIP(timing_mark(s));
-            SKYR_HIP(sweep(prec, MODE_STEP, L, a, s));
+            if (printed)
+                SKYR_HIP(sweep_printed(prec, MODE_STEP, lat, a, s));
+            else
+                SKYR_HIP(sweep(prec, MODE_STEP, L, a, s));
             SKYR_HIP(timing_mark(s));
             hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
             SKYR_HIP(hipGetLastError());
@@ -979,6 +1023,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
 {
     skyr_status rc = check_common(lat, prec, model, phi, work);
     if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "the autotuner times the exact-gradient sweep");
     if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
@@ -1238,6 +1283,7 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     if (!b) return fail(SKYR_E_INVAL, "batch is null");
     skyr_status rc = check_common(lat, prec, model, phi, work);
     if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
     if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)

@@ -16,6 +16,7 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libskyr.so"
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, -1, -2, -3, -4, -5
+FORM_EXACT, FORM_PRINTED = 0, 1
 F64, F32_BULK = 0, 1
 ARREST_ENERGY, ARREST_POWER, NEWTON_FLOW, GRADIENT_FLOW = 0, 1, 2, 3
 _FLOW_MODES = {"energy": ARREST_ENERGY, "power": ARREST_POWER, "newton": NEWTON_FLOW, "gradient": GRADIENT_FLOW}
@@ -49,9 +50,11 @@ class Lattice(ctypes.Structure):
 
 
 class Model(ctypes.Structure):
-    """Couplings: the pion mass m, the optional masses m_y, m_z, m_w and the sextic weight c6."""
+    """Couplings: the pion mass m, the optional masses m_y, m_z, m_w, the sextic
+    weight c6, and the form of the force (FORM_EXACT or FORM_PRINTED)."""
     _fields_ = [("m", ctypes.c_double), ("m_y", ctypes.c_double), ("m_z", ctypes.c_double),
-                ("m_w", ctypes.c_double), ("c6", ctypes.c_double)]
+                ("m_w", ctypes.c_double), ("c6", ctypes.c_double), ("form", ctypes.c_int32),
+                ("_pad", ctypes.c_int32)]
 
 
 class Flow(ctypes.Structure):

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     assert ctypes.sizeof(skyr.Lattice) == 24
-    assert ctypes.sizeof(skyr.Model) == 40
+    assert ctypes.sizeof(skyr.Model) == 48
     assert ctypes.sizeof(skyr.Flow) == 32
     assert ctypes.sizeof(skyr.Constituent) == 8 + 2 * 9 * 16 + 3 * 8 + 4 * 8 + 16 + 4 * 8
     assert ctypes.sizeof(skyr.Obs) == 64
