@@ -3,7 +3,9 @@ configuration files (B = 4 cubes of Table RMA, positions and Euler angles of
 Sec. 7.3.1) relaxed with the arrested Newton flow on the program's large
 lattice (151^3, x in [-8, 8], m = 1), then the printed observables: charge,
 energy, RMS radius, the inertia tensors U, V, W and the quadrupole Q
-(tests/golden/neat_examples.json, each with its citation).
+(tests/golden/neat_examples.json, each with its citation).  The same solutions
+continued with the printed-form force (the program's form, SKYR_FORM_PRINTED)
+reproduce the printed tensors to their two printed decimals.
 
 The paper's profile fits are not printed, so the cubes start from
 f = pi exp(-r / 1.2); the relaxed solution does not depend on it.  The paper's
@@ -59,6 +61,17 @@ def relaxed(skyr):
                       st, 60000, work)
         assert st.converged, (name, st.steps, st.max_force)
         out[name] = (skyr.moments(lat, skyr.F64, model, phi, work), skyr.observables(lat, skyr.F64, model, phi, work))
+        # continue from there with the printed-form force (power rule, half the step: the
+        # printed form's quartic term is stiffer), to its own fixed point O(h^4) away
+        printed = skyr.Model(lat_d["m"])
+        printed.form = skyr.FORM_PRINTED
+        st = skyr.anf_state()
+        vel.zero_()
+        print(f"continuing {name} with the printed form", flush=True)
+        skyr.anf_step(lat, skyr.F64, printed, skyr.Flow(0.05 * h, 2e-5, 60000, 0, skyr.ARREST_POWER), phi, alt, vel,
+                      st, 60000, work)
+        assert st.converged, (name, "printed", st.steps, st.max_force)
+        out[name + "/printed"] = (skyr.moments(lat, skyr.F64, printed, phi, work), st.steps)
         del phi, alt, vel, work
     return out
 
@@ -88,3 +101,24 @@ def test_d_term_ratio(relaxed):
     ref = GOLDEN["b12a"]["D"] / GOLDEN["b8a"]["D"]
     assert got == pytest.approx(ref, rel=1.5e-2)
     assert relaxed["b8a"][0]["D"] < 0 and relaxed["b12a"][0]["D"] < 0
+
+
+@pytest.mark.parametrize("name", ["b8a", "b12a"])
+def test_printed_form_reproduces_the_printed_tensors(relaxed, name):
+    """The printed-form fixed point, reached from the exact-form minimum, gives
+    the printed tensors to their printed precision (two decimals), closer than
+    the exact form does: the program evaluates this form of the force."""
+    ex = GOLDEN[name]
+    m, steps = relaxed[name + "/printed"]
+    exact = relaxed[name][0]
+    assert m["B"] == pytest.approx(ex["B"], abs=1e-3)
+    assert m["E"] == pytest.approx(ex["E"], rel=2e-4)
+    assert m["R"] == pytest.approx(ex["R"], abs=0.006)
+    for k in ("U", "V", "Q"):
+        ref = np.array(ex[k])
+        np.testing.assert_allclose(np.diag(m[k]), np.diag(ref), rtol=5e-4, atol=0.006, err_msg=k)
+        off = ~np.eye(3, dtype=bool)
+        assert np.abs(m[k][off] - ref[off]).max() < 0.1, k
+        # closer to the printed diagonal than the exact form's fixed point
+        assert np.abs(np.diag(m[k]) - np.diag(ref)).sum() <= np.abs(np.diag(exact[k]) - np.diag(ref)).sum() + 0.01, k
+    assert np.abs(m["W"]).max() < 1e-3 * np.abs(m["U"]).max()
