@@ -70,11 +70,12 @@ def recorded_traffic(prec_name, tile):
     return 1024.0 * (fetch + write)
 
 
-def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, mode=None):
+def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, mode=None, form=0):
     """Time `steps` accepted flow steps of the workload after `warmup`.  The
     FP32-bulk flow uses the power arrest rule (its recommended setting), the
     FP64 flow the paper's energy rule; `masses` (m, m_y, m_z, m_w, c6) and
-    `mode` override the workload's model and flow mode."""
+    `mode` override the workload's model and flow mode; form 1 takes the
+    printed-form force."""
     prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
     n, h = w["n"], w["h"]
     lat = skyr.Lattice.cube(n, h)
@@ -85,6 +86,7 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, m
     alt, vel = skyr.new_field(lat, prec, dev), skyr.new_field(lat, prec, dev)
     work = skyr.new_workspace(lat, prec, dev)
     model = skyr.Model(*(masses or (w["m"],)))
+    model.form = form
     # tolerance 0: every call runs exactly its steps
     rule = mode or ("power" if prec_name == "f32" else "energy")
     flow = skyr.Flow(w["dt"], 0.0, 10 ** 12, 16, skyr.flow_mode(rule))
@@ -341,6 +343,10 @@ def main():
     ext_model = (W["m"], 0.5, 0.5, 0.5, 0.1)
     rext = run_flow(skyr, torch, W, "f32", max(args.steps // 5, 20), args.warmup, tiles["f32"], masses=ext_model)
     print(f"# f32-bulk, four potentials and sextic term: {rext}", file=sys.stderr, flush=True)
+    # the printed-form force (one-stage stencil; its stiffer quartic term needs half the step)
+    rform = run_flow(skyr, torch, {**W, "dt": 0.5 * W["dt"]}, "f32", max(args.steps // 5, 20), args.warmup,
+                     (r32["tile"]["variant"], r32["tile"]["xchunk"]), mode="power", form=1)
+    print(f"# f32-bulk, printed form: {rform}", file=sys.stderr, flush=True)
     moments = {p: time_moments(skyr, torch, W, p) for p in ("f32", "f64")}
     print(f"# moments: {moments}", file=sys.stderr, flush=True)
     batch = serve = None
@@ -379,6 +385,9 @@ def main():
         "f32_extended_model": {"m_my_mz_mw_c6": list(ext_model), "value": rext["site_updates_per_s"],
                                "sweep_kernel_avg_us": rext["sweep_kernel_avg_us"], "steps": rext["steps"],
                                "E": rext["E"]},
+        "f32_printed_form": {"dt": 0.5 * W["dt"], "arrest": "power", "value": rform["site_updates_per_s"],
+                             "sweep_kernel_avg_us": rform["sweep_kernel_avg_us"], "steps": rform["steps"],
+                             "E": rform["E"]},
         "moments": moments,
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
