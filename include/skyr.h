@@ -54,7 +54,8 @@ typedef enum {
     SKYR_E_NOMEM = -2,     /* workspace too small / host allocation failed  */
     SKYR_E_DEVICE = -3,    /* a HIP call failed                              */
     SKYR_E_NONFINITE = -4, /* energy or force stopped being finite           */
-    SKYR_E_BUSY = -5       /* batch slot table full                          */
+    SKYR_E_BUSY = -5,      /* batch slot table full                          */
+    SKYR_E_IO = -6         /* a file could not be opened, read or written    */
 } skyr_status;
 
 typedef enum {
@@ -371,6 +372,43 @@ SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec,
  * milliseconds and their count (either pointer may be null). */
 SKYR_API void skyr_timing_enable(int32_t on);
 SKYR_API skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches);
+
+/* Field files in the program's two formats (Sec. 7.4).
+ *   SKYR_FILE_BINARY  (int32) 1234, (double) xmin, ymin, zmin, (int32) XLEN, YLEN, ZLEN,
+ *                     (double) m.x, m.y, m.z, m.w, (double) c6, (double) -123456789.0
+ *                     (sentinel), then the field as XLEN*YLEN*ZLEN records of four
+ *                     doubles (phi0..phi3), z fastest, then y, then x; little-endian,
+ *                     fields written one after another without padding (88 header bytes)
+ *   SKYR_FILE_TEXT    a header line of the eleven parameters above (from xmin to c6,
+ *                     tab-separated), then one line of four tab-separated numbers per
+ *                     site in the same order; doubles printed with 17 significant digits
+ * A lattice of n sites and spacing h spans [xmin, -xmin] with xmin = -(n-1) h / 2 on
+ * every axis; m.x..m.w and c6 are skyr_model's m, m_y, m_z, m_w, c6.  Reading
+ * detects the format from the leading 1234, skips extra parameters that a
+ * modified program stores before the sentinel (at most 64), checks that the
+ * file's lattice equals `lat` (SKYR_E_INVAL otherwise; the spacing to 1e-12
+ * relative, the same on all three axes) and fills model_out (nullable; form = 0).
+ * I/O failures and malformed files give SKYR_E_IO. */
+typedef enum { SKYR_FILE_BINARY = 0, SKYR_FILE_TEXT = 1 } skyr_file_format;
+
+/* Host-memory variants: phi is a host array of 4 * N3 doubles in this library's
+ * layout ([4][n0][n1][n2]). */
+SKYR_API skyr_status skyr_write_field_host(const char* path, int32_t format, const skyr_lattice* lat,
+                                           const skyr_model* model, const double* phi);
+SKYR_API skyr_status skyr_read_field_host(const char* path, const skyr_lattice* lat, skyr_model* model_out,
+                                          double* phi);
+
+/* The lattice and model stored in a field file (either format), for sizing
+ * buffers before skyr_load_field; lat_out and model_out nullable. */
+SKYR_API skyr_status skyr_file_info(const char* path, skyr_lattice* lat_out, skyr_model* model_out);
+
+/* Device variants: phi is a device field of precision prec (layout above);
+ * the field goes through a host buffer (allocated and freed by the call).
+ * Synchronise `stream`. */
+SKYR_API skyr_status skyr_save_field(const char* path, int32_t format, const skyr_lattice* lat, skyr_precision prec,
+                                     const skyr_model* model, const void* phi, void* stream);
+SKYR_API skyr_status skyr_load_field(const char* path, const skyr_lattice* lat, skyr_precision prec,
+                                     skyr_model* model_out, void* phi, void* stream);
 
 #ifdef __cplusplus
 }

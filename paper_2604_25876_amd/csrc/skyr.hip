@@ -1469,3 +1469,253 @@ skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ field files
+// The program's text and binary formats (Sec. 7.4).  Host code; the device
+// variants stage the field through a host buffer.
+namespace {
+constexpr int32_t kFileMagic = 1234;
+constexpr double kFileSentinel = -123456789.0;
+constexpr int kMaxExtraParams = 64;
+
+struct FileHeader {
+    double xmin[3];
+    int32_t n[3];
+    double m[4];
+    double c6;
+};
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser()
+    {
+        if (f) std::fclose(f);
+    }
+};
+
+bool read_exact(FILE* f, void* p, size_t bytes) { return std::fread(p, 1, bytes, f) == bytes; }
+
+// binary header up to and including the sentinel (extra parameters skipped)
+bool read_binary_header(FILE* f, FileHeader& h)
+{
+    int32_t magic = 0;
+    if (!read_exact(f, &magic, 4) || magic != kFileMagic) return false;
+    if (!read_exact(f, h.xmin, sizeof h.xmin) || !read_exact(f, h.n, sizeof h.n) || !read_exact(f, h.m, sizeof h.m) ||
+        !read_exact(f, &h.c6, sizeof h.c6))
+        return false;
+    for (int k = 0; k <= kMaxExtraParams; ++k) {
+        double v;
+        if (!read_exact(f, &v, sizeof v)) return false;
+        if (v == kFileSentinel) return true;
+    }
+    return false;
+}
+
+// text header: eleven numbers on the first line
+bool read_text_header(FILE* f, FileHeader& h)
+{
+    char line[4096];
+    if (!std::fgets(line, sizeof line, f)) return false;
+    double v[11];
+    const char* p = line;
+    for (int k = 0; k < 11; ++k) {
+        char* end = nullptr;
+        v[k] = std::strtod(p, &end);
+        if (end == p) return false;
+        p = end;
+    }
+    for (int i = 0; i < 3; ++i) h.xmin[i] = v[i];
+    for (int i = 0; i < 3; ++i) {
+        if (v[3 + i] != std::floor(v[3 + i]) || v[3 + i] < 1.0 || v[3 + i] > 1e9) return false;
+        h.n[i] = (int32_t)v[3 + i];
+    }
+    for (int i = 0; i < 4; ++i) h.m[i] = v[6 + i];
+    h.c6 = v[10];
+    return true;
+}
+
+// open, detect the format, read the header; leaves f after the header
+skyr_status open_field_file(const char* path, FILE** out, FileHeader& h, bool& binary)
+{
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(SKYR_E_IO, std::string("cannot open ") + path);
+    int32_t magic = 0;
+    binary = read_exact(f, &magic, 4) && magic == kFileMagic;
+    std::rewind(f);
+    const bool ok = binary ? read_binary_header(f, h) : read_text_header(f, h);
+    if (!ok) {
+        std::fclose(f);
+        return fail(SKYR_E_IO, std::string("malformed field file header: ") + path);
+    }
+    *out = f;
+    return SKYR_OK;
+}
+
+// one lattice spacing for all three axes
+bool header_lattice(const FileHeader& h, skyr_lattice* lat)
+{
+    double hs[3];
+    for (int i = 0; i < 3; ++i) {
+        if (h.n[i] < 2) return false;
+        hs[i] = -2.0 * h.xmin[i] / (h.n[i] - 1);
+        if (!(hs[i] > 0.0) || !std::isfinite(hs[i])) return false;
+    }
+    for (int i = 1; i < 3; ++i)
+        if (std::fabs(hs[i] - hs[0]) > 1e-12 * hs[0]) return false;
+    lat->n[0] = h.n[0];
+    lat->n[1] = h.n[1];
+    lat->n[2] = h.n[2];
+    lat->_pad = 0;
+    lat->h = hs[0];
+    return true;
+}
+
+void header_model(const FileHeader& h, skyr_model* m)
+{
+    std::memset(m, 0, sizeof *m);
+    m->m = h.m[0];
+    m->m_y = h.m[1];
+    m->m_z = h.m[2];
+    m->m_w = h.m[3];
+    m->c6 = h.c6;
+}
+}  // namespace
+
+skyr_status skyr_write_field_host(const char* path, int32_t format, const skyr_lattice* lat, const skyr_model* model,
+                                  const double* phi)
+{
+    skyr_status st = check_lattice(lat, SKYR_F64);
+    if (st != SKYR_OK) return st;
+    if (!path || !model || !phi) return fail(SKYR_E_INVAL, "path, model and phi must be non-null");
+    if (format != SKYR_FILE_BINARY && format != SKYR_FILE_TEXT) return fail(SKYR_E_INVAL, "unknown file format");
+    const size_t N3 = (size_t)sites(lat);
+    double xmin[3];
+    for (int i = 0; i < 3; ++i) xmin[i] = -0.5 * (lat->n[i] - 1) * lat->h;
+    const double m[4] = {model->m, model->m_y, model->m_z, model->m_w};
+    FileCloser fc{std::fopen(path, format == SKYR_FILE_BINARY ? "wb" : "w")};
+    if (!fc.f) return fail(SKYR_E_IO, std::string("cannot create ") + path);
+    bool ok = true;
+    if (format == SKYR_FILE_BINARY) {
+        ok = std::fwrite(&kFileMagic, 4, 1, fc.f) == 1 && std::fwrite(xmin, 8, 3, fc.f) == 3 &&
+             std::fwrite(lat->n, 4, 3, fc.f) == 3 && std::fwrite(m, 8, 4, fc.f) == 4 &&
+             std::fwrite(&model->c6, 8, 1, fc.f) == 1 && std::fwrite(&kFileSentinel, 8, 1, fc.f) == 1;
+        std::vector<double> buf;
+        const size_t chunk = 1 << 16;
+        for (size_t s0 = 0; ok && s0 < N3; s0 += chunk) {
+            const size_t s1 = std::min(N3, s0 + chunk);
+            buf.resize(4 * (s1 - s0));
+            for (size_t s = s0; s < s1; ++s)
+                for (int A = 0; A < 4; ++A) buf[4 * (s - s0) + A] = phi[A * N3 + s];
+            ok = std::fwrite(buf.data(), 8, buf.size(), fc.f) == buf.size();
+        }
+    } else {
+        ok = std::fprintf(fc.f, "%.17g\t%.17g\t%.17g\t%d\t%d\t%d\t%.17g\t%.17g\t%.17g\t%.17g\t%.17g\n", xmin[0], xmin[1],
+                          xmin[2], lat->n[0], lat->n[1], lat->n[2], m[0], m[1], m[2], m[3], model->c6) > 0;
+        for (size_t s = 0; ok && s < N3; ++s)
+            ok = std::fprintf(fc.f, "%.17g\t%.17g\t%.17g\t%.17g\n", phi[s], phi[N3 + s], phi[2 * N3 + s],
+                              phi[3 * N3 + s]) > 0;
+    }
+    if (!ok) return fail(SKYR_E_IO, std::string("write failed: ") + path);
+    const int rc = std::fclose(fc.f);
+    fc.f = nullptr;
+    if (rc != 0) return fail(SKYR_E_IO, std::string("write failed: ") + path);
+    return SKYR_OK;
+}
+
+skyr_status skyr_file_info(const char* path, skyr_lattice* lat_out, skyr_model* model_out)
+{
+    if (!path) return fail(SKYR_E_INVAL, "path must be non-null");
+    FILE* f = nullptr;
+    FileHeader h{};
+    bool binary = false;
+    skyr_status st = open_field_file(path, &f, h, binary);
+    if (st != SKYR_OK) return st;
+    std::fclose(f);
+    skyr_lattice lat{};
+    if (!header_lattice(h, &lat)) return fail(SKYR_E_IO, "the file's lattice has unequal or invalid spacings");
+    if (lat_out) *lat_out = lat;
+    if (model_out) header_model(h, model_out);
+    return SKYR_OK;
+}
+
+skyr_status skyr_read_field_host(const char* path, const skyr_lattice* lat, skyr_model* model_out, double* phi)
+{
+    skyr_status st = check_lattice(lat, SKYR_F64);
+    if (st != SKYR_OK) return st;
+    if (!path || !phi) return fail(SKYR_E_INVAL, "path and phi must be non-null");
+    FILE* f = nullptr;
+    FileHeader h{};
+    bool binary = false;
+    st = open_field_file(path, &f, h, binary);
+    if (st != SKYR_OK) return st;
+    FileCloser fc{f};
+    skyr_lattice fl{};
+    if (!header_lattice(h, &fl) || fl.n[0] != lat->n[0] || fl.n[1] != lat->n[1] || fl.n[2] != lat->n[2] ||
+        std::fabs(fl.h - lat->h) > 1e-12 * lat->h)
+        return fail(SKYR_E_INVAL, "the file's lattice differs from the given lattice");
+    const size_t N3 = (size_t)sites(lat);
+    if (binary) {
+        std::vector<double> buf;
+        const size_t chunk = 1 << 16;
+        for (size_t s0 = 0; s0 < N3; s0 += chunk) {
+            const size_t s1 = std::min(N3, s0 + chunk);
+            buf.resize(4 * (s1 - s0));
+            if (!read_exact(f, buf.data(), 8 * buf.size())) return fail(SKYR_E_IO, "field data truncated");
+            for (size_t s = s0; s < s1; ++s)
+                for (int A = 0; A < 4; ++A) phi[A * N3 + s] = buf[4 * (s - s0) + A];
+        }
+    } else {
+        for (size_t s = 0; s < N3; ++s) {
+            double v[4];
+            if (std::fscanf(f, "%lf %lf %lf %lf", &v[0], &v[1], &v[2], &v[3]) != 4)
+                return fail(SKYR_E_IO, "field data truncated or malformed");
+            for (int A = 0; A < 4; ++A) phi[A * N3 + s] = v[A];
+        }
+    }
+    if (model_out) header_model(h, model_out);
+    return SKYR_OK;
+}
+
+skyr_status skyr_save_field(const char* path, int32_t format, const skyr_lattice* lat, skyr_precision prec,
+                            const skyr_model* model, const void* phi, void* stream)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!phi) return fail(SKYR_E_INVAL, "phi must be non-null");
+    const size_t n = 4 * (size_t)sites(lat);
+    std::vector<double> host(n);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == SKYR_F64) {
+        SKYR_HIP(hipMemcpyAsync(host.data(), phi, n * sizeof(double), hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> tmp(n);
+        SKYR_HIP(hipMemcpyAsync(tmp.data(), phi, n * sizeof(float), hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+        for (size_t k = 0; k < n; ++k) host[k] = tmp[k];
+    }
+    return skyr_write_field_host(path, format, lat, model, host.data());
+}
+
+skyr_status skyr_load_field(const char* path, const skyr_lattice* lat, skyr_precision prec, skyr_model* model_out,
+                            void* phi, void* stream)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!phi) return fail(SKYR_E_INVAL, "phi must be non-null");
+    const size_t n = 4 * (size_t)sites(lat);
+    std::vector<double> host(n);
+    st = skyr_read_field_host(path, lat, model_out, host.data());
+    if (st != SKYR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == SKYR_F64) {
+        SKYR_HIP(hipMemcpyAsync(phi, host.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> tmp(n);
+        for (size_t k = 0; k < n; ++k) tmp[k] = (float)host[k];
+        SKYR_HIP(hipMemcpyAsync(phi, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+    }
+    return SKYR_OK;
+}

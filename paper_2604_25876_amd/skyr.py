@@ -15,7 +15,8 @@ from pathlib import Path
 _PKG = Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libskyr.so"
 
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY, E_IO = 0, -1, -2, -3, -4, -5, -6
+FILE_BINARY, FILE_TEXT = 0, 1
 FORM_EXACT, FORM_PRINTED = 0, 1
 F64, F32_BULK = 0, 1
 ARREST_ENERGY, ARREST_POWER, NEWTON_FLOW, GRADIENT_FLOW = 0, 1, 2, 3
@@ -125,6 +126,14 @@ _SIGNATURES = {
     "skyr_anf_step": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState), ctypes.c_int64, _P,
                                      _P]),
+    "skyr_write_field_host": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(Lattice),
+                                             ctypes.POINTER(Model), _P]),
+    "skyr_read_field_host": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Lattice), ctypes.POINTER(Model), _P]),
+    "skyr_file_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Lattice), ctypes.POINTER(Model)]),
+    "skyr_save_field": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(Lattice), ctypes.c_int,
+                                       ctypes.POINTER(Model), _P, _P]),
+    "skyr_load_field": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Lattice), ctypes.c_int,
+                                       ctypes.POINTER(Model), _P, _P]),
     "skyr_orientation_zyz": (None, [ctypes.POINTER(ctypes.c_double * 3), ctypes.POINTER(ctypes.c_double * 4)]),
     "skyr_moments": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
                                     ctypes.POINTER(MomentObs), _P, _P]),
@@ -313,6 +322,50 @@ def moments(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> di
                               _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), ctypes.byref(out),
                               _dev_ptr(work), _stream(stream)))
     return out.as_dict()
+
+
+def _fmt(fmt) -> int:
+    return {"binary": FILE_BINARY, "text": FILE_TEXT}[fmt] if isinstance(fmt, str) else int(fmt)
+
+
+def write_field_host(path, lat: Lattice, model: Model, phi, fmt="binary") -> None:
+    """Write a host field (numpy float64, shape (4, n0, n1, n2)) in the program's
+    binary or text format (skyr_write_field_host)."""
+    import numpy as np
+    a = np.ascontiguousarray(phi, dtype=np.float64)
+    if a.shape != (4,) + lat.shape:
+        raise ValueError(f"field shape {a.shape}, expected {(4,) + lat.shape}")
+    _check(lib().skyr_write_field_host(str(path).encode(), _fmt(fmt), ctypes.byref(lat), ctypes.byref(model),
+                                       ctypes.c_void_p(a.ctypes.data)))
+
+
+def read_field_host(path, lat: Lattice):
+    """(field as numpy float64 (4, n0, n1, n2), Model) from a field file."""
+    import numpy as np
+    a = np.empty((4,) + lat.shape, dtype=np.float64)
+    m = Model()
+    _check(lib().skyr_read_field_host(str(path).encode(), ctypes.byref(lat), ctypes.byref(m),
+                                      ctypes.c_void_p(a.ctypes.data)))
+    return a, m
+
+
+def file_info(path):
+    """(Lattice, Model) stored in a field file."""
+    lat, m = Lattice(), Model()
+    _check(lib().skyr_file_info(str(path).encode(), ctypes.byref(lat), ctypes.byref(m)))
+    return lat, m
+
+
+def save_field(path, lat: Lattice, prec: int, model: Model, phi, fmt="binary", stream=None) -> None:
+    _check(lib().skyr_save_field(str(path).encode(), _fmt(fmt), ctypes.byref(lat), prec, ctypes.byref(model),
+                                 _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), _stream(stream)))
+
+
+def load_field(path, lat: Lattice, prec: int, phi, stream=None) -> Model:
+    m = Model()
+    _check(lib().skyr_load_field(str(path).encode(), ctypes.byref(lat), prec, ctypes.byref(m),
+                                 _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), _stream(stream)))
+    return m
 
 
 def cube_b4(X=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), prof_a: float = math.pi,
