@@ -63,7 +63,6 @@ static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
 static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
 constexpr int kMinChunk = 16;  // shortest slab (planes)
 constexpr int kMaxSlabs = 24;  // the autotuner splits x into 1 .. kMaxSlabs equal slabs
-constexpr int kDefaultChunk = 128;
 
 static int shape_count(skyr_precision prec)
 {
@@ -104,9 +103,25 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
     return L;
 }
 
+// Slab length of a lattice the autotuner has not seen: shape 0, and the even
+// split of x into as many slabs (of at least kMinChunk planes, at most
+// kMaxSlabs) as keep the block count near one round of the chip (float: one
+// 1024-thread block per CU, 256 blocks) or three (double: 768); the autotuner's
+// choices at 256^3 (3 and 4 slabs) follow this rule.
+static int default_chunk(const skyr_lattice* lat, skyr_precision prec)
+{
+    const Launch L = plan_with(lat, prec, 0, kMinChunk);
+    const int tiles = L.tiles_z * L.tiles_y;
+    const int nx = lat->n[0] - 4;
+    const int target = prec == SKYR_F64 ? 768 : 256;
+    const int most = std::max(1, std::min(kMaxSlabs, nx / kMinChunk));
+    const int slabs = std::max(1, std::min(most, target / std::max(1, tiles)));
+    return std::max(kMinChunk, (nx + slabs - 1) / slabs);
+}
+
 static Launch plan(const skyr_lattice* lat, skyr_precision prec)
 {
-    int v = 0, xc = kDefaultChunk;
+    int v = 0, xc = 0;
     {
         std::lock_guard<std::mutex> g(g_tile_mu);
         auto it = g_tiles.find(TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec});
@@ -115,6 +130,7 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
             xc = it->second.second;
         }
     }
+    if (xc == 0) xc = default_chunk(lat, prec);
     return plan_with(lat, prec, v, xc);
 }
 
@@ -476,24 +492,21 @@ static hipError_t launch_batch(bool ext, int blocks, const SweepArgs* jobs, cons
     return hipGetLastError();
 }
 
-static hipError_t batch_sweep(skyr_precision prec, bool ext, int blocks, const SweepArgs* jobs, const int* map,
-                              const int* first, const int* count, hipStream_t s)
+// the batched sweep of the jobs of one (precision, tile shape) group
+static hipError_t batch_sweep(skyr_precision prec, int variant, bool ext, int blocks, const SweepArgs* jobs,
+                              const int* map, const int* first, const int* count, hipStream_t s)
 {
-    // shape 0 of each list
+    int v = 0;
     if (prec == SKYR_F64) {
-        const Shape& sh = kShapesF64[0];
-        int v = 0;
 #define SKYR_B64(a, b, c)                                                                                    \
-    if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
-        return launch_batch<double, a, b, c>(ext, blocks, jobs, map, first, count, s);
+    if (variant == v) return launch_batch<double, a, b, c>(ext, blocks, jobs, map, first, count, s);          \
+    ++v;
         SKYR_SHAPES_F64(SKYR_B64)
 #undef SKYR_B64
     } else {
-        const Shape& sh = kShapesF32[0];
-        int v = 0;
 #define SKYR_B32(a, b, c)                                                                                    \
-    if (v++ == 0 && sh.nw == a && sh.lw == b && sh.ry == c)                                                  \
-        return launch_batch<float, a, b, c>(ext, blocks, jobs, map, first, count, s);
+    if (variant == v) return launch_batch<float, a, b, c>(ext, blocks, jobs, map, first, count, s);           \
+    ++v;
         SKYR_SHAPES_F32(SKYR_B32)
 #undef SKYR_B32
     }
@@ -1110,7 +1123,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
         return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
     double best = INFINITY;
-    int bv = 0, bx = kDefaultChunk;
+    int bv = 0, bx = default_chunk(lat, prec);
     for (const Cand& cd : cands)
         if (cd.us < best) {
             best = cd.us;
@@ -1154,10 +1167,13 @@ struct skyr_batch {
     SweepArgs* d_args = nullptr;     // [max_jobs]
     int* d_first = nullptr;          // [max_jobs] first block of a job in its precision's grid
     int* d_count = nullptr;          // [max_jobs] blocks of a job
-    int* d_map[2] = {nullptr, nullptr};  // block -> job, per precision
-    int map_cap[2] = {0, 0};
-    int grid[2] = {0, 0};
-    bool ext[2] = {false, false};  // some job of the precision needs the extended kernel variant
+    // jobs are grouped by (precision, tile shape): group g < F64 shape count is F64 shape g,
+    // the rest F32 shape g - (F64 shape count); one batched launch per group and sweep slot
+    static constexpr int kGroups = 16;
+    int* d_map[kGroups] = {};  // block -> job, per group
+    int map_cap[kGroups] = {};
+    int grid[kGroups] = {};
+    bool ext[kGroups] = {};  // some job of the group needs the extended kernel variant
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1175,30 +1191,37 @@ static void batch_release_graph(skyr_batch* b)
     b->graph_sweeps = 0;
 }
 
+static int batch_group(skyr_precision prec, int variant)
+{
+    return prec == SKYR_F64 ? variant : shape_count(SKYR_F64) + variant;
+}
+static_assert(sizeof(kShapesF64) / sizeof(Shape) + sizeof(kShapesF32) / sizeof(Shape) <= skyr_batch::kGroups,
+              "batch groups");
+
 // rebuild the device job tables and block maps from the host description
 static skyr_status batch_rebuild(skyr_batch* b)
 {
-    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[2];
-    b->ext[0] = b->ext[1] = false;
+    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[skyr_batch::kGroups];
+    for (int g = 0; g < skyr_batch::kGroups; ++g) b->ext[g] = false;
     for (int j = 0; j < b->max_jobs; ++j) {
         const auto& J = b->jobs[j];
         if (!J.active) continue;
-        const int p = J.prec == SKYR_F64 ? 0 : 1;
-        b->ext[p] = b->ext[p] || needs_ext(b->args[j]);
-        first[j] = (int)map[p].size();
+        const int g = batch_group(J.prec, J.L.variant);
+        b->ext[g] = b->ext[g] || needs_ext(b->args[j]);
+        first[j] = (int)map[g].size();
         count[j] = J.L.blocks();
-        map[p].insert(map[p].end(), count[j], j);
+        map[g].insert(map[g].end(), count[j], j);
     }
-    for (int p = 0; p < 2; ++p) {
-        const int n = (int)map[p].size();
-        if (n > b->map_cap[p]) {
-            if (b->d_map[p]) SKYR_HIP(hipFree(b->d_map[p]));
-            b->d_map[p] = nullptr;
-            SKYR_HIP(hipMalloc((void**)&b->d_map[p], sizeof(int) * n));
-            b->map_cap[p] = n;
+    for (int g = 0; g < skyr_batch::kGroups; ++g) {
+        const int n = (int)map[g].size();
+        if (n > b->map_cap[g]) {
+            if (b->d_map[g]) SKYR_HIP(hipFree(b->d_map[g]));
+            b->d_map[g] = nullptr;
+            SKYR_HIP(hipMalloc((void**)&b->d_map[g], sizeof(int) * n));
+            b->map_cap[g] = n;
         }
-        if (n) SKYR_HIP(hipMemcpy(b->d_map[p], map[p].data(), sizeof(int) * n, hipMemcpyHostToDevice));
-        b->grid[p] = n;
+        if (n) SKYR_HIP(hipMemcpy(b->d_map[g], map[g].data(), sizeof(int) * n, hipMemcpyHostToDevice));
+        b->grid[g] = n;
     }
     SKYR_HIP(hipMemcpy(b->d_first, first.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_count, count.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
@@ -1215,12 +1238,12 @@ static skyr_status batch_capture(skyr_batch* b, int sweeps)
     SKYR_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
-        if (b->grid[0] && e == hipSuccess)
-            e = batch_sweep(SKYR_F64, b->ext[0], b->grid[0], b->d_args, b->d_map[0], b->d_first, b->d_count,
-                            b->capture);
-        if (b->grid[1] && e == hipSuccess)
-            e = batch_sweep(SKYR_F32_BULK, b->ext[1], b->grid[1], b->d_args, b->d_map[1], b->d_first, b->d_count,
-                            b->capture);
+        for (int g = 0; g < skyr_batch::kGroups && e == hipSuccess; ++g) {
+            if (!b->grid[g]) continue;
+            const bool f64 = g < shape_count(SKYR_F64);
+            e = batch_sweep(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[g], b->grid[g],
+                            b->d_args, b->d_map[g], b->d_first, b->d_count, b->capture);
+        }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->max_jobs), dim3(256), 0, b->capture, b->d_args,
                                b->max_jobs);
@@ -1297,9 +1320,8 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
             break;
         }
     if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
-    // the batched sweep uses shape 0 of the precision; the slab length follows the lattice's setting
-    Launch L = plan(lat, prec);
-    L = plan_with(lat, prec, 0, L.xchunk);
+    // tile shape and slab length of the lattice (the autotuner's choice if it ran for it)
+    const Launch L = plan(lat, prec);
     SweepArgs a = make_args(lat, L, model, flow->dt);
     a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
@@ -1354,7 +1376,9 @@ skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
         skyr_status rc = batch_rebuild(b);
         if (rc != SKYR_OK) return rc;
     }
-    if (b->grid[0] + b->grid[1] > 0) {
+    int blocks = 0;
+    for (int g = 0; g < skyr_batch::kGroups; ++g) blocks += b->grid[g];
+    if (blocks > 0) {
         if (!b->exec || b->graph_sweeps != sweeps) {
             skyr_status rc = batch_capture(b, sweeps);
             if (rc != SKYR_OK) return rc;
@@ -1444,7 +1468,7 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
     (void)hipFree(b->d_args);
     (void)hipFree(b->d_first);
     (void)hipFree(b->d_count);
-    for (int p = 0; p < 2; ++p) (void)hipFree(b->d_map[p]);
+    for (int g = 0; g < skyr_batch::kGroups; ++g) (void)hipFree(b->d_map[g]);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     delete b;
     return SKYR_OK;

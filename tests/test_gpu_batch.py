@@ -81,6 +81,30 @@ def test_batch_equals_single_field_entry_point(skyr):
     assert np.array_equal(phi.cpu().numpy(), res[0])
 
 
+def test_batch_groups_jobs_by_tuned_tile_shape(skyr):
+    """Lattices whose tile shape was set differently (as the autotuner would,
+    per lattice and precision) run in one batch, one launch per shape group;
+    each result equals the single-field entry point's with the same setting."""
+    jobs = [job(30, 0.2, 1.0, 0.02, "f32", 2, 21, flow="power"), job(34, 0.2, 1.0, 0.02, "f32", 3, 22, flow="power"),
+            job(26, 0.25, 1.0, 0.025, "f64", 2, 23), job(38, 0.2, 0.0, 0.02, "f64", 1, 24)]
+    lat_of = lambda d: skyr.Lattice.cube(d["n"], d["h"])
+    saved = [(d, prec, skyr.get_tile(lat_of(d), prec)) for d in jobs for prec in (skyr.F64, skyr.F32_BULK)]
+    try:
+        skyr.set_tile(lat_of(jobs[1]), skyr.F32_BULK, 2, 16)
+        skyr.set_tile(lat_of(jobs[0]), skyr.F32_BULK, 1, 26)
+        skyr.set_tile(lat_of(jobs[3]), skyr.F64, 1, 17)
+        mix = _run_batch(skyr, jobs)
+        for j, d in enumerate(jobs):
+            lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+            st = skyr.anf_state()
+            skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
+            assert st.steps == mix[j][2] and st.arrests == mix[j][3], j
+            assert np.array_equal(phi.cpu().numpy(), mix[j][0]), f"job {j}"
+    finally:
+        for d, prec, (v, x) in saved:
+            skyr.set_tile(lat_of(d), prec, v, x)
+
+
 def test_batch_join_while_running(skyr):
     """A field added after others have run for a while ends bitwise equal to its
     run alone (continuous batching)."""
