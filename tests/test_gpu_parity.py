@@ -449,3 +449,53 @@ def test_full_size_random_b10_sampled(skyr, prec):
         assert np.abs(vh[:, p[0], p[1], p[2]] - vo).max() <= 2 * dt * gerr + rnd * (1 + np.abs(vo).max())
         assert np.abs(ph[:, p[0], p[1], p[2]] - po).max() <= 2 * dt * dt * gerr + 4 * rnd
     assert st.E_prev == pytest.approx(E, rel=1e-12 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_largest_lattice_sampled(skyr, prec):
+    """The largest cube the 32-bit component offsets allow (812^3 < 2^29 sites;
+    813^3 is rejected), filled with 60 unit charges spread over the box:
+    gradient and one flow step on sampled sites, the far corner included,
+    against the oracle evaluated on 9^3 patches around them (the exact gradient
+    at a site reads phi within four sites; patches are cut at the faces)."""
+    n, h, m, dt = 812, 0.1, 1.0, 0.01
+    assert skyr.workspace_bytes(skyr.Lattice.cube(n + 1, h), prec) == 0  # 813^3: rejected
+    lat = skyr.Lattice.cube(n, h)
+    assert skyr.workspace_bytes(lat, prec) > 0
+    spec, keep = skyr.spec_from_description({"kind": "random_product", "B": 60, "seed": 9, "radius": 36.0,
+                                              "prof_lambda": 1.0})
+    print(f"largest lattice {n}^3 prec {prec}: init", flush=True)
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    work = skyr.new_workspace(lat, prec, DEV)
+    g = skyr.new_field(lat, prec, DEV)
+    skyr.energy_gradient(lat, prec, skyr.Model(m), phi, work, grad=g, want_parts=False)
+    pts = _sample_sites((n, n, n), 120, 13) + [(n - 3, n - 3, n - 4), (n - 5, n - 3, n - 3), (n - 4, 2, n - 3)]
+
+    def patch(t, p):
+        lo = [max(0, c - 4) for c in p]
+        hi = [min(n, c + 5) for c in p]
+        a = t[:, lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].double().cpu().numpy()
+        return np.ascontiguousarray(a), tuple(c - l for c, l in zip(p, lo))
+
+    before = [patch(phi, p) for p in pts]
+    ref_g = np.array([oracle.gradient_at(a, h, m, *q) for a, q in before])
+    got_g = np.array([g[:, p[0], p[1], p[2]].double().cpu().numpy() for p in pts])
+    assert np.abs(ref_g).max() > 1.0  # the samples see structure
+    scale = np.abs(ref_g).max()
+    tol = 1e-12 if prec == 0 else 2e-4
+    assert np.abs(got_g - ref_g).max() <= tol * scale
+    del g
+    print("one flow step", flush=True)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(m), skyr.Flow(dt, 0.0, 10 ** 9, 16, 0), phi, alt, vel, st, 1, work)
+    assert st.steps == 1 and np.isfinite(st.E_prev)
+    gerr = tol * scale
+    rnd = 1e-15 if prec == 0 else 2e-7
+    for p, (a, q), gr in zip(pts, before, ref_g):
+        po, vo = oracle.update_at(a[:, q[0], q[1], q[2]], np.zeros(4), gr, dt)
+        vh = vel[:, p[0], p[1], p[2]].double().cpu().numpy()
+        ph = phi[:, p[0], p[1], p[2]].double().cpu().numpy()
+        assert np.abs(vh - vo).max() <= 2 * dt * gerr + rnd * (1 + np.abs(vo).max())
+        assert np.abs(ph - po).max() <= 2 * dt * dt * gerr + 4 * rnd
