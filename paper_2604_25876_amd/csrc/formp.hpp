@@ -7,36 +7,47 @@
 // with the five-point second difference D_ii and the mixed derivative D_i D_j
 // as the product of two first-difference stencils (radius 2 in each of its
 // two directions).  The stencil is one-stage: g at a site depends on phi
-// within the 5 x 5 x 5 box around it, so there is no flux pass.  Everything
-// else (energy density for the arrest test, projection, kick-drift update,
-// renormalisation, partial sums) is that of the exact-gradient sweep.
+// within the 5 x 5 x 5 box around it, so there is no flux pass and no tile
+// overlap.  Everything else (energy density for the arrest test, projection,
+// kick-drift update, renormalisation, partial sums) is that of the
+// exact-gradient sweep.
 //
-// 2.5D march: a block owns a 16 x 16 (y, z) tile and a slab of x; a ring of
-// five phi planes with a two-site halo lives in LDS (plane x + 2 replaces
-// plane x - 3), one thread per (y, z) column, two barriers per plane.
+// 2.5D march: a block owns a 16 x 32 (y, z) tile (one thread per column) and
+// a slab of x.  Each thread keeps, for planes x-2 .. x+2 of its column, phi,
+// D_y phi and D_z phi in register rings: the x-derivatives and D_x D_y, D_x D_z
+// come from registers.  phi planes with a two-site halo pass through a ring of
+// four LDS slots: at plane x the block stages plane x+2 (from a register
+// prefetch), and after one barrier each thread takes D_y, D_z of plane x+2 and
+// the y/z second derivatives and D_y D_z of plane x from LDS.  Plane x+2 goes
+// to the slot of x-2, whose last reads came before the previous barrier.
 #pragma once
 
 #include "sweep.hpp"
 
 namespace skyr {
 
-constexpr int FP_TY = 16, FP_TZ = 16, FP_THREADS = FP_TY * FP_TZ;
-constexpr int FP_H = FP_TY + 4, FP_W = FP_TZ + 4;
-constexpr int FP_XCHUNK = 32;  // planes per slab
+constexpr int FP_LW = 32, FP_ROWS = 16, FP_THREADS = FP_LW * FP_ROWS;
+constexpr int FP_H = FP_ROWS + 4, FP_W = FP_LW + 4;
+constexpr int FP_NH = FP_H * FP_W - FP_ROWS * FP_LW;  // halo sites of a plane
+constexpr int FP_XCHUNK = 64;                         // planes per slab
 
-__host__ __device__ inline int formp_tiles(int n1, int n2) { return ((n1 - 4 + FP_TY - 1) / FP_TY) * ((n2 - 4 + FP_TZ - 1) / FP_TZ); }
+__host__ __device__ inline int formp_tiles(int n1, int n2)
+{
+    return ((n1 - 4 + FP_ROWS - 1) / FP_ROWS) * ((n2 - 4 + FP_LW - 1) / FP_LW);
+}
 __host__ __device__ inline int formp_blocks(int n0, int n1, int n2)
 {
     return formp_tiles(n1, n2) * ((n0 - 4 + FP_XCHUNK - 1) / FP_XCHUNK);
 }
 
 template <typename T> struct FormPSmem {
-    T phi[5][4][FP_H][FP_W];
+    T phi[4][4][FP_H][FP_W];  // [slot][component][row][column]
     double red[FP_THREADS / 64][7];
 };
 
+// float: at most 128 VGPRs, so that two blocks (16 waves) share a CU
 template <typename T, int MODE, bool EXT>
-__global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
+__global__ __launch_bounds__(FP_THREADS, sizeof(T) == 4 ? 4 : 1) void formp_kernel(SweepArgs a)
 {
     __shared__ FormPSmem<T> sm;
     const Ctl* ctl = a.ctl;
@@ -56,19 +67,37 @@ __global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
     T* __restrict__ vel = (T*)a.vel;
     T* __restrict__ gout = (T*)a.grad;
 
-    const int tz_tiles = (n2 - 4 + FP_TZ - 1) / FP_TZ;
+    const int tz_tiles = (n2 - 4 + FP_LW - 1) / FP_LW;
     const int tiles = formp_tiles(n1, n2);
     const int slab = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-    const int y0 = 2 + (tile / tz_tiles) * FP_TY, z0 = 2 + (tile % tz_tiles) * FP_TZ;
+    const int y0 = 2 + (tile / tz_tiles) * FP_ROWS, z0 = 2 + (tile % tz_tiles) * FP_LW;
     const int xb = 2 + slab * a.xchunk, xe = min(n0 - 2, xb + a.xchunk);
-    const int tid = threadIdx.x, ly = tid / FP_TZ, lz = tid % FP_TZ;
+    const int tid = threadIdx.x, ly = tid / FP_LW, lz = tid % FP_LW;
     const int y = y0 + ly, z = z0 + lz;
     const bool out = (y <= n1 - 3) && (z <= n2 - 3);
+    const int r = ly + 2, q = lz + 2;  // LDS position of the own column
+    // own column and, for the first FP_NH threads, one halo site of the tile
+    const size_t own = (size_t)clampi(y, 0, n1 - 1) * n2 + clampi(z, 0, n2 - 1);
+    const bool halo_loader = tid < FP_NH;
+    int hr = 0, hq = 0;
+    {
+        // halo sites: rows 0, 1, FP_H-2, FP_H-1 (all columns), then columns 0, 1,
+        // FP_W-2, FP_W-1 of the other rows
+        const int u = min(tid, FP_NH - 1);
+        if (u < 4 * FP_W) {
+            const int k = u / FP_W;
+            hr = k < 2 ? k : FP_ROWS + k;
+            hq = u % FP_W;
+        } else {
+            const int v = u - 4 * FP_W, k = v & 3;
+            hr = 2 + (v >> 2);
+            hq = k < 2 ? k : FP_LW + k;
+        }
+    }
+    const size_t hoff = (size_t)clampi(y0 - 2 + hr, 0, n1 - 1) * n2 + clampi(z0 - 2 + hq, 0, n2 - 1);
 
     const T c1h = T(Coef<double>::c1 / a.h), c2h = T(Coef<double>::c2 / a.h);
     const T d1h = T(Coef<double>::d1 / (a.h * a.h)), d2h = T(Coef<double>::d2 / (a.h * a.h));
-    const T c1 = Coef<T>::c1, c2 = Coef<T>::c2;
-    const T ih2 = T(1.0 / (a.h * a.h));
     const T dt = T(a.dt);
     const T m2 = T(a.m * a.m), my2 = T(a.m_y * a.m_y), mz2 = T(a.m_z * a.m_z), mw2 = T(a.m_w * a.m_w);
     const bool grad_flow = MODE == MODE_STEP && a.gradient_flow != 0;
@@ -77,84 +106,109 @@ __global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
     double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb = 0.0, pp = 0.0;
     T pf2 = T(0);
 
-    // the plane-load pattern is the same for every plane: thread tid moves elements
-    // tid + 256 k of the 4 x FP_H x FP_W halo tile; its source offsets within a plane
-    // (component, clamped y and z) and LDS positions are fixed up front
-    constexpr int NE = 4 * FP_H * FP_W, NK = (NE + FP_THREADS - 1) / FP_THREADS;
-    unsigned goff[NK];
-    int loff[NK];
+    // register rings over planes x-2 .. x+2 (slots 0 .. 4) of the own column
+    T rphi[5][4], rdy[5][4], rdz[5][4];
+    T nxt[4], hnxt[4];  // prefetch of the next plane to stage: own column and halo site
+
+    auto prefetch = [&](int x) {
+        const size_t xo = (size_t)clampi(x, 0, n0 - 1) * plane;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const int e = min(tid + k * FP_THREADS, NE - 1);
-        const int A = e / (FP_H * FP_W), rem = e % (FP_H * FP_W);
-        const int ry = rem / FP_W, rz = rem % FP_W;
-        const int gy = clampi(y0 - 2 + ry, 0, n1 - 1), gz = clampi(z0 - 2 + rz, 0, n2 - 1);
-        goff[k] = (unsigned)(A * N3) + (unsigned)(gy * n2 + gz);
-        loff[k] = e;
-    }
-    auto load_plane = [&](int x) {
-        T* dst = &sm.phi[x % 5][0][0][0];  // x >= 0
-        const T* src = pin + (size_t)clampi(x, 0, n0 - 1) * plane;
+        for (int A = 0; A < 4; ++A) {
+            nxt[A] = pin[(size_t)A * N3 + xo + own];
+            if (halo_loader) hnxt[A] = pin[(size_t)A * N3 + xo + hoff];
+        }
+    };
+    auto stage = [&](int x) {  // the prefetched plane x into its LDS slot
+        const int sl = x & 3;
 #pragma unroll
-        for (int k = 0; k < NK; ++k)
-            if (k < NK - 1 || tid + k * FP_THREADS < NE) dst[loff[k]] = src[goff[k]];
+        for (int A = 0; A < 4; ++A) {
+            sm.phi[sl][A][r][q] = nxt[A];
+            if (halo_loader) sm.phi[sl][A][hr][hq] = hnxt[A];
+        }
+    };
+    auto take = [&](int x) {  // phi, D_y phi, D_z phi of the staged plane x into ring slot 4
+        const int sl = x & 3;
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+            const T(*P)[FP_W] = sm.phi[sl][A];
+            rphi[4][A] = P[r][q];
+            rdy[4][A] = c1h * (P[r + 1][q] - P[r - 1][q]) + c2h * (P[r + 2][q] - P[r - 2][q]);
+            rdz[4][A] = c1h * (P[r][q + 1] - P[r][q - 1]) + c2h * (P[r][q + 2] - P[r][q - 2]);
+        }
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+                rphi[s][A] = rphi[s + 1][A];
+                rdy[s][A] = rdy[s + 1][A];
+                rdz[s][A] = rdz[s + 1][A];
+            }
     };
 
     if (xb < xe) {
-        for (int x = xb - 2; x <= xb + 1; ++x) load_plane(x);
-        for (int x = xb; x < xe; ++x) {
-            load_plane(x + 2);
+        // prologue: planes xb-2 .. xb+1 into ring slots 1 .. 4
+        prefetch(xb - 2);
+        for (int x = xb - 2; x <= xb + 1; ++x) {
+            stage(x);
+            prefetch(x + 1);
             __syncthreads();
+            shift();
+            take(x);
+        }
+        for (int x = xb; x < xe; ++x) {
+            // stage plane x+2 into the slot of plane x-2 (last read before the previous barrier)
+            stage(x + 2);
+            prefetch(x + 3);
+            const size_t s = (size_t)x * plane + own;
+            T vc[4];
+            if constexpr (MODE == MODE_STEP) {
+#pragma unroll
+                for (int A = 0; A < 4; ++A) vc[A] = (redo || !out) ? T(0) : vel[(size_t)A * N3 + s];
+            }
+            __syncthreads();
+            shift();  // slots 0 .. 3 now hold planes x-2 .. x+1
+            take(x + 2);
             if (out) {
-                const int sm2 = (x - 2) % 5, sm1 = (x - 1) % 5, s0 = x % 5, sp1 = (x + 1) % 5, sp2 = (x + 2) % 5;
-                const int r = ly + 2, q = lz + 2;
-                // pass 1: centre values and first derivatives, then the Gram matrix
+                const int sl = x & 3;  // LDS slot of plane x (ring slot 2)
                 T c[4], ax[4], ay[4], az[4];
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    const T(*P0)[FP_W] = sm.phi[s0][A];
-                    c[A] = P0[r][q];
-                    ax[A] = c1h * (sm.phi[sp1][A][r][q] - sm.phi[sm1][A][r][q]) +
-                            c2h * (sm.phi[sp2][A][r][q] - sm.phi[sm2][A][r][q]);
-                    ay[A] = c1h * (P0[r + 1][q] - P0[r - 1][q]) + c2h * (P0[r + 2][q] - P0[r - 2][q]);
-                    az[A] = c1h * (P0[r][q + 1] - P0[r][q - 1]) + c2h * (P0[r][q + 2] - P0[r][q - 2]);
+                    c[A] = rphi[2][A];
+                    ax[A] = c1h * (rphi[3][A] - rphi[1][A]) + c2h * (rphi[4][A] - rphi[0][A]);
+                    ay[A] = rdy[2][A];
+                    az[A] = rdz[2][A];
                 }
                 const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
                 const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
                 const T S = gxx + gyy + gzz;
-                // pass 2, one component at a time: the second derivatives of component A give
-                //   u_A = (1 + S) Lap_A - sum_ij G_ij (D_i D_j phi)_A,  lap_A,
-                // and their contributions to c_i = sum_j (D_i D_j phi) . a_j - Lap . a_i
+                // per component: u_A = (1 + S) Lap_A - sum_ij G_ij (D_i D_j phi)_A, Lap_A, and the
+                // contributions to c_i = sum_j (D_i D_j phi) . a_j - Lap . a_i
                 T uu[4], lap[4];
                 T cx = T(0), cy = T(0), cz = T(0);
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    const T(*P0)[FP_W] = sm.phi[s0][A];
+                    const T(*P)[FP_W] = sm.phi[sl][A];
                     const T cc = c[A];
-                    auto second = [&](T m2v, T m1v, T p1v, T p2v) {
-                        return d1h * ((p1v - cc) + (m1v - cc)) + d2h * ((p2v - cc) + (m2v - cc));
+                    // five-point second differences from the centre (weights sum to zero)
+                    const T dxx = d1h * ((rphi[3][A] - cc) + (rphi[1][A] - cc)) +
+                                  d2h * ((rphi[4][A] - cc) + (rphi[0][A] - cc));
+                    const T dyy = d1h * ((P[r + 1][q] - cc) + (P[r - 1][q] - cc)) +
+                                  d2h * ((P[r + 2][q] - cc) + (P[r - 2][q] - cc));
+                    const T dzz = d1h * ((P[r][q + 1] - cc) + (P[r][q - 1] - cc)) +
+                                  d2h * ((P[r][q + 2] - cc) + (P[r][q - 2] - cc));
+                    // D_x D_y and D_x D_z from the rings, D_y D_z from the LDS plane
+                    const T dxy = c1h * (rdy[3][A] - rdy[1][A]) + c2h * (rdy[4][A] - rdy[0][A]);
+                    const T dxz = c1h * (rdz[3][A] - rdz[1][A]) + c2h * (rdz[4][A] - rdz[0][A]);
+                    auto dz_row = [&](int rr) {
+                        return c1h * (P[rr][q + 1] - P[rr][q - 1]) + c2h * (P[rr][q + 2] - P[rr][q - 2]);
                     };
-                    const T dxx = second(sm.phi[sm2][A][r][q], sm.phi[sm1][A][r][q], sm.phi[sp1][A][r][q],
-                                         sm.phi[sp2][A][r][q]);
-                    const T dyy = second(P0[r - 2][q], P0[r - 1][q], P0[r + 1][q], P0[r + 2][q]);
-                    const T dzz = second(P0[r][q - 2], P0[r][q - 1], P0[r][q + 1], P0[r][q + 2]);
-                    // D_x D_y: the y-difference on the four x-neighbour planes, then the x-difference
-                    auto dy_on = [&](int sl) {
-                        const T(*Pl)[FP_W] = sm.phi[sl][A];
-                        return c1 * (Pl[r + 1][q] - Pl[r - 1][q]) + c2 * (Pl[r + 2][q] - Pl[r - 2][q]);
-                    };
-                    auto dz_on = [&](int sl, int rr) {
-                        const T* row = sm.phi[sl][A][rr];
-                        return c1 * (row[q + 1] - row[q - 1]) + c2 * (row[q + 2] - row[q - 2]);
-                    };
-                    const T dxy = ih2 * (c1 * (dy_on(sp1) - dy_on(sm1)) + c2 * (dy_on(sp2) - dy_on(sm2)));
-                    const T dxz = ih2 * (c1 * (dz_on(sp1, r) - dz_on(sm1, r)) + c2 * (dz_on(sp2, r) - dz_on(sm2, r)));
-                    const T dyz =
-                        ih2 * (c1 * (dz_on(s0, r + 1) - dz_on(s0, r - 1)) + c2 * (dz_on(s0, r + 2) - dz_on(s0, r - 2)));
+                    const T dyz = c1h * (dz_row(r + 1) - dz_row(r - 1)) + c2h * (dz_row(r + 2) - dz_row(r - 2));
                     const T la = dxx + dyy + dzz;
                     lap[A] = la;
-                    uu[A] = (T(1) + S) * la - (gxx * dxx + gyy * dyy + gzz * dzz +
-                                               T(2) * (gxy * dxy + gxz * dxz + gyz * dyz));
+                    uu[A] = (T(1) + S) * la -
+                            (gxx * dxx + gyy * dyy + gzz * dzz + T(2) * (gxy * dxy + gxz * dxz + gyz * dyz));
                     cx += dxx * ax[A] + dxy * ay[A] + dxz * az[A] - la * ax[A];
                     cy += dxy * ax[A] + dyy * ay[A] + dyz * az[A] - la * ay[A];
                     cz += dxz * ax[A] + dyz * ay[A] + dzz * az[A] - la * az[A];
@@ -163,7 +217,8 @@ __global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
                 T vslope = -m2, vpot = m2 * u;
                 if constexpr (EXT) {
                     vslope -= my2 * c[0] + mz2 * u + mw2 * u * u * u;
-                    vpot += T(0.5) * my2 * (T(1) - c[0] * c[0]) + T(0.5) * mz2 * u * u + T(0.25) * mw2 * (u * u) * (u * u);
+                    vpot += T(0.5) * my2 * (T(1) - c[0] * c[0]) + T(0.5) * mz2 * u * u +
+                            T(0.25) * mw2 * (u * u) * (u * u);
                 }
                 T g[4];
 #pragma unroll
@@ -185,11 +240,8 @@ __global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
 #pragma unroll
                 for (int A = 0; A < 4; ++A) f[A] = gp * c[A] - g[A];
                 pf2 = fmax_nonneg(pf2, dot4(f, f));
-                const size_t s = (size_t)x * plane + (size_t)y * n2 + z;
                 if constexpr (MODE == MODE_STEP) {
-                    T vc[4], v[4], qv[4];
-#pragma unroll
-                    for (int A = 0; A < 4; ++A) vc[A] = redo ? T(0) : vel[(size_t)A * N3 + s];
+                    T v[4], qv[4];
                     pp += (double)dot4(f, vc);
 #pragma unroll
                     for (int A = 0; A < 4; ++A) {
@@ -217,7 +269,6 @@ __global__ __launch_bounds__(FP_THREADS) void formp_kernel(SweepArgs a)
                     for (int A = 0; A < 4; ++A) gout[(size_t)A * N3 + s] = projected ? -f[A] : g[A];
                 }
             }
-            __syncthreads();
         }
     }
 
