@@ -407,26 +407,33 @@ __global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, int nj
 // ------------------------------------------------------------- launches
 // the kernel variant with the extra potentials and the gradient flow is used only
 // by models and flows that need it
-static bool needs_ext(const SweepArgs& a)
+// kernel variant a field needs: the sextic term, else the extra potentials or the
+// gradient flow, else the plain sweep
+static int ext_level(const SweepArgs& a)
 {
-    return a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.c6 != 0.0 || a.gradient_flow != 0;
+    if (a.c6 != 0.0) return EXT_SEXTIC;
+    return (a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.gradient_flow != 0) ? EXT_POT : EXT_NONE;
+}
+
+template <typename T, int NW, int LW, int RY, int MODE>
+static void launch_level(int ext, dim3 grid, dim3 block, const SweepArgs& args, hipStream_t s)
+{
+    if (ext == EXT_SEXTIC)
+        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_SEXTIC>), grid, block, 0, s, args);
+    else if (ext == EXT_POT)
+        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_POT>), grid, block, 0, s, args);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_NONE>), grid, block, 0, s, args);
 }
 
 template <typename T, int NW, int LW, int RY>
 static hipError_t launch_shape(int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
 {
     const dim3 grid(L.blocks()), block(NW * 64);
-    if (needs_ext(args)) {
-        if (mode == MODE_STEP)
-            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP, true>), grid, block, 0, s, args);
-        else
-            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD, true>), grid, block, 0, s, args);
-    } else {
-        if (mode == MODE_STEP)
-            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_STEP, false>), grid, block, 0, s, args);
-        else
-            hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE_GRAD, false>), grid, block, 0, s, args);
-    }
+    if (mode == MODE_STEP)
+        launch_level<T, NW, LW, RY, MODE_STEP>(ext_level(args), grid, block, args, s);
+    else
+        launch_level<T, NW, LW, RY, MODE_GRAD>(ext_level(args), grid, block, args, s);
     return hipGetLastError();
 }
 
@@ -470,7 +477,7 @@ static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattic
 {
     args.xchunk = FP_XCHUNK;
     const dim3 grid(formp_blocks(lat->n[0], lat->n[1], lat->n[2])), block(FP_THREADS);
-    const bool ext = needs_ext(args);
+    const bool ext = ext_level(args) != EXT_NONE;
     if (prec == SKYR_F64)
         launch_printed<double>(mode, ext, grid, block, args, s);
     else
@@ -480,20 +487,23 @@ static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattic
 
 // The batched sweep uses the first compiled shape of each precision.
 template <typename T, int NW, int LW, int RY>
-static hipError_t launch_batch(bool ext, int blocks, const SweepArgs* jobs, const int* map, const int* first,
+static hipError_t launch_batch(int ext, int blocks, const SweepArgs* jobs, const int* map, const int* first,
                                const int* count, hipStream_t s)
 {
-    if (ext)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, true>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
+    if (ext == EXT_SEXTIC)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_SEXTIC>), dim3(blocks), dim3(NW * 64), 0, s, jobs,
+                           map, first, count);
+    else if (ext == EXT_POT)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_POT>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
                            first, count);
     else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, false>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
-                           first, count);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_NONE>), dim3(blocks), dim3(NW * 64), 0, s, jobs,
+                           map, first, count);
     return hipGetLastError();
 }
 
 // the batched sweep of the jobs of one (precision, tile shape) group
-static hipError_t batch_sweep(skyr_precision prec, int variant, bool ext, int blocks, const SweepArgs* jobs,
+static hipError_t batch_sweep(skyr_precision prec, int variant, int ext, int blocks, const SweepArgs* jobs,
                               const int* map, const int* first, const int* count, hipStream_t s)
 {
     int v = 0;
@@ -1173,7 +1183,7 @@ struct skyr_batch {
     int* d_map[kGroups] = {};  // block -> job, per group
     int map_cap[kGroups] = {};
     int grid[kGroups] = {};
-    bool ext[kGroups] = {};  // some job of the group needs the extended kernel variant
+    int ext[kGroups] = {};  // the highest kernel variant a job of the group needs
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1202,12 +1212,12 @@ static_assert(sizeof(kShapesF64) / sizeof(Shape) + sizeof(kShapesF32) / sizeof(S
 static skyr_status batch_rebuild(skyr_batch* b)
 {
     std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[skyr_batch::kGroups];
-    for (int g = 0; g < skyr_batch::kGroups; ++g) b->ext[g] = false;
+    for (int g = 0; g < skyr_batch::kGroups; ++g) b->ext[g] = EXT_NONE;
     for (int j = 0; j < b->max_jobs; ++j) {
         const auto& J = b->jobs[j];
         if (!J.active) continue;
         const int g = batch_group(J.prec, J.L.variant);
-        b->ext[g] = b->ext[g] || needs_ext(b->args[j]);
+        b->ext[g] = std::max(b->ext[g], ext_level(b->args[j]));
         first[j] = (int)map[g].size();
         count[j] = J.L.blocks();
         map[g].insert(map[g].end(), count[j], j);

@@ -213,9 +213,11 @@ template <typename T, int NW, int LW, int RY> struct Tile {
     static_assert(THREADS >= NH, "every halo site of a plane has its own loading thread");
 };
 
-// EXT: the kernel variant with the extra potentials (m_y, m_z, m_w) and the gradient
-// flow; the plain variant has the pion-mass potential and the kick-drift update only.
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, bool EXT = false> struct Sweeper {
+// EXT: 0 the plain variant (pion-mass potential, kick-drift update); 1 adds the extra
+// potentials (m_y, m_z, m_w) and the gradient flow; 2 also the sextic term.  The levels
+// are separate kernels so that each carries only the registers it needs.
+enum : int { EXT_NONE = 0, EXT_POT = 1, EXT_SEXTIC = 2 };
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE> struct Sweeper {
     using TL = Tile<T, NW, LW, RY>;
     static constexpr int PY = TL::PY;
     static constexpr int R0 = TL::R0;
@@ -404,7 +406,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
             const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
             const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
             T e6 = T(0);
-            if constexpr (!EXT) {
+            if constexpr (EXT < EXT_SEXTIC) {
 #pragma unroll
                 for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
                 if (full) {
@@ -461,7 +463,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
                     const T e4 = T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
                     const T e0 = potential(c[0]);
                     if constexpr (MODE == MODE_STEP) {
-                        if constexpr (EXT)
+                        if constexpr (EXT == EXT_SEXTIC)
                             pe2 += (double)(e2 + e4 + e0 + e6);  // the flow needs the total energy only
                         else
                             pe2 += (double)(e2 + e4 + e0);
@@ -469,7 +471,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
                         pe2 += (double)e2;
                         pe4 += (double)e4;
                         pe0 += (double)e0;
-                        if constexpr (EXT) pe6 += (double)e6;
+                        if constexpr (EXT == EXT_SEXTIC) pe6 += (double)e6;
                         if (baryon) pb_sum += (double)det4(c, ax, ay, az);
                     }
                 }
@@ -576,7 +578,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
 // One block's share of one field: logical block b of nb blocks covering the
 // field's work items.  Used by the single-field and the batched kernels
 // (FROM_TABLE: the arguments were read from the batch's job table).
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, bool EXT = false>
+template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
                                             typename Sweeper<T, NW, LW, RY, MODE, FROM_TABLE, EXT>::Smem& smem)
 {
@@ -776,7 +778,7 @@ __device__ __forceinline__ int xcd_logical_block(int i, int n)
     return xcd * q8 + min(xcd, r8) + i / 8;
 }
 
-template <typename T, int NW, int LW, int RY, int MODE, bool EXT>
+template <typename T, int NW, int LW, int RY, int MODE, int EXT>
 __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 {
     __shared__ typename Sweeper<T, NW, LW, RY, MODE, false, EXT>::Smem smem;
@@ -787,7 +789,7 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 // Many fields in one launch: block i (after the XCD remap) belongs to field
 // job_of_block[i] and is its block (i - first_block[job]); every field's blocks
 // and partial sums are exactly those of a launch of that field alone.
-template <typename T, int NW, int LW, int RY, bool EXT>
+template <typename T, int NW, int LW, int RY, int EXT>
 __global__ __launch_bounds__(NW * 64) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
                                                               const int* __restrict__ job_of_block,
                                                               const int* __restrict__ first_block,
