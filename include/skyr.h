@@ -280,6 +280,14 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                              const void* phi, skyr_obs* out, void* work, void* stream);
 
+/* Kinetic energy of a flow's velocity field (Sec. 3: the quantity whose growth
+ * the arrest criterion watches), T = (1/2) h^3 sum over I of |v|^2, in this
+ * library's normalisation (one half of the printed one, like skyr_obs.E).
+ * vel: device field of precision prec; out: host double.  FP64 sums in a
+ * fixed order.  Synchronises `stream`. */
+SKYR_API skyr_status skyr_kinetic_energy(const skyr_lattice* lat, skyr_precision prec, const void* vel, double* out,
+                                         void* work, void* stream);
+
 /* Moment observables of a field (Sec. 5), in the printed (un-halved)
  * normalisation of the Lagrangian, integrals as h^3 sums over the interior I
  * with a_i the fourth-order first differences, coordinates x = (idx - (n-1)/2) h:

@@ -242,6 +242,13 @@ def observables(phi, h: float, m) -> dict:
     return {k: float(v) for k, v in zip(keys, out)}
 
 
+def kinetic(vel, h: float) -> float:
+    """Kinetic energy of a flow velocity, (1/2) h^3 sum over I of |v|^2 (the
+    definition; this library's normalisation)."""
+    v = _field(vel)[:, 2:-2, 2:-2, 2:-2]
+    return float(0.5 * h ** 3 * np.sum(v * v))
+
+
 # ------------------------------------------------------------------------ ANF
 def anf(phi, vel, h: float, m: float, dt: float, tol: float, target_steps: int, state: AnfState | None = None,
         arrest: bool = True, trace: bool = False, rule: str = "energy", form: str = "exact"):

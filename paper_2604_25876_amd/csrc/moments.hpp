@@ -268,4 +268,47 @@ __global__ __launch_bounds__(MOM_THREADS) void moments_finish_kernel(MomArgs a, 
     o[42] = -(2.0 * E / 5.0) * h3 * s[27];
 }
 
+// kinetic energy: per-block sums of |v|^2 over I (slot 0 of the partial records)
+template <typename T>
+__global__ __launch_bounds__(MOM_THREADS) void kinetic_kernel(const T* __restrict__ vel, int n0, int n1, int n2,
+                                                              double* __restrict__ partials)
+{
+    const size_t sy = (size_t)n2, sx = (size_t)n1 * n2, N3 = (size_t)n0 * sx;
+    const int ni1 = n1 - 4, ni2 = n2 - 4;
+    const long long nI = (long long)(n0 - 4) * ni1 * ni2;
+    double acc = 0.0;
+    for (long long q = (long long)blockIdx.x * MOM_THREADS + threadIdx.x; q < nI;
+         q += (long long)gridDim.x * MOM_THREADS) {
+        const int z = 2 + (int)(q % ni2);
+        const long long yx = q / ni2;
+        const int y = 2 + (int)(yx % ni1);
+        const int x = 2 + (int)(yx / ni1);
+        const size_t s = (size_t)x * sx + (size_t)y * sy + (size_t)z;
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+            const double v = (double)vel[(size_t)A * N3 + s];
+            acc += v * v;
+        }
+    }
+    __shared__ double red[MOM_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < MOM_THREADS / 64; ++w) v += red[w];
+        partials[(size_t)blockIdx.x * MOM_NACC] = v;
+    }
+}
+
+__global__ __launch_bounds__(MOM_THREADS) void kinetic_finish_kernel(const double* __restrict__ partials, int nblocks,
+                                                                     double h, double* __restrict__ out)
+{
+    __shared__ double red[MOM_THREADS];
+    const double s = mom_reduce_slot(partials, nblocks, 0, red);
+    if (threadIdx.x == 0) out[0] = 0.5 * h * h * h * s;
+}
+
 }  // namespace skyr

@@ -858,6 +858,33 @@ skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const
     return SKYR_OK;
 }
 
+skyr_status skyr_kinetic_energy(const skyr_lattice* lat, skyr_precision prec, const void* vel, double* out,
+                                void* work, void* stream)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!vel || !out || !work) return fail(SKYR_E_INVAL, "vel, out and work must be non-null");
+    if (!aligned256(work)) return fail(SKYR_E_INVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)work;
+    double* partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+    double* res = (double*)(w + CTL_BYTES + MOM_OUT_OFFSET);
+    const long long nI = (long long)(lat->n[0] - 4) * (lat->n[1] - 4) * (lat->n[2] - 4);
+    const int nb = (int)std::min<long long>(MOM_MAX_BLOCKS, (nI + MOM_THREADS - 1) / MOM_THREADS);
+    if (prec == SKYR_F64)
+        hipLaunchKernelGGL(kinetic_kernel<double>, dim3(nb), dim3(MOM_THREADS), 0, s, (const double*)vel, lat->n[0],
+                           lat->n[1], lat->n[2], partials);
+    else
+        hipLaunchKernelGGL(kinetic_kernel<float>, dim3(nb), dim3(MOM_THREADS), 0, s, (const float*)vel, lat->n[0],
+                           lat->n[1], lat->n[2], partials);
+    SKYR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(kinetic_finish_kernel, dim3(1), dim3(MOM_THREADS), 0, s, partials, nb, lat->h, res);
+    SKYR_HIP(hipGetLastError());
+    SKYR_HIP(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, s));
+    SKYR_HIP(hipStreamSynchronize(s));
+    return SKYR_OK;
+}
+
 skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
                          skyr_moment_obs* out, void* work, void* stream)
 {

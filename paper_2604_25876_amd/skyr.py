@@ -135,6 +135,8 @@ _SIGNATURES = {
     "skyr_load_field": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Lattice), ctypes.c_int,
                                        ctypes.POINTER(Model), _P, _P]),
     "skyr_orientation_zyz": (None, [ctypes.POINTER(ctypes.c_double * 3), ctypes.POINTER(ctypes.c_double * 4)]),
+    "skyr_kinetic_energy": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
+                                           _P, _P]),
     "skyr_moments": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
                                     ctypes.POINTER(MomentObs), _P, _P]),
     "skyr_observables": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model), _P,
@@ -312,6 +314,14 @@ def observables(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -
                                   _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), ctypes.byref(obs),
                                   _dev_ptr(work), _stream(stream)))
     return obs.as_dict()
+
+
+def kinetic_energy(lat: Lattice, prec: int, vel, work, stream=None) -> float:
+    """(1/2) h^3 sum over the interior of |v|^2 (skyr_kinetic_energy)."""
+    out = ctypes.c_double()
+    _check(lib().skyr_kinetic_energy(ctypes.byref(lat), prec, _dev_ptr(vel, field_dtype(prec), (4,) + lat.shape),
+                                     ctypes.byref(out), _dev_ptr(work), _stream(stream)))
+    return float(out.value)
 
 
 def moments(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> dict:

@@ -499,3 +499,21 @@ def test_largest_lattice_sampled(skyr, prec):
         ph = phi[:, p[0], p[1], p[2]].double().cpu().numpy()
         assert np.abs(vh - vo).max() <= 2 * dt * gerr + rnd * (1 + np.abs(vo).max())
         assert np.abs(ph - po).max() <= 2 * dt * dt * gerr + 4 * rnd
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kinetic_energy_matches_oracle(skyr, prec):
+    """Kinetic energy of the velocity after a few flow steps on a ragged lattice
+    against the oracle's definition on the same stored values."""
+    shape, h = (29, 23, 41), 0.2
+    lat = _lat(skyr, shape, h)
+    phi = torch.tensor(random_unit_field(shape, 8, 0.3), dtype=skyr.field_dtype(prec), device=DEV)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(1.0), skyr.Flow(0.01, 0.0, 10 ** 9, 0, skyr.NEWTON_FLOW), phi, alt, vel, st,
+                  5, work)
+    T = skyr.kinetic_energy(lat, prec, vel, work)
+    ref = oracle.kinetic(vel.double().cpu().numpy(), h)
+    assert ref > 0
+    assert T == pytest.approx(ref, rel=1e-13 if prec == 0 else 1e-12)

@@ -627,6 +627,15 @@ def test_spatial_orientation_turns_the_constituent():
     assert np.abs(turned - plain).max() > 0.1
 
 
+def test_kinetic_energy_of_a_uniform_velocity():
+    """(1/2) h^3 sum over the interior of |v|^2: a velocity c on every site
+    (frozen layers included) gives (1/2) h^3 |c|^2 (n-4)^3."""
+    n, h = 9, 0.3
+    c = np.array([0.1, -0.4, 0.25, 2.0])
+    vel = np.broadcast_to(c[:, None, None, None], (4, n, n, n)).copy()
+    assert oracle.kinetic(vel, h) == pytest.approx(0.5 * h ** 3 * (c @ c) * (n - 4) ** 3, rel=1e-14)
+
+
 def test_product_and_isorotation_against_pauli_matrices():
     """The quaternion product and D(A) used for the product ansatz agree with
     explicit 2x2 matrix products U = U1 (A U2 A^dagger) (Sec. 4.2, Sec. 5.3)."""
