@@ -119,3 +119,35 @@ def test_printed_form_is_rejected_where_unsupported(skyr):
         with pytest.raises(skyr.SkyrError) as e:
             b.add(lat, 0, _model(skyr, (1.0,)), skyr.Flow(0.02, 1e-4, 100, 0, 0), phi, alt, vel, work)
         assert e.value.status == skyr.E_INVAL
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", [(5, 5, 5), (5, 7, 6), (6, 5, 37)])
+def test_printed_form_on_the_smallest_lattices(skyr, prec, shape):
+    """One interior site (5^3), one interior row, a thin slab: every stencil
+    reaches the frozen layers."""
+    h = 0.3
+    phi = random_unit_field(shape, 3, 0.8)
+    if prec == 1:
+        phi = phi.astype(np.float32).astype(np.float64)
+    lat = _lat(skyr, shape, h)
+    g = skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    t = torch.tensor(phi, dtype=skyr.field_dtype(prec), device=DEV)
+    skyr.energy_gradient(lat, prec, _model(skyr, (0.7,)), t, work, grad=g)
+    ref = oracle.gradient_literal(phi, h, 0.7)
+    assert _rel_inf(g.double().cpu().numpy(), ref) <= (1e-12 if prec == 0 else 3e-5)
+
+
+def test_printed_form_reports_nonfinite_input(skyr):
+    lat = skyr.Lattice.cube(16, 0.2)
+    phi = skyr.new_field(lat, 0, DEV)
+    phi[0] = 1.0
+    phi[1, 7, 9, 8] = float("nan")
+    alt, vel = skyr.new_field(lat, 0, DEV), skyr.new_field(lat, 0, DEV)
+    work = skyr.new_workspace(lat, 0, DEV)
+    st = skyr.anf_state()
+    with pytest.raises(skyr.SkyrError) as e:
+        skyr.anf_step(lat, 0, _model(skyr, (1.0,)), skyr.Flow(0.02, 0.0, 10, 0, skyr.ARREST_POWER), phi, alt, vel,
+                      st, 10, work)
+    assert e.value.status == skyr.E_NONFINITE and st.nonfinite == 1
