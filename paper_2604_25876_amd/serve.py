@@ -63,6 +63,12 @@ class GpuBackend:
         self.batch = skyr.Batch(max_jobs)
         self.bufs = {}
 
+    def _model(self, desc):
+        """The request's model: the pion mass "m" and, optionally, "m_y", "m_z",
+        "m_w" and the sextic weight "c6"."""
+        return self.skyr.Model(desc["m"], desc.get("m_y", 0.0), desc.get("m_z", 0.0), desc.get("m_w", 0.0),
+                               desc.get("c6", 0.0))
+
     @staticmethod
     def _prec(desc):
         from . import skyr
@@ -88,7 +94,7 @@ class GpuBackend:
         work = s.new_workspace(lat, prec, self.device)
         flow = s.Flow(desc["dt"], desc["tol"], int(desc["steps"]), int(desc.get("renorm64_every", 16)),
                       s.flow_mode(desc.get("flow", "energy")))
-        slot = self.batch.add(lat, prec, s.Model(desc["m"]), flow, phi, alt, vel, work)
+        slot = self.batch.add(lat, prec, self._model(desc), flow, phi, alt, vel, work)
         self.bufs[slot] = (lat, prec, desc, phi, alt, vel, work)
         return slot
 
@@ -105,7 +111,7 @@ class GpuBackend:
         s = self.skyr
         lat, prec, desc, phi, alt, vel, work = self.bufs.pop(slot)
         self.batch.remove(slot)
-        out = s.observables(lat, prec, s.Model(desc["m"]), phi, work)
+        out = s.observables(lat, prec, self._model(desc), phi, work)
         if keep_field:
             out["field"] = phi
         return out

@@ -142,3 +142,25 @@ def test_served_stream_results_equal_alone(skyr):
         alone = _run_batch(skyr, [r.desc])[0]
         assert r.state["steps"] == alone[2]
         assert np.array_equal(r.result["field"].cpu().numpy(), alone[0]), r.rid
+
+
+def test_served_requests_with_extended_models(skyr):
+    """Requests that carry the extra potentials and the sextic term run in the
+    same batch as plain ones; each result equals the single-field flow with that
+    model."""
+    from paper_2604_25876_amd.serve import GpuBackend, Request, Server
+    jobs = [dict(MIX[0], m_y=0.5, m_z=0.3), dict(MIX[1], c6=0.05), dict(MIX[3])]
+    be = GpuBackend(max_jobs=3)
+    srv = Server(be, max_jobs=3, hbm_budget=2 ** 30, sweeps_per_tick=16, keep_fields=True)
+    rep = srv.serve([Request(d, arrival=0.0, rid=i) for i, d in enumerate(jobs)])
+    be.close()
+    assert rep["jobs"] == 3
+    for r in srv.done:
+        d = r.desc
+        lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+        model = skyr.Model(d["m"], d.get("m_y", 0.0), d.get("m_z", 0.0), d.get("m_w", 0.0), d.get("c6", 0.0))
+        st = skyr.anf_state()
+        skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, d["steps"], work)
+        assert r.state["steps"] == st.steps and r.state["arrests"] == st.arrests, r.rid
+        assert np.array_equal(r.result["field"].cpu().numpy(), phi.cpu().numpy()), r.rid
+        assert r.result["E6"] > 0 if d.get("c6") else r.result["E6"] == 0.0
