@@ -29,15 +29,28 @@ namespace skyr {
 constexpr int FP_LW = 32, FP_ROWS = 16, FP_THREADS = FP_LW * FP_ROWS;
 constexpr int FP_H = FP_ROWS + 4, FP_W = FP_LW + 4;
 constexpr int FP_NH = FP_H * FP_W - FP_ROWS * FP_LW;  // halo sites of a plane
-constexpr int FP_XCHUNK = 64;                         // planes per slab
 
 __host__ __device__ inline int formp_tiles(int n1, int n2)
 {
     return ((n1 - 4 + FP_ROWS - 1) / FP_ROWS) * ((n2 - 4 + FP_LW - 1) / FP_LW);
 }
-__host__ __device__ inline int formp_blocks(int n0, int n1, int n2)
+// planes per slab: the even split of x into the most slabs (of at least 16
+// planes) whose blocks fit one round of the chip, two blocks per CU in float
+// and one in double (the LDS ring of four planes)
+__host__ __device__ inline int formp_chunk(int n0, int n1, int n2, bool dbl)
 {
-    return formp_tiles(n1, n2) * ((n0 - 4 + FP_XCHUNK - 1) / FP_XCHUNK);
+    const int nx = n0 - 4, tiles = formp_tiles(n1, n2);
+    const int target = dbl ? 256 : 512;
+    int slabs = target / (tiles > 0 ? tiles : 1);
+    const int most = nx / 16 > 1 ? nx / 16 : 1;
+    slabs = slabs < 1 ? 1 : (slabs > most ? most : slabs);
+    const int xc = (nx + slabs - 1) / slabs;
+    return xc < 16 ? 16 : xc;
+}
+__host__ __device__ inline int formp_blocks(int n0, int n1, int n2, bool dbl)
+{
+    const int xc = formp_chunk(n0, n1, n2, dbl);
+    return formp_tiles(n1, n2) * ((n0 - 4 + xc - 1) / xc);
 }
 
 template <typename T> struct FormPSmem {

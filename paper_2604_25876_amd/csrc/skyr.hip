@@ -148,7 +148,7 @@ static size_t workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
 {
     int most = 0;
     for (int v = 0; v < shape_count(prec); ++v) most = std::max(most, plan_with(lat, prec, v, kMinChunk).blocks());
-    most = std::max(most, formp_blocks(lat->n[0], lat->n[1], lat->n[2]));
+    most = std::max(most, formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64));
     const size_t sweep_part = (size_t)most * NPART * sizeof(double);
     const size_t mom_part = (size_t)MOM_MAX_BLOCKS * MOM_NACC * sizeof(double);
     return CTL_BYTES + OBS_BYTES + std::max(sweep_part, mom_part);
@@ -475,8 +475,9 @@ static void launch_printed(int mode, bool ext, dim3 grid, dim3 block, const Swee
 // The printed-form sweep: one launch over formp_blocks() blocks.
 static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattice* lat, SweepArgs args, hipStream_t s)
 {
-    args.xchunk = FP_XCHUNK;
-    const dim3 grid(formp_blocks(lat->n[0], lat->n[1], lat->n[2])), block(FP_THREADS);
+    const bool dbl = prec == SKYR_F64;
+    args.xchunk = formp_chunk(lat->n[0], lat->n[1], lat->n[2], dbl);
+    const dim3 grid(formp_blocks(lat->n[0], lat->n[1], lat->n[2], dbl)), block(FP_THREADS);
     const bool ext = ext_level(args) != EXT_NONE;
     if (prec == SKYR_F64)
         launch_printed<double>(mode, ext, grid, block, args, s);
@@ -790,7 +791,7 @@ static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, co
     else
         SKYR_HIP(sweep(prec, MODE_GRAD, L, a, s));
     if (obs_out) {
-        const int nb = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2]) : L.blocks();
+        const int nb = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64) : L.blocks();
         hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, nb, lat->h, obs);
         SKYR_HIP(hipGetLastError());
         SKYR_HIP(hipMemcpyAsync(obs_out, obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -969,7 +970,7 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
     h.flow_mode = flow->mode;
     const bool printed = model->form == SKYR_FORM_PRINTED;
-    h.nblocks = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2]) : L.blocks();
+    h.nblocks = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64) : L.blocks();
     h.E_prev = st->E_prev;
     h.E = st->E;
     h.max_force = st->max_force;
