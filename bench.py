@@ -42,6 +42,18 @@ def kernel_source_hash() -> str:
     return hsh.hexdigest()
 
 
+def _summary(name):
+    """`key: value` lines of a committed profile summary, or None."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as fh:
+            kv = dict(line.split(":", 1) for line in fh.read().splitlines()
+                      if ":" in line and not line.startswith(("#", "|", "`", " ")))
+    except OSError:
+        return None
+    return {k.strip(): v.strip() for k, v in kv.items()}
+
+
 def recorded_traffic(prec_name, tile):
     """HBM bytes per sweep launch from the committed counter summary, or None.
 
@@ -50,14 +62,9 @@ def recorded_traffic(prec_name, tile):
     counter, the tile and the kernel-source hash the counters were taken
     with).  Counters taken on other kernel sources or another tile do not
     describe this launch and give None."""
-    path = os.path.join(ROOT, "profiles", "sweep_traffic_random-b10-256.md")
-    try:
-        with open(path) as fh:
-            kv = dict(line.split(":", 1) for line in fh.read().splitlines()
-                      if ":" in line and not line.startswith(("#", "|", "`", " ")))
-    except OSError:
+    kv = _summary("sweep_traffic_random-b10-256.md")
+    if not kv:
         return None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("source_sha256") != kernel_source_hash():
         return None
     if kv.get(f"{prec_name}_tile") != f"{tile[0]}:{tile[1]}":
@@ -68,6 +75,36 @@ def recorded_traffic(prec_name, tile):
     except (KeyError, ValueError):
         return None
     return 1024.0 * (fetch + write)
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 vector instruction per
+# SIMD every 4 cycles (16 lanes per SIMD), in wave-instructions per second
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def recorded_valu(prec_name, tile):
+    """VALU wave-instructions per sweep launch (SQ_INSTS_VALU) from the committed
+    counter summary, or None when the kernel sources or the tile differ."""
+    kv = _summary("sweep_instructions_random-b10-256.md")
+    if not kv or kv.get("source_sha256") != kernel_source_hash():
+        return None
+    if kv.get(f"{prec_name}_tile") != f"{tile[0]}:{tile[1]}":
+        return None
+    try:
+        return float(kv[f"{prec_name}_valu_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_roofline(prec_name, tile, kernel_avg_s):
+    """The sweep against the VALU issue rate: recorded instructions per launch
+    over the live kernel time, as a fraction of the issue peak."""
+    inst = recorded_valu(prec_name, tile)
+    if inst is None:
+        return None
+    rate = inst / kernel_avg_s
+    return {"bound": "alu", "achieved": rate / 1e9, "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave-instructions/s",
+            "frac": rate / VALU_ISSUE_PEAK, "valu_per_launch": inst}
 
 
 def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, mode=None, form=0):
@@ -123,7 +160,7 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, m
         sweep_kernel_avg_us=kernel_avg_s * 1e6, sweep_launches=sweep_n, bytes_per_launch=bytes_launch,
         achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"],
         arrest=rule, tile={"variant": tile[0], "shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]},
-        traffic=recorded_traffic(prec_name, tile))
+        traffic=recorded_traffic(prec_name, tile), valu=valu_roofline(prec_name, tile, kernel_avg_s))
 
 
 def time_moments(skyr, torch, w, prec_name, reps=5):
@@ -385,6 +422,8 @@ def main():
                      "sweep_kernel_avg_us": r64["sweep_kernel_avg_us"], "achieved_GBs": r64["achieved_GBs"],
                      "arrests": r64["arrests"], "sweeps": r64["sweeps"], "traffic": r64["traffic"]},
         "speedup_f32_over_f64": r32["site_updates_per_s"] / r64["site_updates_per_s"],
+        "valu_issue": {"f32": r32["valu"], "f64": r64["valu"]},
+        "sweeps_per_s": {"f32": r32["sweeps"] / r32["elapsed_s"], "f64": r64["sweeps"] / r64["elapsed_s"]},
         "f32_four_potentials": {"m_my_mz_mw": list(pot_model), "value": rpot["site_updates_per_s"],
                                 "sweep_kernel_avg_us": rpot["sweep_kernel_avg_us"], "steps": rpot["steps"],
                                 "E": rpot["E"]},
