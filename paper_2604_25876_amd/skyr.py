@@ -211,6 +211,21 @@ def _dev_ptr(t, dtype=None, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _work_ptr(work, lat: Lattice, prec: int):
+    """The workspace pointer, after checking on the host that the tensor is a
+    contiguous device buffer of at least workspace_bytes(lat, prec) bytes (the
+    library cannot see the size of what it is given; it checks the alignment)."""
+    if work is None:
+        raise ValueError("a workspace is required")
+    if not work.is_cuda or not work.is_contiguous():
+        raise ValueError("workspace must be a contiguous GPU tensor")
+    need = workspace_bytes(lat, prec)
+    have = work.numel() * work.element_size()
+    if have < need:
+        raise ValueError(f"workspace of {have} bytes, this lattice and precision need {need}")
+    return ctypes.c_void_p(work.data_ptr())
+
+
 def field_dtype(prec: int):
     import torch
     return torch.float64 if prec == F64 else torch.float32
@@ -288,7 +303,7 @@ def energy_gradient(lat: Lattice, prec: int, model: Model, phi, work, grad=None,
     _check(lib().skyr_energy_gradient(ctypes.byref(lat), prec, ctypes.byref(model),
                                       _dev_ptr(phi, field_dtype(prec), shape),
                                       _dev_ptr(grad, field_dtype(prec), shape), int(bool(projected)),
-                                      ctypes.byref(obs) if want_parts else None, _dev_ptr(work), _stream(stream)))
+                                      ctypes.byref(obs) if want_parts else None, _work_ptr(work, lat, prec), _stream(stream)))
     return obs.as_dict() if want_parts else None
 
 
@@ -304,7 +319,7 @@ def anf_step(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, ve
     dt = field_dtype(prec)
     _check(lib().skyr_anf_step(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
-                               ctypes.byref(state), int(nsteps), _dev_ptr(work), _stream(stream)))
+                               ctypes.byref(state), int(nsteps), _work_ptr(work, lat, prec), _stream(stream)))
     return state
 
 
@@ -312,7 +327,7 @@ def observables(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -
     obs = Obs()
     _check(lib().skyr_observables(ctypes.byref(lat), prec, ctypes.byref(model),
                                   _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), ctypes.byref(obs),
-                                  _dev_ptr(work), _stream(stream)))
+                                  _work_ptr(work, lat, prec), _stream(stream)))
     return obs.as_dict()
 
 
@@ -320,7 +335,7 @@ def kinetic_energy(lat: Lattice, prec: int, vel, work, stream=None) -> float:
     """(1/2) h^3 sum over the interior of |v|^2 (skyr_kinetic_energy)."""
     out = ctypes.c_double()
     _check(lib().skyr_kinetic_energy(ctypes.byref(lat), prec, _dev_ptr(vel, field_dtype(prec), (4,) + lat.shape),
-                                     ctypes.byref(out), _dev_ptr(work), _stream(stream)))
+                                     ctypes.byref(out), _work_ptr(work, lat, prec), _stream(stream)))
     return float(out.value)
 
 
@@ -330,7 +345,7 @@ def moments(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> di
     out = MomentObs()
     _check(lib().skyr_moments(ctypes.byref(lat), prec, ctypes.byref(model),
                               _dev_ptr(phi, field_dtype(prec), (4,) + lat.shape), ctypes.byref(out),
-                              _dev_ptr(work), _stream(stream)))
+                              _work_ptr(work, lat, prec), _stream(stream)))
     return out.as_dict()
 
 
@@ -445,7 +460,7 @@ def autotune(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, ve
     v, x, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(lib().skyr_autotune(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
-                               _dev_ptr(work), _stream(stream), ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
+                               _work_ptr(work, lat, prec), _stream(stream), ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
     return int(v.value), int(x.value), float(us.value)
 
 
@@ -482,14 +497,16 @@ def autotune_cached(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_
 # ---------------------------------------------------------------- batches
 class Batch:
     """Owner of a skyr_batch (many flows advanced by shared launches).  Field,
-    velocity and workspace tensors belong to the caller and must stay alive
-    while their flow is in the batch."""
+    velocity and workspace tensors belong to the caller; the batch keeps a
+    reference to each flow's tensors until the flow is removed, so that their
+    memory is not reused while its launches still write to it."""
 
     def __init__(self, max_jobs: int, stream=None):
         h = ctypes.c_void_p()
         _check(lib().skyr_batch_create(int(max_jobs), _stream(stream), ctypes.byref(h)))
         self._h = h
         self.max_jobs = int(max_jobs)
+        self._tensors = {}
 
     def add(self, lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work) -> int:
         shape = (4,) + lat.shape
@@ -497,7 +514,8 @@ class Batch:
         slot = ctypes.c_int32()
         _check(lib().skyr_batch_add(self._h, ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                     _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
-                                    _dev_ptr(vel, dt, shape), _dev_ptr(work), ctypes.byref(slot)))
+                                    _dev_ptr(vel, dt, shape), _work_ptr(work, lat, prec), ctypes.byref(slot)))
+        self._tensors[int(slot.value)] = (phi, phi_alt, vel, work)
         return int(slot.value)
 
     def run(self, sweeps: int) -> None:
@@ -512,6 +530,7 @@ class Batch:
 
     def remove(self, slot: int) -> None:
         _check(lib().skyr_batch_remove(self._h, int(slot)))
+        self._tensors.pop(int(slot), None)
 
     def active(self) -> int:
         return int(lib().skyr_batch_active(self._h))
@@ -520,6 +539,7 @@ class Batch:
         if self._h:
             _check(lib().skyr_batch_destroy(self._h))
             self._h = ctypes.c_void_p()
+            self._tensors.clear()
 
     def __enter__(self):
         return self

@@ -118,6 +118,39 @@ def test_invalid_arguments_rejected_without_device_work():
     assert L.skyr_init_field(ctypes.byref(lat), 0, ctypes.byref(spec), fake, None) == skyr.E_INVAL
 
 
+class _FakeDeviceBuffer:
+    """Stands in for a device tensor on the host: only what the binding's
+    workspace check reads."""
+    is_cuda = True
+
+    def __init__(self, nbytes):
+        self.nbytes = nbytes
+
+    def is_contiguous(self):
+        return True
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
+
+    def data_ptr(self):
+        return 0x100000
+
+
+def test_workspace_size_checked_before_the_call():
+    """The C entry points cannot see the size of the workspace they are given;
+    the binding refuses one smaller than skyr_workspace_bytes."""
+    lat = skyr.Lattice.cube(40, 0.2)
+    need = skyr.workspace_bytes(lat, skyr.F64)
+    assert skyr._work_ptr(_FakeDeviceBuffer(need), lat, skyr.F64).value == 0x100000
+    with pytest.raises(ValueError, match="workspace of"):
+        skyr._work_ptr(_FakeDeviceBuffer(need - 1), lat, skyr.F64)
+    with pytest.raises(ValueError):
+        skyr._work_ptr(None, lat, skyr.F64)
+
+
 def test_random_constituents_host_side():
     cs = skyr.random_constituents(1, 10, 3.0)
     assert len(cs) == 10

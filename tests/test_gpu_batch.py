@@ -164,3 +164,24 @@ def test_served_requests_with_extended_models(skyr):
         assert r.state["steps"] == st.steps and r.state["arrests"] == st.arrests, r.rid
         assert np.array_equal(r.result["field"].cpu().numpy(), phi.cpu().numpy()), r.rid
         assert r.result["E6"] > 0 if d.get("c6") else r.result["E6"] == 0.0
+
+
+def test_batch_keeps_its_tensors_until_removed(skyr):
+    """A flow's tensors stay referenced by the batch while the flow is in it,
+    so a caller that drops its own references cannot hand their memory back
+    to the allocator under the batch's launches."""
+    import gc
+    import weakref
+    d = MIX[0]
+    with skyr.Batch(2) as b:
+        lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+        slot = b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
+        refs = [weakref.ref(t) for t in (phi, alt, vel, work)]
+        del phi, alt, vel, work
+        gc.collect()
+        assert all(r() is not None for r in refs)
+        b.run(4)
+        assert b.poll(slot).steps > 0
+        b.remove(slot)
+        gc.collect()
+        assert all(r() is None for r in refs)
