@@ -1216,6 +1216,12 @@ struct skyr_batch {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_sweeps = 0;
+    // the groups of one sweep slot are independent launches: the captured graph forks
+    // them onto side streams so that one group's blocks fill the CUs another group's
+    // tail leaves idle, and joins them before the slot's finaliser
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    std::vector<hipEvent_t> events;  // fork and join events of the captured slots
 };
 
 namespace skyr {
@@ -1273,14 +1279,39 @@ static skyr_status batch_rebuild(skyr_batch* b)
 static skyr_status batch_capture(skyr_batch* b, int sweeps)
 {
     batch_release_graph(b);
+    int used[skyr_batch::kGroups];
+    int nu = 0;
+    for (int g = 0; g < skyr_batch::kGroups; ++g)
+        if (b->grid[g]) used[nu++] = g;
+    const int nside = std::min(std::max(nu - 1, 0), skyr_batch::kSide);
+    const size_t per_slot = 1 + skyr_batch::kSide;  // one fork and up to kSide joins
+    for (int j = 0; j < nside; ++j)
+        if (!b->side[j]) SKYR_HIP(hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking));
+    while (b->events.size() < (size_t)sweeps * per_slot) {
+        hipEvent_t ev = nullptr;
+        SKYR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->events.push_back(ev);
+    }
     SKYR_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
-        for (int g = 0; g < skyr_batch::kGroups && e == hipSuccess; ++g) {
-            if (!b->grid[g]) continue;
+        hipEvent_t* ev = &b->events[(size_t)k * per_slot];
+        if (nside > 0) e = hipEventRecord(ev[0], b->capture);
+        for (int i = 0; i < nu && e == hipSuccess; ++i) {
+            const int g = used[i];
+            hipStream_t s = b->capture;
+            if (i > 0) {
+                s = b->side[(i - 1) % nside];
+                if (i <= nside) e = hipStreamWaitEvent(s, ev[0], 0);
+                if (e != hipSuccess) break;
+            }
             const bool f64 = g < shape_count(SKYR_F64);
             e = batch_sweep(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[g], b->grid[g],
-                            b->d_args, b->d_map[g], b->d_first, b->d_count, b->capture);
+                            b->d_args, b->d_map[g], b->d_first, b->d_count, s);
+        }
+        for (int j = 0; j < nside && e == hipSuccess; ++j) {
+            e = hipEventRecord(ev[1 + j], b->side[j]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->capture, ev[1 + j], 0);
         }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->max_jobs), dim3(256), 0, b->capture, b->d_args,
@@ -1508,6 +1539,9 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
     (void)hipFree(b->d_count);
     for (int g = 0; g < skyr_batch::kGroups; ++g) (void)hipFree(b->d_map[g]);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (hipStream_t s : b->side)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
     delete b;
     return SKYR_OK;
 }
