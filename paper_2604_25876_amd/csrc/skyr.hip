@@ -396,11 +396,11 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
 
 __global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl) { finalize_flow(part, ctl); }
 
-// one block per field of a batch
-__global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, int njobs)
+// one block per field of one group of a batch: block i finalises field list[i]
+__global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, const int* __restrict__ list, int n)
 {
-    const int j = blockIdx.x;
-    if (j >= njobs) return;
+    if ((int)blockIdx.x >= n) return;
+    const int j = list[blockIdx.x];
     finalize_flow(jobs[j].partials, jobs[j].ctl);
 }
 
@@ -1203,25 +1203,34 @@ struct skyr_batch {
     std::vector<Ctl> ctl;            // host mirror of d_ctl (valid after a run / poll)
     Ctl* d_ctl = nullptr;            // [max_jobs]
     SweepArgs* d_args = nullptr;     // [max_jobs]
-    int* d_first = nullptr;          // [max_jobs] first block of a job in its precision's grid
+    int* d_first = nullptr;          // [max_jobs] first block of a job in its chain's grid
     int* d_count = nullptr;          // [max_jobs] blocks of a job
-    // jobs are grouped by (precision, tile shape): group g < F64 shape count is F64 shape g,
-    // the rest F32 shape g - (F64 shape count); one batched launch per group and sweep slot
+    // Jobs are grouped by (precision, tile shape): group g < F64 shape count is F64 shape g,
+    // the rest F32 shape g - (F64 shape count); one kernel serves a group.  A group's jobs
+    // are split into one or more chains (balanced by blocks); a chain is one batched launch
+    // and one finaliser of its own jobs per sweep slot.  Chains share no field, so their
+    // sequences of sweep slots are independent: the captured graph forks them onto side
+    // streams, where one chain's blocks fill the CUs another chain's last round leaves
+    // idle, and joins them at its end.
     static constexpr int kGroups = 16;
-    int* d_map[kGroups] = {};  // block -> job, per group
-    int map_cap[kGroups] = {};
-    int grid[kGroups] = {};
-    int ext[kGroups] = {};  // the highest kernel variant a job of the group needs
+    static constexpr int kSide = 3;
+    static constexpr int kStreams = 1 + kSide;
+    static constexpr int kChains = kGroups * kStreams;
+    int nchains = 0;
+    int chain_group[kChains] = {};
+    int* d_map[kChains] = {};  // block -> job, per chain
+    int map_cap[kChains] = {};
+    int grid[kChains] = {};
+    int* d_list[kChains] = {};  // the jobs of each chain (for its finaliser)
+    int list_cap[kChains] = {};
+    int nlist[kChains] = {};
+    int ext[kChains] = {};  // the highest kernel variant a job of the chain needs
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_sweeps = 0;
-    // the groups of one sweep slot are independent launches: the captured graph forks
-    // them onto side streams so that one group's blocks fill the CUs another group's
-    // tail leaves idle, and joins them before the slot's finaliser
-    static constexpr int kSide = 3;
     hipStream_t side[kSide] = {};
-    std::vector<hipEvent_t> events;  // fork and join events of the captured slots
+    hipEvent_t events[kStreams] = {};  // fork, then the join of each side stream
 };
 
 namespace skyr {
@@ -1242,31 +1251,71 @@ static int batch_group(skyr_precision prec, int variant)
 static_assert(sizeof(kShapesF64) / sizeof(Shape) + sizeof(kShapesF32) / sizeof(Shape) <= skyr_batch::kGroups,
               "batch groups");
 
-// rebuild the device job tables and block maps from the host description
+// upload `v` to a device array of at least v.size() ints, growing it when needed
+static skyr_status upload_ints(const std::vector<int>& v, int*& d, int& cap)
+{
+    const int n = (int)v.size();
+    if (n > cap) {
+        if (d) SKYR_HIP(hipFree(d));
+        d = nullptr;
+        SKYR_HIP(hipMalloc((void**)&d, sizeof(int) * n));
+        cap = n;
+    }
+    if (n) SKYR_HIP(hipMemcpy(d, v.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    return SKYR_OK;
+}
+
+// rebuild the device job tables, chains and block maps from the host description
 static skyr_status batch_rebuild(skyr_batch* b)
 {
-    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), map[skyr_batch::kGroups];
-    for (int g = 0; g < skyr_batch::kGroups; ++g) b->ext[g] = EXT_NONE;
+    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), of_group[skyr_batch::kGroups];
+    int groups = 0;
     for (int j = 0; j < b->max_jobs; ++j) {
         const auto& J = b->jobs[j];
         if (!J.active) continue;
-        const int g = batch_group(J.prec, J.L.variant);
-        b->ext[g] = std::max(b->ext[g], ext_level(b->args[j]));
-        first[j] = (int)map[g].size();
         count[j] = J.L.blocks();
-        map[g].insert(map[g].end(), count[j], j);
+        auto& v = of_group[batch_group(J.prec, J.L.variant)];
+        groups += v.empty() ? 1 : 0;
+        v.push_back(j);
     }
+    // chains per group: the streams shared out over the groups present, at most two (four
+    // concurrent chains of one kernel ran the 64-job mix 3% slower than one; two match it)
+    const int parts = std::min(2, std::max(1, skyr_batch::kStreams / std::max(groups, 1)));
+    std::vector<int> map[skyr_batch::kChains], list[skyr_batch::kChains];
+    int nc = 0;
     for (int g = 0; g < skyr_batch::kGroups; ++g) {
-        const int n = (int)map[g].size();
-        if (n > b->map_cap[g]) {
-            if (b->d_map[g]) SKYR_HIP(hipFree(b->d_map[g]));
-            b->d_map[g] = nullptr;
-            SKYR_HIP(hipMalloc((void**)&b->d_map[g], sizeof(int) * n));
-            b->map_cap[g] = n;
+        auto& v = of_group[g];
+        if (v.empty()) continue;
+        const int np = std::min(parts, (int)v.size());
+        // largest jobs first, each to the chain with the fewest blocks so far
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return count[x] > count[y]; });
+        std::vector<long long> load(np, 0);
+        for (int j : v) {
+            const int c = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[c] += count[j];
+            list[nc + c].push_back(j);
         }
-        if (n) SKYR_HIP(hipMemcpy(b->d_map[g], map[g].data(), sizeof(int) * n, hipMemcpyHostToDevice));
-        b->grid[g] = n;
+        for (int c = 0; c < np; ++c) {
+            b->chain_group[nc + c] = g;
+            // jobs of a chain in slot order, so that the block map does not depend on their sizes
+            std::sort(list[nc + c].begin(), list[nc + c].end());
+        }
+        nc += np;
     }
+    for (int c = 0; c < skyr_batch::kChains; ++c) {
+        b->ext[c] = EXT_NONE;
+        for (int j : list[c]) {
+            b->ext[c] = std::max(b->ext[c], ext_level(b->args[j]));
+            first[j] = (int)map[c].size();
+            map[c].insert(map[c].end(), count[j], j);
+        }
+        skyr_status rc = upload_ints(map[c], b->d_map[c], b->map_cap[c]);
+        if (rc == SKYR_OK) rc = upload_ints(list[c], b->d_list[c], b->list_cap[c]);
+        if (rc != SKYR_OK) return rc;
+        b->grid[c] = (int)map[c].size();
+        b->nlist[c] = (int)list[c].size();
+    }
+    b->nchains = nc;
     SKYR_HIP(hipMemcpy(b->d_first, first.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_count, count.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_args, b->args.data(), sizeof(SweepArgs) * b->max_jobs, hipMemcpyHostToDevice));
@@ -1275,49 +1324,41 @@ static skyr_status batch_rebuild(skyr_batch* b)
     return SKYR_OK;
 }
 
-// capture `sweeps` sweep slots: per slot, the batched sweep of each precision and the finaliser
+// capture `sweeps` sweep slots of every chain: per slot, the chain's batched sweep and the
+// finaliser of its jobs; chain c runs on stream c mod kStreams (0: the capture stream)
 static skyr_status batch_capture(skyr_batch* b, int sweeps)
 {
     batch_release_graph(b);
-    int used[skyr_batch::kGroups];
-    int nu = 0;
-    for (int g = 0; g < skyr_batch::kGroups; ++g)
-        if (b->grid[g]) used[nu++] = g;
-    const int nside = std::min(std::max(nu - 1, 0), skyr_batch::kSide);
-    const size_t per_slot = 1 + skyr_batch::kSide;  // one fork and up to kSide joins
-    for (int j = 0; j < nside; ++j)
+    const int nc = b->nchains;
+    const int nside = std::min(std::max(nc - 1, 0), skyr_batch::kSide);
+    for (int j = 0; j < nside; ++j) {
         if (!b->side[j]) SKYR_HIP(hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking));
-    while (b->events.size() < (size_t)sweeps * per_slot) {
-        hipEvent_t ev = nullptr;
-        SKYR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        b->events.push_back(ev);
+        if (!b->events[1 + j]) SKYR_HIP(hipEventCreateWithFlags(&b->events[1 + j], hipEventDisableTiming));
     }
+    if (nside > 0 && !b->events[0]) SKYR_HIP(hipEventCreateWithFlags(&b->events[0], hipEventDisableTiming));
+    auto stream_of = [&](int c) { return c % (nside + 1) == 0 ? b->capture : b->side[c % (nside + 1) - 1]; };
     SKYR_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
+    if (nside > 0) e = hipEventRecord(b->events[0], b->capture);
+    for (int j = 0; j < nside && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->events[0], 0);
     for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
-        hipEvent_t* ev = &b->events[(size_t)k * per_slot];
-        if (nside > 0) e = hipEventRecord(ev[0], b->capture);
-        for (int i = 0; i < nu && e == hipSuccess; ++i) {
-            const int g = used[i];
-            hipStream_t s = b->capture;
-            if (i > 0) {
-                s = b->side[(i - 1) % nside];
-                if (i <= nside) e = hipStreamWaitEvent(s, ev[0], 0);
-                if (e != hipSuccess) break;
-            }
+        for (int c = 0; c < nc && e == hipSuccess; ++c) {
+            const int g = b->chain_group[c];
+            const hipStream_t s = stream_of(c);
             const bool f64 = g < shape_count(SKYR_F64);
-            e = batch_sweep(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[g], b->grid[g],
-                            b->d_args, b->d_map[g], b->d_first, b->d_count, s);
-        }
-        for (int j = 0; j < nside && e == hipSuccess; ++j) {
-            e = hipEventRecord(ev[1 + j], b->side[j]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(b->capture, ev[1 + j], 0);
-        }
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->max_jobs), dim3(256), 0, b->capture, b->d_args,
-                               b->max_jobs);
+            e = batch_sweep(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[c], b->grid[c],
+                            b->d_args, b->d_map[c], b->d_first, b->d_count, s);
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->nlist[c]), dim3(256), 0, s, b->d_args, b->d_list[c],
+                               b->nlist[c]);
             e = hipGetLastError();
         }
+    }
+    // join every side stream back, also after an error, so that the capture can end
+    for (int j = 0; j < nside; ++j) {
+        hipError_t ej = hipEventRecord(b->events[1 + j], b->side[j]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(b->capture, b->events[1 + j], 0);
+        if (e == hipSuccess) e = ej;
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->capture, &g);
@@ -1446,7 +1487,7 @@ skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
         if (rc != SKYR_OK) return rc;
     }
     int blocks = 0;
-    for (int g = 0; g < skyr_batch::kGroups; ++g) blocks += b->grid[g];
+    for (int c = 0; c < b->nchains; ++c) blocks += b->grid[c];
     if (blocks > 0) {
         if (!b->exec || b->graph_sweeps != sweeps) {
             skyr_status rc = batch_capture(b, sweeps);
@@ -1537,11 +1578,13 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
     (void)hipFree(b->d_args);
     (void)hipFree(b->d_first);
     (void)hipFree(b->d_count);
-    for (int g = 0; g < skyr_batch::kGroups; ++g) (void)hipFree(b->d_map[g]);
+    for (int c = 0; c < skyr_batch::kChains; ++c) (void)hipFree(b->d_map[c]);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int c = 0; c < skyr_batch::kChains; ++c) (void)hipFree(b->d_list[c]);
     for (hipStream_t s : b->side)
         if (s) (void)hipStreamDestroy(s);
-    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : b->events)
+        if (ev) (void)hipEventDestroy(ev);
     delete b;
     return SKYR_OK;
 }
