@@ -268,7 +268,7 @@ def batch_throughput(skyr, torch, jobs, sweeps=64):
 SERVE_STEPS_EST = 9000
 
 
-def served_stream(skyr, torch, count=24, cap=20000, rate=None, throughput=None):
+def served_stream(skyr, torch, count=24, cap=20000, rate=None, throughput=None, sweeps_per_tick=32):
     """The served workload (Poisson arrivals, jobs of mixed size and precision).
     The arrival rate is 1.2 x the estimated service capacity: batched
     site-updates/s over the mean work of a request (SERVE_STEPS_EST steps of
@@ -287,7 +287,7 @@ def served_stream(skyr, torch, count=24, cap=20000, rate=None, throughput=None):
         reqs.append(Request(d, arrival=d["arrival"], rid=i))
     free, total = torch.cuda.mem_get_info()
     be = GpuBackend(max_jobs=32)
-    srv = Server(be, max_jobs=32, hbm_budget=int(0.8 * free), sweeps_per_tick=32)
+    srv = Server(be, max_jobs=32, hbm_budget=int(0.8 * free), sweeps_per_tick=sweeps_per_tick)
     rep = srv.serve(reqs)
     be.close()
     rep.update({"rate_per_s": rate, "capacity_est_jobs_per_s": capacity, "step_cap": cap,

@@ -105,15 +105,17 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
 
 // Slab length of a lattice the autotuner has not seen: shape 0, and the even
 // split of x into as many slabs (of at least kMinChunk planes, at most
-// kMaxSlabs) as keep the block count near one round of the chip (float: one
-// 1024-thread block per CU, 256 blocks) or three (double: 768); the autotuner's
-// choices at 256^3 (3 and 4 slabs) follow this rule.
+// kMaxSlabs) as keep the block count within about four rounds of the chip
+// (float: one 1024-thread block per CU, 1024 blocks; double: 3072).  The
+// default serves batches: there short blocks let the chains of a batch share the
+// CUs evenly, which a solo launch does not need (the autotuner's choice at
+// 256^3 is 3 slabs in float, 4 in double).
 static int default_chunk(const skyr_lattice* lat, skyr_precision prec)
 {
     const Launch L = plan_with(lat, prec, 0, kMinChunk);
     const int tiles = L.tiles_z * L.tiles_y;
     const int nx = lat->n[0] - 4;
-    const int target = prec == SKYR_F64 ? 768 : 256;
+    const int target = prec == SKYR_F64 ? 3072 : 1024;
     const int most = std::max(1, std::min(kMaxSlabs, nx / kMinChunk));
     const int slabs = std::max(1, std::min(most, target / std::max(1, tiles)));
     return std::max(kMinChunk, (nx + slabs - 1) / slabs);
