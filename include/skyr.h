@@ -319,13 +319,15 @@ SKYR_API skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, 
                                   const void* phi, skyr_moment_obs* out, void* work, void* stream);
 
 /* Batches: many independent flows (uneven lattices, charges, masses and
- * precisions) advanced together.  Per sweep slot, one persistent launch per
- * precision covers every active field's tiles, followed by one finaliser
- * launch (one block per field); skyr_batch_run replays a captured hipGraph of
- * `sweeps` slots.  Each field's blocks, partial sums and decisions are those
- * of the same field flowing alone (the batched sweep uses tile shape 0 of its
- * precision and the lattice's slab length), so a field's result does not
- * depend on the other fields in the batch.  A batch object owns only its job
+ * precisions) advanced together.  Fields of one precision and tile shape share
+ * a kernel and are split into one or two chains balanced by block count; per
+ * sweep slot a chain is one launch over its fields' tiles followed by a
+ * finaliser launch for those fields (one block per field).  Chains share no
+ * field: skyr_batch_run replays a captured hipGraph of `sweeps` slots that runs
+ * the chains on separate streams and joins them at its end.  Each field's
+ * blocks, partial sums and decisions are those of the same field flowing alone
+ * with its lattice's tile setting, so a field's result does not depend on the
+ * other fields in the batch.  A batch object owns only its job
  * table, control blocks and graph; field, velocity and workspace memory stay
  * with the caller and must stay valid while the field is in the batch.  A
  * batch is used by one thread at a time.
