@@ -358,10 +358,12 @@ SKYR_API skyr_status skyr_batch_destroy(skyr_batch* b);
  * slab.  The choice is kept per (lattice dimensions, precision) for the whole
  * process and applies to every later sweep on such a lattice; results are
  * deterministic for a given choice.  Default (a lattice never set or tuned):
- * shape 0 and the even split of x into the most slabs (of at least 16 planes,
- * at most 24) whose block count stays within 1024 (float) or 3072 (double)
- * blocks, a split made for batches; a lattice stepped on its own is usually
- * faster after skyr_autotune.  skyr_get_tile reports the setting in force, the
+ * the shape whose padded (y, z) tiling costs least (flux positions of all
+ * tiles, each priced by a per-shape factor measured at 256^3), and the even
+ * split of x into the most slabs (of at least 16 planes, at most 24) whose
+ * block count stays within 1024 (float) or 3072 (double) blocks, a split made
+ * for batches; a lattice stepped on its own is usually faster after
+ * skyr_autotune.  skyr_get_tile reports the setting in force, the
  * default included. */
 SKYR_API int32_t skyr_tile_variants(skyr_precision prec);
 SKYR_API skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant, int32_t info[3]);

@@ -103,16 +103,43 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
     return L;
 }
 
-// Slab length of a lattice the autotuner has not seen: shape 0, and the even
+// Relative cost of one flux position and plane for each compiled shape, in the
+// order of the shape lists: sweep time over (tiles x flux positions per tile)
+// at 256^3, where every shape's tiles fit the interior (252) exactly or nearly.
+static const double kShapeCostF64[] = {1.0, 1.19};
+static const double kShapeCostF32[] = {1.0, 1.27, 0.89};
+static_assert(sizeof(kShapeCostF64) / sizeof(double) == sizeof(kShapesF64) / sizeof(Shape), "one cost per shape");
+static_assert(sizeof(kShapeCostF32) / sizeof(double) == sizeof(kShapesF32) / sizeof(Shape), "one cost per shape");
+
+// Tile shape of a lattice the autotuner has not seen: the one with the least
+// cost of its padded (y, z) tiling (flux positions of all tiles, each priced by
+// its shape), the lowest shape on ties.
+static int default_variant(const skyr_lattice* lat, skyr_precision prec)
+{
+    int best_v = 0;
+    double best = INFINITY;
+    for (int v = 0; v < shape_count(prec); ++v) {
+        const Launch L = plan_with(lat, prec, v, kMinChunk);
+        const double positions = (double)L.tiles_z * L.tiles_y * L.shape.threads() * L.shape.ry;
+        const double c = positions * (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
+        if (c < best) {
+            best = c;
+            best_v = v;
+        }
+    }
+    return best_v;
+}
+
+// Slab length of a lattice the autotuner has not seen, for shape v: the even
 // split of x into as many slabs (of at least kMinChunk planes, at most
 // kMaxSlabs) as keep the block count within about four rounds of the chip
 // (float: one 1024-thread block per CU, 1024 blocks; double: 3072).  The
 // default serves batches: there short blocks let the chains of a batch share the
 // CUs evenly, which a solo launch does not need (the autotuner's choice at
 // 256^3 is 3 slabs in float, 4 in double).
-static int default_chunk(const skyr_lattice* lat, skyr_precision prec)
+static int default_chunk(const skyr_lattice* lat, skyr_precision prec, int v)
 {
-    const Launch L = plan_with(lat, prec, 0, kMinChunk);
+    const Launch L = plan_with(lat, prec, v, kMinChunk);
     const int tiles = L.tiles_z * L.tiles_y;
     const int nx = lat->n[0] - 4;
     const int target = prec == SKYR_F64 ? 3072 : 1024;
@@ -132,7 +159,10 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
             xc = it->second.second;
         }
     }
-    if (xc == 0) xc = default_chunk(lat, prec);
+    if (xc == 0) {
+        v = default_variant(lat, prec);
+        xc = default_chunk(lat, prec, v);
+    }
     return plan_with(lat, prec, v, xc);
 }
 
@@ -1163,7 +1193,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
         return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
     double best = INFINITY;
-    int bv = 0, bx = default_chunk(lat, prec);
+    int bv = 0, bx = default_chunk(lat, prec, 0);
     for (const Cand& cd : cands)
         if (cd.us < best) {
             best = cd.us;
