@@ -226,6 +226,11 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
     // double precision; in single precision the extra code path costs the register that
     // keeps the 1024-thread shape at four waves per SIMD.
     static constexpr bool kHaloFast = sizeof(T) == 8;
+    // Double precision runs two waves per SIMD: a wave that reaches one of the plane's LDS
+    // read phases (the phi stencil after the barrier, the flux divergence) is raised above
+    // waves that are computing, so that its reads are issued early (4.6% at 256^3; in single
+    // precision, with four waves per SIMD, the same hint costs 4%).
+    static constexpr bool kPrio = sizeof(T) == 8;
 
     struct Smem {
         T phi[2][4][PY + 4][LW + 4];  // phi of two planes, rows y0-4 .. y0+PY-1, columns z0-4 .. z0+LW-1
@@ -325,6 +330,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
         constexpr int S_M2 = 0, S_M1 = 1, S_0 = 2, S_P1 = 3, S_P2 = 4;
         const int qb = pb ^ 1;
 
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
         // commit the prefetched plane j+2 and the halo of plane j+1; prefetch j+3 and the halo of j+2
         T hcur[4];
 #pragma unroll
@@ -399,6 +405,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
                 }
             }
 
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
             const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
             const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
             const bool valid = yz_in[k] && j_in;
@@ -479,6 +486,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
         }
 
         // y- and z-divergence of the flux of plane j-1 (written before the last barrier)
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
         if (full && j - 1 >= xb && j - 1 < xe) {
 #pragma unroll
             for (int k = 0; k < RY; ++k) {
@@ -494,6 +502,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
             }
         }
 
+        if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         // output plane j-2 is complete
         if (full && j - 2 >= xb && j - 2 < xe) {
             const unsigned base = (unsigned)(j - 2) * plane_b;
