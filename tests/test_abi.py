@@ -196,3 +196,34 @@ def test_orientation_zyz_is_the_product_of_axis_rotations():
         D = np.array([[0.5 * np.trace(pauli[i] @ Bm @ pauli[j] @ Bm.conj().T).real for j in range(3)]
                       for i in range(3)])
         np.testing.assert_allclose(D, rz(a[0]) @ ry(a[1]) @ rz(a[2]), atol=1e-14)
+
+
+def _default_tile(n, prec):
+    """The default tile rule, restated: the compiled shape whose padded (y, z)
+    tiling costs least (flux positions of all tiles times a per-shape price, the
+    lowest shape on ties), then the even split of x into the most slabs of at
+    least 16 planes, at most 24, within 1024 (float) / 3072 (double) blocks."""
+    import math
+    shapes = {skyr.F64: [((8, 32, 1), 1.0), ((8, 16, 1), 1.19)],
+              skyr.F32_BULK: [((16, 32, 1), 1.0), ((8, 32, 2), 1.27), ((16, 64, 1), 0.89)]}[prec]
+    i = n - 4
+    best = None
+    for v, ((nw, lw, ry), price) in enumerate(shapes):
+        oy, oz = (64 // lw) * nw * ry - 4, lw - 4
+        tiles = math.ceil(i / oy) * math.ceil(i / oz)
+        cost = tiles * (oy + 4) * (oz + 4) * price
+        if best is None or cost < best[0]:
+            best = (cost, v, tiles)
+    _, v, tiles = best
+    target = 3072 if prec == skyr.F64 else 1024
+    most = max(1, min(24, i // 16))
+    slabs = max(1, min(most, target // max(1, tiles)))
+    return v, max(16, math.ceil(i / slabs))
+
+
+@pytest.mark.parametrize("n", [9, 24, 48, 66, 100, 118, 176, 182, 256, 400])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_default_tile_choice(n, prec):
+    """skyr_get_tile on a lattice never set or tuned (host logic only)."""
+    lat = skyr.Lattice.cube(n, 0.1)
+    assert skyr.get_tile(lat, prec) == _default_tile(n, prec)
