@@ -333,6 +333,8 @@ def main():
                     help="time one precision only (profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served workloads")
     ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--served-only", action="store_true",
+                    help="run only the batched and served workloads and print the served record (profiling runs)")
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="print the sweep time of every compiled tile shape and x-chunk, then exit")
     ap.add_argument("--copy-probe", action="store_true",
@@ -364,6 +366,12 @@ def main():
     from skyr_inputs import RANDOM_B10_256 as W
 
     skyr.lib()
+    if args.served_only:
+        from skyr_inputs import batch_jobs
+        batch = batch_throughput(skyr, torch, batch_jobs(4, 64))
+        serve = served_stream(skyr, torch, count=args.serve_jobs, throughput=batch["batched_site_updates_per_s"])
+        print(json.dumps({"batched_64_jobs": batch, "served": serve}), flush=True)
+        return
     if args.sweep_tiles:
         for p in ([args.only] if args.only else ["f32", "f64"]):
             sweep_tiles(skyr, torch, W, p)
