@@ -267,7 +267,12 @@ SKYR_API void skyr_anf_state_init(skyr_anf_state* st);
  * flow->max_steps), convergence, or a non-finite value.
  *   phi      in/out; holds the result on return
  *   phi_alt  scratch field of the same size (its frozen layers are overwritten)
- *   vel      in/out velocity, same layout; zero at the start of a flow
+ *   vel      in/out velocity, same layout; zero at the start of a flow.  On
+ *            return it is v_k, the velocity belonging to the returned phi_k,
+ *            also after convergence: the sweep that finds max|F_k| < tol has
+ *            already kicked vel to v_k + dt F_k in place, and one more sweep
+ *            over phi_k writes (v_k + dt F_k) - dt F_k back (within one rounding
+ *            of v_k; exactly zero when v_k was reset by an arrest)
  *   st       in/out state (skyr_anf_state_init before the first call)
  * Returns SKYR_E_NONFINITE if the energy or force stops being finite (field
  * contents then unspecified).  Synchronises `stream`. */

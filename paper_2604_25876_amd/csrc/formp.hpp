@@ -66,8 +66,10 @@ __global__ __launch_bounds__(FP_THREADS, sizeof(T) == 4 ? 4 : 1) void formp_kern
     const Ctl* ctl = a.ctl;
     int cur = 0;
     bool redo = false, renorm64 = false;
+    int restore = RESTORE_NONE;
     if constexpr (MODE == MODE_STEP) {
-        if (ctl->done) return;  // uniform
+        restore = ctl->restore;
+        if (ctl->done && !restore) return;  // uniform
         cur = ctl->cur;
         redo = ctl->redo != 0;
         const int kr = ctl->renorm64_every;
@@ -255,7 +257,13 @@ __global__ __launch_bounds__(FP_THREADS, sizeof(T) == 4 ? 4 : 1) void formp_kern
                 pf2 = fmax_nonneg(pf2, dot4(f, f));
                 if constexpr (MODE == MODE_STEP) {
                     T v[4], qv[4];
-                    pp += (double)dot4(f, vc);
+                    pp += (double)f[0] * vc[0] + (double)f[1] * vc[1] + (double)f[2] * vc[2] + (double)f[3] * vc[3];
+                    if (restore) {
+#pragma unroll
+                        for (int A = 0; A < 4; ++A)
+                            vel[(size_t)A * N3 + s] = restore == RESTORE_ZERO ? T(0) : vc[A] - dt * f[A];
+                        continue;
+                    }
 #pragma unroll
                     for (int A = 0; A < 4; ++A) {
                         v[A] = grad_flow ? T(0) : vc[A] + dt * f[A];

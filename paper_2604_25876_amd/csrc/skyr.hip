@@ -383,7 +383,11 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
 // otherwise accept the update (swap buffers).
 __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
 {
-    if (ctl->done) return;  // uniform
+    if (ctl->done) {  // uniform
+        // the sweep just before this one restored v_k after convergence
+        if (threadIdx.x == 0 && ctl->restore) ctl->restore = RESTORE_NONE;
+        return;
+    }
     double s[NRED];
     reduce_partials(part, ctl->nblocks, s);
     if (threadIdx.x != 0) return;
@@ -408,6 +412,10 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
     if (r < ctl->tol) {
         ctl->done = 1;
         ctl->status = 1;
+        // the sweep wrote v_k + dt F_k over v_k; the next one puts v_k back (zero if v_k was
+        // reset by an arrest at this step or was zero on this redo sweep)
+        const bool v_zero = ctl->redo || arrest || ctl->flow_mode == SKYR_GRADIENT_FLOW;
+        ctl->restore = v_zero ? RESTORE_ZERO : RESTORE_UNKICK;
         ctl->redo = 0;
         return;
     }
@@ -964,9 +972,14 @@ skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, const sky
     return SKYR_OK;
 }
 
-skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
-                          const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
-                          int64_t nsteps, void* work, void* stream)
+}  // extern "C"
+
+namespace skyr {
+
+// argument checks of a flow call (before any device work)
+static skyr_status check_flow(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                              const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                              int64_t nsteps, void* work)
 {
     skyr_status rc = check_common(lat, prec, model, phi, work);
     if (rc != SKYR_OK) return rc;
@@ -976,7 +989,14 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     if (nsteps < 0 || flow->max_steps < 0 || flow->renorm64_every < 0) return fail(SKYR_E_INVAL, "negative step count");
     if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
     if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
-    hipStream_t s = (hipStream_t)stream;
+    return SKYR_OK;
+}
+
+// the flow itself, after the argument checks; timed: record sweep events (skyr_timing_enable)
+static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                           int64_t nsteps, void* work, hipStream_t s, bool timed)
+{
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
     if (st->converged || target <= st->steps) return SKYR_OK;
 
@@ -1025,23 +1045,28 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     const int64_t remaining = target - st->steps;
     int64_t group = std::min<int64_t>(std::max<int64_t>(remaining, 1), 32);
     int64_t budget = 2 * remaining + 2;  // every step takes at most one redo sweep
+    auto enqueue_sweep = [&](bool timed) -> hipError_t {
+        hipError_t e = timed ? timing_mark(s) : hipSuccess;
+        if (e == hipSuccess) e = printed ? sweep_printed(prec, MODE_STEP, lat, a, s) : sweep(prec, MODE_STEP, L, a, s);
+        if (e == hipSuccess && timed) e = timing_mark(s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
+        return hipGetLastError();
+    };
     for (;;) {
-        for (int64_t i = 0; i < group; ++i) {
-            SKYR_HIP(timing_mark(s));
-            if (printed)
-                SKYR_HIP(sweep_printed(prec, MODE_STEP, lat, a, s));
-            else
-                SKYR_HIP(sweep(prec, MODE_STEP, L, a, s));
-            SKYR_HIP(timing_mark(s));
-            hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
-            SKYR_HIP(hipGetLastError());
-        }
+        for (int64_t i = 0; i < group; ++i) SKYR_HIP(enqueue_sweep(timed));
         budget -= group;
         SKYR_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
         SKYR_HIP(hipStreamSynchronize(s));
-        SKYR_HIP(timing_collect());
+        if (timed) SKYR_HIP(timing_collect());
         if (h.done || budget <= 0) break;
         group = std::min<int64_t>(std::max<int64_t>(h.target - h.steps, 1), 32);
+    }
+    if (h.restore) {
+        // converged in the last sweep of a group: one more sweep puts v_k back
+        SKYR_HIP(enqueue_sweep(false));
+        SKYR_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
     }
     if (h.cur == 1) {
         SKYR_HIP(hipMemcpyAsync(phi, phi_alt, 4 * sites(lat) * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
@@ -1060,6 +1085,19 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     if (st->nonfinite) return fail(SKYR_E_NONFINITE, "energy or force is not finite");
     if (!h.done) return fail(SKYR_E_DEVICE, "flow did not reach its target within the sweep budget");
     return SKYR_OK;
+}
+
+}  // namespace skyr
+
+extern "C" {
+
+skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                          const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                          int64_t nsteps, void* work, void* stream)
+{
+    const skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work);
+    if (rc != SKYR_OK) return rc;
+    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true);
 }
 
 int32_t skyr_tile_variants(skyr_precision prec)
@@ -1547,10 +1585,20 @@ static void state_from_ctl(const Ctl& h, skyr_anf_state* st)
     st->_pad = 0;
 }
 
-// once a field has stopped, make sure its result sits in phi
+// once a field has stopped, make sure its result sits in phi and, after convergence in the
+// last sweep slot of a run, that its velocity is v_k again (a restore sweep of its own)
 static skyr_status batch_settle(skyr_batch* b, int j)
 {
     Ctl& h = b->ctl[j];
+    if (h.restore) {
+        const auto& J = b->jobs[j];
+        const SweepArgs& a = b->args[j];
+        SKYR_HIP(sweep(J.prec, MODE_STEP, J.L, a, b->stream));
+        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, b->stream, a.partials, a.ctl);
+        SKYR_HIP(hipGetLastError());
+        SKYR_HIP(hipMemcpyAsync(&h, a.ctl, sizeof h, hipMemcpyDeviceToHost, b->stream));
+        SKYR_HIP(hipStreamSynchronize(b->stream));
+    }
     if (h.cur == 1) {
         const auto& J = b->jobs[j];
         SKYR_HIP(hipMemcpyAsync(J.phi, J.phi_alt, 4 * sites(&J.lat) * elem_bytes(J.prec), hipMemcpyDeviceToDevice,

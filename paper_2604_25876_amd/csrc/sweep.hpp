@@ -45,7 +45,7 @@ struct Ctl {
     int32_t renorm64_every;
     int32_t nblocks;      // number of partial-sum blocks of the sweep
     int32_t flow_mode;    // skyr_flow_mode
-    int32_t pad_i;
+    int32_t restore;      // after convergence: the next sweep over phi_k rewrites v_k (RESTORE_*)
     double E_prev;
     double E;
     double P;             // power h^3 sum F_k . v_k of the last sweep (arrest rule POWER)
@@ -58,6 +58,12 @@ struct Ctl {
 static_assert(sizeof(Ctl) <= 256, "control block must fit its 256-byte slot");
 
 enum : int { MODE_STEP = 0, MODE_GRAD = 1 };
+
+// The converging sweep over phi_k has already written v_k + dt F_k over v_k.  The sweep
+// after it recomputes F_k from phi_k (the same arithmetic, so the same F_k) and writes
+// v_k back: v - dt F_k, or exactly zero when v_k was zero (an arrest at step k, a redo
+// sweep, or the gradient flow).  No field is written by that sweep.
+enum : int { RESTORE_NONE = 0, RESTORE_UNKICK = 1, RESTORE_ZERO = 2 };
 
 struct SweepArgs {
     const void* phi0;  // field buffer 0 (phi)
@@ -255,6 +261,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
     int zl, rg, z, hrow, hcol;
     unsigned hoff;  // byte offset of this thread's halo site within a plane
     bool halo_loader, redo, renorm64, projected, baryon, has_grad;
+    int restore;     // RESTORE_*: this sweep only rewrites the velocity
     bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
     int yk[RY];
     unsigned offk[RY];  // byte offsets of the flux positions within a plane
@@ -275,7 +282,7 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
     // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
     // flow step keeps the total energy density in pe2 and leaves the others at zero
     double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0, pe6 = 0.0;
-    T pp = T(0);  // power F . v of the incoming velocity (flow step; used by the power arrest rule)
+    double pp = 0.0;  // power F . v of the incoming velocity (flow step; used by the power arrest rule)
     T pf2 = T(0);
 
     __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
@@ -522,7 +529,14 @@ template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false,
                     pf2 = fmax_nonneg(pf2, dot4(f, f));
                     if constexpr (MODE == MODE_STEP) {
                         // power of the incoming velocity (zero on a redo sweep, where v = 0)
-                        pp += f[0] * vcur[0][k] + f[1] * vcur[1][k] + f[2] * vcur[2][k] + f[3] * vcur[3][k];
+                        pp += (double)f[0] * vcur[0][k] + (double)f[1] * vcur[1][k] + (double)f[2] * vcur[2][k] +
+                              (double)f[3] * vcur[3][k];
+                        if (restore) {
+#pragma unroll
+                            for (int A = 0; A < 4; ++A)
+                                stb(vel[A], base + offk[k], restore == RESTORE_ZERO ? T(0) : vcur[A][k] - dt * f[A]);
+                            continue;
+                        }
                         T v[4], q[4], pn[4];
 #pragma unroll
                         for (int A = 0; A < 4; ++A) {
@@ -601,8 +615,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     SW sw(smem);
     sw.redo = false;
     sw.renorm64 = false;
+    sw.restore = RESTORE_NONE;
     if constexpr (MODE == MODE_STEP) {
-        if (ctl->done) return;  // uniform: the flow has stopped
+        sw.restore = ctl->restore;
+        if (ctl->done && !sw.restore) return;  // uniform: the flow has stopped
         cur = ctl->cur;
         sw.redo = ctl->redo != 0;
         const int kr = ctl->renorm64_every;
@@ -752,7 +768,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[7] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, (double)sw.pp, sw.pe6};
+    double vals[7] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, sw.pp, sw.pe6};
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         double v = vals[i];

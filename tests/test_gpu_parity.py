@@ -294,6 +294,35 @@ def test_converged_energy_matches_oracle(skyr):
     assert got["B"] == pytest.approx(ro["B"], rel=1e-8)
 
 
+@pytest.mark.parametrize("rule", ["energy", "power"])
+def test_velocity_after_convergence_matches_oracle(skyr, rule):
+    """The velocity returned with a converged field is v_k of that field, as in
+    the oracle (the in-place kick of the sweep that found convergence is undone),
+    and its kinetic energy agrees; a flow then resumed with a tighter tolerance
+    follows the oracle's uninterrupted flow to the tighter tolerance."""
+    n, h, m, dt = 24, 0.25, 1.0, 0.03
+    tol1, tol2 = 3e-3, 2e-4
+    mode = skyr.flow_mode(rule)
+    lat, phi, alt, vel, work = _flow_pair(skyr, n, h, m, dt)
+    ref0 = phi.cpu().numpy()
+    st = skyr.anf_state()
+    skyr.anf_step(lat, 0, skyr.Model(m), skyr.Flow(dt, tol1, 10 ** 6, 0, mode), phi, alt, vel, st, 10 ** 6, work)
+    ref, rvel, rst, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, tol1, 10 ** 6, rule=rule)
+    assert st.converged == 1 and rst.converged == 1
+    assert st.steps == rst.steps and st.arrests == rst.arrests
+    assert np.abs(phi.cpu().numpy() - ref).max() < 1e-10
+    vscale = max(np.abs(rvel).max(), 1e-300)
+    assert np.abs(vel.cpu().numpy() - rvel).max() <= 1e-10 * vscale + 1e-300
+    assert skyr.kinetic_energy(lat, 0, vel, work) == pytest.approx(oracle.kinetic(rvel, h), rel=1e-9, abs=1e-300)
+    # resume with the tighter tolerance
+    st.converged = 0
+    skyr.anf_step(lat, 0, skyr.Model(m), skyr.Flow(dt, tol2, 10 ** 6, 0, mode), phi, alt, vel, st, 10 ** 6, work)
+    ref2, rvel2, rst2, _, _ = oracle.anf(ref0, np.zeros_like(ref0), h, m, dt, tol2, 10 ** 6, rule=rule)
+    print(f"{rule}: {rst.steps} steps to {tol1}, {rst2.steps} to {tol2}; arrests {st.arrests} / {rst2.arrests}")
+    assert st.converged == 1 and st.steps == rst2.steps and st.arrests == rst2.arrests
+    assert np.abs(phi.cpu().numpy() - ref2).max() < 1e-9
+
+
 def test_converged_f32_bulk_against_oracle(skyr):
     """FP32-bulk relaxation of the same hedgehog: converged energy within 1e-6
     of the FP64 oracle's converged energy, B within 1e-3; the FP64 energy of

@@ -766,6 +766,56 @@ def test_relaxed_unit_skyrmion_small():
     assert o["E"] == pytest.approx(rr.radial_minimum(m), rel=0.02)
 
 
+def test_virial_is_minus_the_scaling_derivative_of_the_energy():
+    """Sec. 5.6, eq. Virial: under x -> lambda x the same lattice values at
+    spacing h / lambda describe the compressed field, so the virial returned by
+    the observables must equal -dE_{h/lambda}/dlambda at lambda = 1.  The
+    derivative is taken numerically from the energy alone (central differences,
+    Richardson-extrapolated), with every term of the energy switched on: the
+    four potentials and the sextic term.  A wrong coefficient or sign on any of
+    E2, E4, E0, E6 in the virial fails this."""
+    shape, h = (14, 15, 16), 0.3
+    phi = oracle.init_product(shape, h, [oracle.hedgehog(X=(0.3, -0.2, 0.1), prof_lambda=0.9),
+                                         oracle.hedgehog(X=(-0.9, 0.6, -0.4), quat=(0.6, 0.0, 0.8, 0.0))])
+    masses = (1.1, 0.7, 0.9, 0.6, 0.35)  # m, m_y, m_z, m_w, c6
+
+    def E(lam):
+        return sum(oracle.energy_parts(phi, h / lam, masses))
+
+    def central(eps):
+        return (E(1.0 + eps) - E(1.0 - eps)) / (2.0 * eps)
+
+    eps = 1e-3
+    dE = (4.0 * central(eps / 2) - central(eps)) / 3.0
+    o = oracle.observables(phi, h, masses)
+    assert min(abs(o["E2"]), abs(o["E4"]), abs(o["E0"]), abs(o["E6"])) > 1e-2  # every part contributes
+    assert o["virial"] == pytest.approx(-dE, rel=1e-9)
+
+
+def test_relaxed_unit_skyrmion_virial_and_charge_fall_at_fourth_order():
+    """Relaxed B = 1 (m = 1) in the box [-4, 4]^3 at h = 0.2 and 0.15 (power
+    arrest rule, max|F| < 1e-4): the Derrick virial E2 - E4 + 3 E0 of the
+    converged field (Sec. 5.6) and the charge deficit 1 - B both fall with h at
+    about fourth order, and at h = 0.15 the virial is below 2% of E and B is
+    within 5e-3 of 1 (the fixed facts a converged solution must show; the slow
+    test takes them to h = 0.1)."""
+    m, L = 1.0, 4.0
+    res = {}
+    for h in (0.2, 0.15):
+        n = int(round(2 * L / h)) + 4
+        n += n % 2
+        phi = oracle.init_product((n, n, n), h, [oracle.hedgehog()])
+        out, vel, st, _, _ = oracle.anf(phi, np.zeros_like(phi), h, m, 0.1 * h, 1e-4, 8000, rule="power")
+        assert st.converged == 1
+        res[h] = oracle.observables(out, h, m)
+    for key, f in (("virial", lambda o: o["virial"] / o["E"]), ("B", lambda o: o["B"] - 1.0)):
+        e2, e15 = f(res[0.2]), f(res[0.15])
+        order = math.log(abs(e2 / e15)) / math.log(0.2 / 0.15)
+        assert 3.0 < order < 5.5, (key, e2, e15, order)
+    assert abs(res[0.15]["virial"]) < 0.02 * res[0.15]["E"]
+    assert abs(res[0.15]["B"] - 1.0) < 5e-3
+
+
 @pytest.mark.slow
 def test_relaxed_unit_skyrmion_converges_at_fourth_order():
     """Relaxed B = 1 (m = 1) at h = 0.2, 0.15, 0.1: the energy approaches the
