@@ -280,6 +280,26 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
                           int64_t nsteps, void* work, void* stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses
+ * that forbid hipMalloc / hipFree, callers without a workspace of their own):
+ * skyr_anf_step with the same arguments except `work`.  The control block and
+ * the per-block partial sums live in a fixed device array of
+ * SKYR_NOALLOC_SCRATCH_BYTES inside the library, one per device (its address
+ * is taken on the first call on a device, with that device current, and the
+ * array is held until the process ends).  The call allocates nothing and runs
+ * the same kernels as skyr_anf_step, so its results are the same bit for bit.
+ * A lattice whose flow needs more workspace than the array holds (the control
+ * block, 512 bytes of observables and 64 bytes per sweep block; about 16,000
+ * sweep blocks) gives SKYR_E_INVAL before any device work.  Every call on one
+ * device shares that device's array and leaves its last contents there (each
+ * call initialises what it reads): calls that overlap in time on one device,
+ * from any stream or thread, race and give undefined results.  Synchronises
+ * `stream`. */
+#define SKYR_NOALLOC_SCRATCH_BYTES (1u << 20)
+SKYR_API skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel,
+                                           skyr_anf_state* st, int64_t nsteps, void* stream);
+
 /* Energy parts, baryon number, virial and largest projected force of phi
  * (Sec. 2.1 eq. B0_components, Sec. 5.6 eq. Virial).  Synchronises `stream`. */
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,

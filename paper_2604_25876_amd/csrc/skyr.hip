@@ -992,6 +992,15 @@ static skyr_status check_flow(const skyr_lattice* lat, skyr_precision prec, cons
     return SKYR_OK;
 }
 
+// bytes of workspace one flow call uses: control block, observables and the partial
+// sums of the sweep it launches
+static size_t flow_work_bytes(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model)
+{
+    const int nb = model->form == SKYR_FORM_PRINTED ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64)
+                                                    : plan(lat, prec).blocks();
+    return CTL_BYTES + OBS_BYTES + (size_t)nb * NPART * sizeof(double);
+}
+
 // the flow itself, after the argument checks; timed: record sweep events (skyr_timing_enable)
 static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
@@ -1087,6 +1096,33 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     return SKYR_OK;
 }
 
+// ------------------------------------------------------ allocation-free flow
+// The workspace of skyr_anf_step_noalloc: a fixed device array.  Every device holds
+// its own copy at its own address (taken once per device with hipGetSymbolAddress and
+// kept for the life of the process); host code uses only that address, never the
+// array's name, which on the host is a stand-in and not a device pointer.
+static __device__ __align__(256) unsigned char scratch[SKYR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch address on the current device
+static skyr_status scratch_on_current_device(void** out)
+{
+    int dev = -1;
+    SKYR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SKYR_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(SKYR_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SKYR_OK;
+}
+
 }  // namespace skyr
 
 extern "C" {
@@ -1098,6 +1134,25 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     const skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work);
     if (rc != SKYR_OK) return rc;
     return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true);
+}
+
+skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                  const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                                  int64_t nsteps, void* stream)
+{
+    // the checks need a non-null, aligned workspace; the scratch address is known only
+    // after the lattice has been checked, so a stand-in value is checked first
+    void* const stand_in = (void*)(uintptr_t)256;
+    skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, stand_in);
+    if (rc != SKYR_OK) return rc;
+    const size_t need = flow_work_bytes(lat, prec, model);
+    if (need > SKYR_NOALLOC_SCRATCH_BYTES)
+        return fail(SKYR_E_INVAL, "this lattice needs " + std::to_string(need) + " bytes of workspace; the fixed scratch holds " +
+                                      std::to_string((size_t)SKYR_NOALLOC_SCRATCH_BYTES));
+    void* work = nullptr;
+    rc = scratch_on_current_device(&work);
+    if (rc != SKYR_OK) return rc;
+    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, false);
 }
 
 int32_t skyr_tile_variants(skyr_precision prec)

@@ -126,6 +126,9 @@ _SIGNATURES = {
     "skyr_anf_step": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState), ctypes.c_int64, _P,
                                      _P]),
+    "skyr_anf_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                             ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState),
+                                             ctypes.c_int64, _P]),
     "skyr_write_field_host": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(Lattice),
                                              ctypes.POINTER(Model), _P]),
     "skyr_read_field_host": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(Lattice), ctypes.POINTER(Model), _P]),
@@ -320,6 +323,18 @@ def anf_step(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, ve
     _check(lib().skyr_anf_step(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
                                ctypes.byref(state), int(nsteps), _work_ptr(work, lat, prec), _stream(stream)))
+    return state
+
+
+def anf_step_noalloc(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, state: AnfState,
+                     nsteps: int, stream=None) -> AnfState:
+    """skyr_anf_step_noalloc: the flow with the library's fixed device scratch as
+    its workspace (nothing is allocated)."""
+    shape = (4,) + lat.shape
+    dt = field_dtype(prec)
+    _check(lib().skyr_anf_step_noalloc(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
+                                       _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
+                                       _dev_ptr(vel, dt, shape), ctypes.byref(state), int(nsteps), _stream(stream)))
     return state
 
 

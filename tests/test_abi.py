@@ -118,6 +118,29 @@ def test_invalid_arguments_rejected_without_device_work():
     assert L.skyr_init_field(ctypes.byref(lat), 0, ctypes.byref(spec), fake, None) == skyr.E_INVAL
 
 
+def test_noalloc_flow_rejects_a_lattice_beyond_its_scratch():
+    """skyr_anf_step_noalloc refuses, before any device work, a lattice whose
+    sweep has more blocks than its fixed scratch holds partial sums for (here
+    800^3 in double with 16-plane slabs: about 97,000 blocks), and checks its
+    other arguments like skyr_anf_step."""
+    L = skyr.lib()
+    lat = skyr.Lattice.cube(800, 0.1)
+    skyr.set_tile(lat, skyr.F64, 0, 16)
+    st = skyr.anf_state()
+    model, flow = skyr.Model(1.0), skyr.Flow(0.01, 0.0, 10, 0, 0)
+    a, b, c = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    rc = L.skyr_anf_step_noalloc(ctypes.byref(lat), skyr.F64, ctypes.byref(model), ctypes.byref(flow), a, b, c,
+                                 ctypes.byref(st), 1, None)
+    assert rc == skyr.E_INVAL and "scratch" in L.skyr_last_error().decode()
+    small = skyr.Lattice.cube(40, 0.2)
+    bad_flow = skyr.Flow(0.0, 0.0, 10, 0, 0)
+    assert L.skyr_anf_step_noalloc(ctypes.byref(small), skyr.F64, ctypes.byref(model), ctypes.byref(bad_flow), a, b,
+                                   c, ctypes.byref(st), 1, None) == skyr.E_INVAL
+    assert L.skyr_anf_step_noalloc(ctypes.byref(small), skyr.F64, ctypes.byref(model), ctypes.byref(flow), a, a, c,
+                                   ctypes.byref(st), 1, None) == skyr.E_INVAL
+    assert st.steps == 0 and st.sweeps == 0
+
+
 class _FakeDeviceBuffer:
     """Stands in for a device tensor on the host: only what the binding's
     workspace check reads."""
