@@ -40,29 +40,34 @@ static skyr_status fail(skyr_status s, const std::string& msg)
     } while (0)
 
 // ------------------------------------------------------------ tile choice
-// A tile shape is (waves per block, lanes per row, flux rows per thread); a
-// few shapes are compiled per precision.  x is cut into slabs of `xchunk`
-// planes and one block marches one (y, z) tile of one slab.  The choice for a
-// (lattice, precision) pair is a process-wide setting (skyr_set_tile /
-// skyr_autotune); the default is shape 0 with 128-plane slabs.
+// A tile shape is (interior waves, halo waves, halo positions per halo lane,
+// output columns); a tile has interior waves x 64 / columns rows.  A few shapes
+// are compiled per precision.  A field's work, one unit per (tile, plane),
+// is ordered slab by slab (slabs of `xchunk` planes along x) and split evenly
+// over the launch's blocks, one round of the chip for large lattices.  The
+// choice for a (lattice, precision) pair is a process-wide setting
+// (skyr_set_tile / skyr_autotune).
 struct Shape {
-    int nw, lw, ry;
-    int threads() const { return nw * 64; }
-    int oy() const { return (64 / lw) * nw * ry - 4; }
-    int oz() const { return lw - 4; }
+    int nwi, nwh, hpt, cols;
+    int per_cu;  // blocks resident on one CU (LDS and registers)
+    int threads() const { return (nwi + nwh) * 64; }
+    int oy() const { return nwi * 64 / cols; }
+    int oz() const { return cols; }
 };
 
 #ifndef SKYR_SHAPES_F64
-#define SKYR_SHAPES_F64(X) X(8, 32, 1) X(8, 16, 1)
+#define SKYR_SHAPES_F64(X) X(6, 2, 2, 32, 1) X(6, 2, 2, 16, 1)
 #endif
 #ifndef SKYR_SHAPES_F32
-#define SKYR_SHAPES_F32(X) X(16, 32, 1) X(8, 32, 2) X(16, 64, 1)
+#define SKYR_SHAPES_F32(X) X(12, 4, 1, 32, 1) X(14, 2, 2, 32, 1) X(6, 2, 2, 32, 2)
 #endif
-#define SKYR_SHAPE_ENTRY(a, b, c) Shape{a, b, c},
+#define SKYR_SHAPE_ENTRY(a, b, c, d, e) Shape{a, b, c, d, e},
 static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
 static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
-constexpr int kMinChunk = 16;  // shortest slab (planes)
-constexpr int kMaxSlabs = 24;  // the autotuner splits x into 1 .. kMaxSlabs equal slabs
+constexpr int kMinChunk = 16;   // shortest slab a tile setting may name (planes)
+constexpr int kMaxSlabs = 8;    // the autotuner tries 1 .. kMaxSlabs slabs
+constexpr int kCUs = 256;       // compute units of the device the launches are sized for
+constexpr int kMinPlanes = 32;  // planes of work per block at least, where the lattice allows
 
 static int shape_count(skyr_precision prec)
 {
@@ -75,8 +80,9 @@ struct Launch {
     int variant;
     Shape shape;
     int xchunk;  // planes per slab
-    int tiles_z, tiles_y, slabs;
-    int blocks() const { return tiles_z * tiles_y * slabs; }
+    int tiles_z, tiles_y, zstart, slabs;
+    int nblocks;
+    int blocks() const { return nblocks; }
     int threads() const { return shape.threads(); }
 };
 
@@ -90,38 +96,58 @@ struct TileKey {
 static std::mutex g_tile_mu;
 static std::map<TileKey, std::pair<int, int>> g_tiles;  // (variant, planes per slab)
 
+// Tiles of the (y, z) plane: rows from y = 2; columns from z = 0 (so that tile rows
+// start on 128-byte lines) unless starting at z = 2 saves a tile.
+static void tile_grid(const skyr_lattice* lat, const Shape& sh, int& tiles_y, int& tiles_z, int& zstart)
+{
+    const int iy = lat->n[1] - 4, n2 = lat->n[2];
+    tiles_y = (iy + sh.oy() - 1) / sh.oy();
+    const int aligned = (n2 - 3) / sh.oz() + 1;
+    const int inner = (n2 - 4 + sh.oz() - 1) / sh.oz();
+    zstart = aligned <= inner ? 0 : 2;
+    tiles_z = aligned <= inner ? aligned : inner;
+}
+
+// blocks of a launch: one round of the chip, fewer when that would leave a block less
+// than kMinPlanes planes of work
+static int plan_blocks(long long units, const Shape& sh)
+{
+    const long long round = (long long)kCUs * sh.per_cu;
+    return (int)std::max<long long>(1, std::min(round, units / kMinPlanes));
+}
+
 static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int variant, int xchunk)
 {
     Launch L{};
     L.variant = variant;
     L.shape = shape_of(prec, variant);
     L.xchunk = xchunk;
-    const int ix = lat->n[0] - 4, iy = lat->n[1] - 4, iz = lat->n[2] - 4;
-    L.tiles_z = (iz + L.shape.oz() - 1) / L.shape.oz();
-    L.tiles_y = (iy + L.shape.oy() - 1) / L.shape.oy();
-    L.slabs = (ix + xchunk - 1) / xchunk;
+    tile_grid(lat, L.shape, L.tiles_y, L.tiles_z, L.zstart);
+    const int nx = lat->n[0] - 4;
+    L.slabs = (nx + xchunk - 1) / xchunk;
+    L.nblocks = plan_blocks((long long)L.tiles_y * L.tiles_z * nx, L.shape);
     return L;
 }
 
-// Relative cost of one flux position and plane for each compiled shape, in the
-// order of the shape lists: sweep time over (tiles x flux positions per tile)
-// at 256^3, where every shape's tiles fit the interior (252) exactly or nearly.
-static const double kShapeCostF64[] = {1.0, 1.19};
-static const double kShapeCostF32[] = {1.0, 1.27, 0.89};
+// Relative cost of one output site of a tile for each compiled shape, in the order of
+// the shape lists (sweep time per tile site at 256^3).
+static const double kShapeCostF64[] = {1.0, 1.0};
+static const double kShapeCostF32[] = {1.0, 1.07, 1.08};
 static_assert(sizeof(kShapeCostF64) / sizeof(double) == sizeof(kShapesF64) / sizeof(Shape), "one cost per shape");
 static_assert(sizeof(kShapeCostF32) / sizeof(double) == sizeof(kShapesF32) / sizeof(Shape), "one cost per shape");
 
-// Tile shape of a lattice the autotuner has not seen: the one with the least
-// cost of its padded (y, z) tiling (flux positions of all tiles, each priced by
-// its shape), the lowest shape on ties.
+// Tile shape of a lattice the autotuner has not seen: the one with the least cost of
+// its padded (y, z) tiling (the sites of all tiles, each priced by its shape), the
+// lowest shape on ties.
 static int default_variant(const skyr_lattice* lat, skyr_precision prec)
 {
     int best_v = 0;
     double best = INFINITY;
     for (int v = 0; v < shape_count(prec); ++v) {
-        const Launch L = plan_with(lat, prec, v, kMinChunk);
-        const double positions = (double)L.tiles_z * L.tiles_y * L.shape.threads() * L.shape.ry;
-        const double c = positions * (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
+        const Shape& sh = shape_of(prec, v);
+        int ty = 0, tz = 0, zs = 0;
+        tile_grid(lat, sh, ty, tz, zs);
+        const double c = (double)ty * tz * sh.oy() * sh.oz() * (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
         if (c < best) {
             best = c;
             best_v = v;
@@ -130,21 +156,19 @@ static int default_variant(const skyr_lattice* lat, skyr_precision prec)
     return best_v;
 }
 
-// Slab length of a lattice the autotuner has not seen, for shape v: the even
-// split of x into as many slabs (of at least kMinChunk planes, at most
-// kMaxSlabs) as keep the block count within about four rounds of the chip
-// (float: one 1024-thread block per CU, 1024 blocks; double: 3072).  The
-// default serves batches: there short blocks let the chains of a batch share the
-// CUs evenly, which a solo launch does not need (the autotuner's choice at
-// 256^3 is 3 slabs in float, 4 in double).
+// Slab length of a lattice the autotuner has not seen, for shape v: the even split
+// of x into about as many slabs as there are blocks per tile, so that a block's
+// work mostly stays within one tile of one slab (neighbouring blocks then march
+// through the same planes of neighbouring tiles).
 static int default_chunk(const skyr_lattice* lat, skyr_precision prec, int v)
 {
-    const Launch L = plan_with(lat, prec, v, kMinChunk);
-    const int tiles = L.tiles_z * L.tiles_y;
+    const Shape& sh = shape_of(prec, v);
+    int ty = 0, tz = 0, zs = 0;
+    tile_grid(lat, sh, ty, tz, zs);
     const int nx = lat->n[0] - 4;
-    const int target = prec == SKYR_F64 ? 3072 : 1024;
-    const int most = std::max(1, std::min(kMaxSlabs, nx / kMinChunk));
-    const int slabs = std::max(1, std::min(most, target / std::max(1, tiles)));
+    const int nb = plan_blocks((long long)ty * tz * nx, sh);
+    const int most = std::max(1, nx / kMinChunk);
+    const int slabs = std::max(1, std::min(most, (nb + ty * tz / 2) / std::max(1, ty * tz)));
     return std::max(kMinChunk, (nx + slabs - 1) / slabs);
 }
 
@@ -455,25 +479,25 @@ static int ext_level(const SweepArgs& a)
     return (a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0 || a.gradient_flow != 0) ? EXT_POT : EXT_NONE;
 }
 
-template <typename T, int NW, int LW, int RY, int MODE>
+template <typename T, class G, int MODE>
 static void launch_level(int ext, dim3 grid, dim3 block, const SweepArgs& args, hipStream_t s)
 {
     if (ext == EXT_SEXTIC)
-        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_SEXTIC>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((sweep_kernel<T, G, MODE, EXT_SEXTIC>), grid, block, 0, s, args);
     else if (ext == EXT_POT)
-        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_POT>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((sweep_kernel<T, G, MODE, EXT_POT>), grid, block, 0, s, args);
     else
-        hipLaunchKernelGGL((sweep_kernel<T, NW, LW, RY, MODE, EXT_NONE>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((sweep_kernel<T, G, MODE, EXT_NONE>), grid, block, 0, s, args);
 }
 
-template <typename T, int NW, int LW, int RY>
+template <typename T, class G>
 static hipError_t launch_shape(int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
 {
-    const dim3 grid(L.blocks()), block(NW * 64);
+    const dim3 grid(L.blocks()), block(G::THREADS);
     if (mode == MODE_STEP)
-        launch_level<T, NW, LW, RY, MODE_STEP>(ext_level(args), grid, block, args, s);
+        launch_level<T, G, MODE_STEP>(ext_level(args), grid, block, args, s);
     else
-        launch_level<T, NW, LW, RY, MODE_GRAD>(ext_level(args), grid, block, args, s);
+        launch_level<T, G, MODE_GRAD>(ext_level(args), grid, block, args, s);
     return hipGetLastError();
 }
 
@@ -481,14 +505,14 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_CASE64(a, b, c)                                                                                \
-    if (L.variant == v) return launch_shape<double, a, b, c>(mode, L, args, s);                              \
+#define SKYR_CASE64(a, b, c, d, e)                                                                          \
+    if (L.variant == v) return launch_shape<double, Geo<a, b, c, d>>(mode, L, args, s);                      \
     ++v;
         SKYR_SHAPES_F64(SKYR_CASE64)
 #undef SKYR_CASE64
     } else {
-#define SKYR_CASE32(a, b, c)                                                                                \
-    if (L.variant == v) return launch_shape<float, a, b, c>(mode, L, args, s);                               \
+#define SKYR_CASE32(a, b, c, d, e)                                                                          \
+    if (L.variant == v) return launch_shape<float, Geo<a, b, c, d>>(mode, L, args, s);                       \
     ++v;
         SKYR_SHAPES_F32(SKYR_CASE32)
 #undef SKYR_CASE32
@@ -526,20 +550,20 @@ static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattic
     return hipGetLastError();
 }
 
-// The batched sweep uses the first compiled shape of each precision.
-template <typename T, int NW, int LW, int RY>
+// The batched sweep of one (precision, tile shape) group.
+template <typename T, class G>
 static hipError_t launch_batch(int ext, int blocks, const SweepArgs* jobs, const int* map, const int* first,
                                const int* count, hipStream_t s)
 {
     if (ext == EXT_SEXTIC)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_SEXTIC>), dim3(blocks), dim3(NW * 64), 0, s, jobs,
-                           map, first, count);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_SEXTIC>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
+                           first, count);
     else if (ext == EXT_POT)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_POT>), dim3(blocks), dim3(NW * 64), 0, s, jobs, map,
+        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_POT>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
                            first, count);
     else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, NW, LW, RY, EXT_NONE>), dim3(blocks), dim3(NW * 64), 0, s, jobs,
-                           map, first, count);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_NONE>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
+                           first, count);
     return hipGetLastError();
 }
 
@@ -549,14 +573,14 @@ static hipError_t batch_sweep(skyr_precision prec, int variant, int ext, int blo
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_B64(a, b, c)                                                                                    \
-    if (variant == v) return launch_batch<double, a, b, c>(ext, blocks, jobs, map, first, count, s);          \
+#define SKYR_B64(a, b, c, d, e)                                                                             \
+    if (variant == v) return launch_batch<double, Geo<a, b, c, d>>(ext, blocks, jobs, map, first, count, s);  \
     ++v;
         SKYR_SHAPES_F64(SKYR_B64)
 #undef SKYR_B64
     } else {
-#define SKYR_B32(a, b, c)                                                                                    \
-    if (variant == v) return launch_batch<float, a, b, c>(ext, blocks, jobs, map, first, count, s);           \
+#define SKYR_B32(a, b, c, d, e)                                                                             \
+    if (variant == v) return launch_batch<float, Geo<a, b, c, d>>(ext, blocks, jobs, map, first, count, s);   \
     ++v;
         SKYR_SHAPES_F32(SKYR_B32)
 #undef SKYR_B32
@@ -572,6 +596,7 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_
     a.n2 = lat->n[2];
     a.tiles_z = L.tiles_z;
     a.tiles_y = L.tiles_y;
+    a.zstart = L.zstart;
     a.xchunk = L.xchunk;
     a.h = lat->h;
     a.m = model->m;
@@ -1166,9 +1191,9 @@ skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant, int32_t
     if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return fail(SKYR_E_INVAL, "unknown precision");
     if (!info || variant < 0 || variant >= shape_count(prec)) return fail(SKYR_E_INVAL, "no such tile variant");
     const Shape& sh = shape_of(prec, variant);
-    info[0] = sh.nw;
-    info[1] = sh.lw;
-    info[2] = sh.ry;
+    info[0] = sh.threads();
+    info[1] = sh.oy();
+    info[2] = sh.oz();
     return SKYR_OK;
 }
 

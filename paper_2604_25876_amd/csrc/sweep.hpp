@@ -6,18 +6,33 @@
 // and either the kick-drift-renormalise update (Sec. 3) or a gradient output,
 // plus FP64 per-block partial sums of E2, E4, E0, B and the largest |F|^2.
 //
-// Work decomposition (2.5D march):
-//   * a thread block owns an output tile of (PY-4) rows (y) x (LW-4) columns (z)
-//     and a chunk of planes [xb, xe) along x, and marches through x;
-//   * every thread owns RY "flux positions" (rows r_k, column zl); the flux
-//     region is PY x LW and overlaps neighbouring tiles by two rows/columns;
-//   * x-neighbours live in registers: a ring of five phi planes per position
-//     and a ring of five gradient accumulators (planes j-2..j+2);
-//   * y- and z-neighbours go through LDS: one phi plane with a two-site halo on
-//     all four sides, and one plane each of the y- and z-flux;
-//   * the x-flux of plane j is pushed into the accumulators of planes j+-1, j+-2;
-//     output plane j-2 is complete after plane j and is written at once.
-// Energy, charge and force sums are accumulated in double.
+// The gradient is -Lap phi (with boundary terms) - sum_i D_i Q_i + V'(phi0) e0, where
+// Q_i = S a_i - sum_j G_ij a_j is the flux of the quartic term at the sites of I (zero
+// elsewhere).  Two stencil passes: the flux needs phi within two sites, the divergence
+// needs the flux within two sites.
+//
+// Work decomposition (2.5D march along x):
+//   * a tile is OY rows (y) x OZ columns (z) of output sites; tiles in z start on a
+//     128-byte line when that costs no extra tile;
+//   * the block's waves have two roles.  Interior waves hold one output site per lane
+//     and do everything there: the derivatives, the Laplacian, the three fluxes, the
+//     x-divergence by pushes into a register ring of five gradient accumulators, the
+//     y/z-divergence from LDS and the update.  Halo waves hold the flux positions
+//     around the tile (two rows above and below, two columns left and right), where
+//     only one flux component is ever read (Q_y on the y-halo, Q_z on the z-halo), and
+//     compute just that one;
+//   * x-neighbours live in per-lane register rings of five phi planes; the march is
+//     unrolled five planes deep so that every ring slot is a fixed register;
+//   * y- and z-neighbours go through LDS: phi planes (with the frame of sites only the halo
+//     positions read, loaded by the halo lanes) and planes of Q_y and Q_z, each
+//     double-buffered by plane parity, so one block barrier per plane suffices;
+//   * a launch's blocks share the (tile, plane) work of a field evenly: the work is
+//     ordered slab by slab, tile by tile, plane by plane, and every block takes one
+//     contiguous run of it (one or two marches).
+// Stencils are evaluated in the scaled form 8 (f[+1] - f[-1]) - (f[+2] - f[-2]) =
+// 12 h D f (and 16 (...) - (...) = 12 h^2 L f); the constant factors are folded into
+// the weights of the final sums.  Energy, charge and force sums are accumulated in
+// double.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,7 +89,8 @@ struct SweepArgs {
     Ctl* ctl;          // MODE_STEP: control block
     int n0, n1, n2;
     int tiles_z, tiles_y;  // output tiles of the (y, z) plane
-    int xchunk;            // planes per slab
+    int zstart;            // z of the first tile's first column (0: line-aligned tiles; 2: the first interior column)
+    int xchunk;            // planes per slab (the work order's outer unit)
     int projected;     // MODE_GRAD: write g - (g.phi) phi instead of g
     int baryon;        // accumulate the baryon density
     double h, dt;
@@ -205,431 +221,706 @@ __device__ __forceinline__ T det4_cofactors(const T* c0, const T* c1, const T* c
     return m01 * n23 - m02 * n13 + m03 * n12 + m12 * n03 - m13 * n02 + m23 * n01;
 }
 
-template <typename T, int NW, int LW, int RY> struct Tile {
-    static constexpr int RPW = 64 / LW;     // rows per wave
-    static constexpr int R0 = NW * RPW;     // rows per row group
-    static constexpr int PY = R0 * RY;      // flux rows per tile
-    static constexpr int OY = PY - 4;       // output rows per tile
-    static constexpr int OZ = LW - 4;       // output columns per tile
+// fused multiply-add in the field type
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Tile geometry of a shape: NWI interior waves of 64 / OZ rows of OZ lanes, NWH halo
+// waves whose lanes hold HPT halo positions each.
+template <int NWI_, int NWH_, int HPT_, int OZ_> struct Geo {
+    static constexpr int NWI = NWI_, NWH = NWH_, HPT = HPT_, OZ = OZ_;
+    static constexpr int NW = NWI + NWH;
     static constexpr int THREADS = NW * 64;
-    // phi halo of a plane: rows 0, 1, PY+2, PY+3 over all LW+4 columns, then
-    // columns 0, 1, LW+2, LW+3 of rows 2 .. PY+1; one site per loading thread
-    static constexpr int NH_ROWS = 4 * (LW + 4);
-    static constexpr int NH = NH_ROWS + 4 * PY;
-    static_assert(THREADS >= NH, "every halo site of a plane has its own loading thread");
+    static constexpr int RPW = 64 / OZ;
+    static constexpr int OY = NWI * RPW;
+    // halo positions: rows -2, -1, OY, OY+1 over the OZ columns (they supply Q_y), then
+    // columns -2, -1, OZ, OZ+1 of the OY rows (they supply Q_z)
+    static constexpr int NHALO = 4 * OZ + 4 * OY;
+    // frame: the phi sites only halo positions read (rows -4, -3, OY+2, OY+3 over the
+    // columns; columns -4, -3, OZ+2, OZ+3 over the rows; the sixteen corner sites of the
+    // halo rows and columns)
+    static constexpr int NFRAME = 4 * OZ + 4 * OY + 16;
+    static constexpr int PW = OZ + 8, PH = OY + 8;  // phi plane: rows -4 .. OY+3, columns -4 .. OZ+3
+    static constexpr int QW = OZ + 4, QH = OY + 4;  // flux plane: rows -2 .. OY+1, columns -2 .. OZ+1
+    static constexpr int PPLANE = PH * PW, QPLANE = QH * QW;
+    static_assert(64 % OZ == 0, "an interior wave covers whole rows");
+    static constexpr int FPT = (NFRAME + NWH * 64 - 1) / (NWH * 64);  // frame sites per halo lane
+    static_assert(NWH * 64 * HPT >= NHALO, "every halo position has a lane");
+};
+
+template <typename T, class G> struct SweepSmem {
+    T phi[2][4][G::PPLANE];     // [plane parity][component]
+    T q[2][2][4][G::QPLANE];    // [plane parity][0: Q_y, 1: Q_z][component]
+    double red[G::NW][NPART];
 };
 
 // EXT: 0 the plain variant (pion-mass potential, kick-drift update); 1 adds the extra
 // potentials (m_y, m_z, m_w) and the gradient flow; 2 also the sextic term.  The levels
 // are separate kernels so that each carries only the registers it needs.
 enum : int { EXT_NONE = 0, EXT_POT = 1, EXT_SEXTIC = 2 };
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE> struct Sweeper {
-    using TL = Tile<T, NW, LW, RY>;
-    static constexpr int PY = TL::PY;
-    static constexpr int R0 = TL::R0;
-    using C = Coef<T>;
-    // Waves made only of y-halo flux rows take a short path (y-flux only).  Enabled in
-    // double precision; in single precision the extra code path costs the register that
-    // keeps the 1024-thread shape at four waves per SIMD.
-    static constexpr bool kHaloFast = sizeof(T) == 8;
-    // Double precision runs two waves per SIMD: a wave that reaches one of the plane's LDS
-    // read phases (the phi stencil after the barrier, the flux divergence) is raised above
-    // waves that are computing, so that its reads are issued early (4.6% at 256^3; in single
-    // precision, with four waves per SIMD, the same hint costs 4%).
-    static constexpr bool kPrio = sizeof(T) == 8;
 
-    struct Smem {
-        T phi[2][4][PY + 4][LW + 4];  // phi of two planes, rows y0-4 .. y0+PY-1, columns z0-4 .. z0+LW-1
-        // y- and z-flux of two planes, flux row r at [r + 2]: two unwritten rows above and below
-        // let the divergence read rows r-2 .. r+2 and (row-major, flat) columns c-2 .. c+2
-        // without clamping; the values read there only reach positions whose result is
-        // discarded.  The row stride stays LW, so the two rows of a wave fall on distinct banks.
-        T qy[2][4][PY + 4][LW];
-        T qz[2][4][PY + 4][LW];
-        double red[NW][NPART];
-    };
+// Per-launch constants.  With a^ = 12 h a (the scaled first difference), G^ = (12 h)^2 G,
+// Q^ = (12 h)^3 Q and L^ = 12 h^2 Lap, the scaled gradient g^ = K g, K = (12 h)^4, is
+//   g^ = lapw (L^ phi - boundary terms) - sum_i (8 (Q^_i[+1] - Q^_i[-1]) - (Q^_i[+2] - Q^_i[-2]))
+//        + K V'(phi0) e0 + (sextic local term),
+// and F = F^ / K with F^ = (g^.phi) phi - g^.
+template <typename T> struct SweepConst {
+    T lapw;                  // -K / (12 h^2) = -1728 h^2
+    T ke2, ke4;              // e2 = ke2 phi.L^phi, e4 = ke4 (G^ quadratic form)
+    T dt, dtK;               // dt and dt / K
+    T m2, my2, mz2, mw2;     // potential energy density (unscaled)
+    T m2K, my2K, mz2K, mw2K; // the same masses times K (scaled slope)
+    T c6e, c6q;              // sextic: e6 = c6e det^2, flux and local weight c6q det (det of phi, a^_i)
+    T invK;                  // gradient output
+    double dinvK, dinvK2, dinv12h3;  // unscale the power, |F|^2 and charge-density sums
+    bool more_pot, sextic, grad_flow;
 
-    Smem& sm;
-    // per-component base pointers (uniform); element offsets within a component fit 32 bits
-    fptr<FROM_TABLE, const T> pin[4];
-    fptr<FROM_TABLE, T> pout[4];
-    fptr<FROM_TABLE, T> vel[4];
-    fptr<FROM_TABLE, T> gout[4];
+    __device__ __forceinline__ void init(const SweepArgs& a, bool step_mode)
+    {
+        const double h = a.h, s = 12.0 * h, K = s * s * s * s;
+        lapw = T(-1728.0 * h * h);
+        ke2 = T(-1.0 / (24.0 * h * h));
+        ke4 = T(0.5 / K);
+        dt = T(a.dt);
+        dtK = T(a.dt / K);
+        m2 = T(a.m * a.m);
+        my2 = T(a.m_y * a.m_y);
+        mz2 = T(a.m_z * a.m_z);
+        mw2 = T(a.m_w * a.m_w);
+        m2K = T(K * a.m * a.m);
+        my2K = T(K * a.m_y * a.m_y);
+        mz2K = T(K * a.m_z * a.m_z);
+        mw2K = T(K * a.m_w * a.m_w);
+        c6e = T(0.5 * a.c6 / (K * s * s));
+        c6q = T(a.c6 / (s * s));
+        invK = T(1.0 / K);
+        dinvK = 1.0 / K;
+        dinvK2 = 1.0 / (K * K);
+        dinv12h3 = 1.0 / (s * s * s);
+        more_pot = a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0;
+        sextic = a.c6 != 0.0;
+        grad_flow = step_mode && a.gradient_flow != 0;
+    }
+};
+
+// One contiguous run of a field's work: output planes [xa, xe) of tile (ty, tz).
+struct Segment {
+    int ty, tz, xa, xe;
+};
+
+// The work of a field is ordered slab by slab (slabs of xchunk planes along x), tile by
+// tile within a slab, plane by plane within a tile; unit u is one plane of one tile.
+// Takes the segment that starts at unit u and ends at u1 or at the end of its (slab,
+// tile), whichever comes first, and advances u past it.
+__device__ __forceinline__ bool next_segment(long long& u, long long u1, int tiles, int tiles_z, int nx, int xchunk,
+                                             Segment& s)
+{
+    if (u >= u1) return false;
+    const long long per_slab = (long long)tiles * xchunk;
+    const int slab = (int)(u / per_slab);
+    const int x0 = slab * xchunk;
+    const int len = min(nx, x0 + xchunk) - x0;
+    const long long r = u - (long long)tiles * x0;
+    const int tile = (int)(r / len);
+    const int xo = (int)(r - (long long)tile * len);
+    const long long e = min(u1, u - xo + len);
+    s.ty = tile / tiles_z;
+    s.tz = tile - s.ty * tiles_z;
+    s.xa = 2 + x0 + xo;
+    s.xe = s.xa + (int)(e - u);
+    u = e;
+    return true;
+}
+
+// A march over output planes [xa, xe) takes (xe - xa) + 4 steps (flux planes xa-2 ..
+// xe+1); it runs in whole groups of five and so starts this many planes early.
+__device__ __forceinline__ int march_lead(int xa, int xe) { return (5 - ((xe - xa) + 4) % 5) % 5; }
+
+// Fields, flags and sums shared by the two roles.
+template <typename T, bool FROM_TABLE> struct SweepCommon {
+    // global-memory pointers, uniform over the block
+    gptr<const T> pin[4];
+    gptr<T> pout[4];
+    gptr<T> vel[4];
+    gptr<T> gout[4];
     int n0, n1, n2;
     unsigned plane_b;  // bytes per x-plane of one component
-    int xb, xe;
-    int zl, rg, z, hrow, hcol;
-    unsigned hoff;  // byte offset of this thread's halo site within a plane
-    bool halo_loader, redo, renorm64, projected, baryon, has_grad;
-    int restore;     // RESTORE_*: this sweep only rewrites the velocity
-    bool halo_wave;  // every flux row of this wave is a y-halo row (only its y-flux is used)
-    int yk[RY];
-    unsigned offk[RY];  // byte offsets of the flux positions within a plane
-    bool row_out[RY], yz_in[RY], y_near[RY], z_near;
-    T c1h, c2h, d1h, d2h, hd1h, hd2h, dt;  // stencil weights with 1/h, 1/h^2 (and 1/2) folded in
-    T m2, my2, mz2, mw2;                   // squared potential masses
-    T c6;                                  // sextic coefficient
-    bool more_pot;                         // any of m_y, m_z, m_w nonzero
-    bool sextic;                           // c6 nonzero
-    bool grad_flow;                        // gradient flow: phi += dt F, no velocity
+    bool redo, renorm64, projected, baryon, has_grad;
+    int restore;       // RESTORE_*: this sweep only rewrites the velocity
 
-    // registers carried along the march
-    T ring[5][4][RY];  // phi at planes j-2 .. j+2 (slot = plane mod 5 relative to the start)
-    T acc[5][4][RY];   // gradient accumulators of planes j-2 .. j+2
-    T nxt[4][RY];      // prefetched phi(j+3)
-    T hnxt[4];         // prefetched halo rows of phi(j+1)
+    __device__ __forceinline__ void load(unsigned off, int x, T (&dst)[4]) const
+    {
+        const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * plane_b;
+#pragma unroll
+        for (int A = 0; A < 4; ++A) dst[A] = ldb(pin[A], base + off);
+    }
+    __device__ __forceinline__ unsigned site_off(int y, int z) const
+    {
+        return (unsigned)(clampi(y, 0, n1 - 1) * n2 + clampi(z, 0, n2 - 1)) * (unsigned)sizeof(T);
+    }
+};
 
-    // FP64 partial sums of this thread: E2, E4, E0 and B densities (gradient mode); the
-    // flow step keeps the total energy density in pe2 and leaves the others at zero
-    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pb_sum = 0.0, pe6 = 0.0;
-    double pp = 0.0;  // power F . v of the incoming velocity (flow step; used by the power arrest rule)
-    T pf2 = T(0);
+// --------------------------------------------------------------- interior role
+// One output site per lane: row, col of the tile.
+template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interior {
+    using Smem = SweepSmem<T, G>;
+    Smem& sm;
+    const SweepConst<T>& k;
+    const SweepCommon<T, FROM_TABLE>& cm;
+    int row, col;
+    int pidx, qidx;    // LDS index of the own site in a phi plane and in a flux plane
+    unsigned off;      // byte offset of the own site within a plane
+    int xa, xe;
+    bool out;          // the own site is in I (in y and z)
+    bool yz_near;      // within two sites of a y or z face of I
+    unsigned outside;  // bit d: the y/z neighbour d (O_* below) lies outside I
+    enum : unsigned { O_YP1 = 1, O_YM1 = 2, O_YP2 = 4, O_YM2 = 8, O_ZP1 = 16, O_ZM1 = 32, O_ZP2 = 64, O_ZM2 = 128 };
 
-    __device__ __forceinline__ Sweeper(Smem& s) : sm(s) {}
+    T ring[5][4];  // phi of planes j-2 .. j+2 (slot = plane offset + 2 + step, mod 5)
+    T acc[5][4];   // scaled gradient accumulators of planes j-2 .. j+2 (same slots)
+    T nxt[4];      // prefetched phi(j+3)
 
-    // potential density V(phi0) and dV/dphi0: m^2 (1 - phi0) + m_y^2 (1 - phi0^2)/2
-    // + m_z^2 (1 - phi0)^2/2 + m_w^2 (1 - phi0)^4/4 (the program's four potentials,
-    // Sec. 7.7, halved to this energy's normalisation)
+    double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pe6 = 0.0, pb_sum = 0.0;
+    double pp = 0.0;  // scaled power F^ . v of the incoming velocity
+    T pf2 = T(0);     // largest scaled |F^|^2
+
+    __device__ __forceinline__ Interior(Smem& s, const SweepConst<T>& kk, const SweepCommon<T, FROM_TABLE>& c, int tid)
+        : sm(s), k(kk), cm(c)
+    {
+        row = tid / G::OZ;
+        col = tid - row * G::OZ;
+        pidx = (row + 4) * G::PW + col + 4;
+        qidx = (row + 2) * G::QW + col + 2;
+    }
+
     __device__ __forceinline__ T potential(T p0) const
     {
         const T u = T(1) - p0;
-        T v = m2 * u;
+        T v = k.m2 * u;
         if constexpr (EXT) {
-            if (more_pot) v += T(0.5) * my2 * (T(1) - p0 * p0) + T(0.5) * mz2 * u * u + T(0.25) * mw2 * (u * u) * (u * u);
+            if (k.more_pot)
+                v += T(0.5) * k.my2 * (T(1) - p0 * p0) + T(0.5) * k.mz2 * u * u + T(0.25) * k.mw2 * (u * u) * (u * u);
         }
         return v;
     }
-    __device__ __forceinline__ T potential_slope(T p0) const
+    // K dV/dphi0
+    __device__ __forceinline__ T slopeK(T p0) const
     {
         const T u = T(1) - p0;
-        T d = -m2;
+        T d = -k.m2K;
         if constexpr (EXT) {
-            if (more_pot) d -= my2 * p0 + mz2 * u + mw2 * u * u * u;
+            if (k.more_pot) d -= k.my2K * p0 + k.mz2K * u + k.mw2K * u * u * u;
         }
         return d;
     }
 
-    __device__ __forceinline__ void load_plane(int x, T (&dst)[4][RY]) const
+    __device__ __forceinline__ void setup(const Segment& s, int tiles_z_start)
     {
-        const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * plane_b;
-#pragma unroll
-        for (int A = 0; A < 4; ++A)
-#pragma unroll
-            for (int k = 0; k < RY; ++k) dst[A][k] = ldb(pin[A], base + offk[k]);
+        const int y0 = 2 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
+        const int n1 = cm.n1, n2 = cm.n2;
+        const int y = y0 + row, z = z0 + col;
+        out = (y <= n1 - 3) && (z >= 2) && (z <= n2 - 3);
+        outside = (y + 1 > n1 - 3 ? O_YP1 : 0u) | (y - 1 < 2 ? O_YM1 : 0u) | (y + 2 > n1 - 3 ? O_YP2 : 0u) |
+                  (y - 2 < 2 ? O_YM2 : 0u) | (z + 1 > n2 - 3 ? O_ZP1 : 0u) | (z - 1 < 2 ? O_ZM1 : 0u) |
+                  (z + 2 > n2 - 3 ? O_ZP2 : 0u) | (z - 2 < 2 ? O_ZM2 : 0u);
+        yz_near = out && outside != 0u;
+        off = cm.site_off(y, z);
+        xa = s.xa;
+        xe = s.xe;
     }
 
-    __device__ __forceinline__ void load_halo(int x, T (&dst)[4]) const
+    template <int SM2, int SM1, int S0, int SP1, int SP2>
+    __device__ __forceinline__ void boundary_terms(int j, const T* P)
     {
-        if (halo_loader) {
-            const unsigned base = (unsigned)clampi(x, 0, n0 - 1) * plane_b;
-#pragma unroll
-            for (int A = 0; A < 4; ++A) dst[A] = ldb(pin[A], base + hoff);
-        }
-    }
-
-    // one plane of the march, between two block barriers: flux at plane j, y/z-divergence
-    // of plane j-1, output of plane j-2, and staging of phi(j+1).  LDS buffers alternate
-    // by plane parity: phi(j) and the flux of plane j live in buffer pb, phi(j+1) and the
-    // flux of plane j-1 in buffer pb ^ 1, so one barrier per plane suffices.  Ring and
-    // accumulator slots 0..4 hold planes j-2 .. j+2 and are shifted at the end of the step.
-    __device__ __forceinline__ void step(int j, int pb)
-    {
-        constexpr int S_M2 = 0, S_M1 = 1, S_0 = 2, S_P1 = 3, S_P2 = 4;
-        const int qb = pb ^ 1;
-
-        if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
-        // commit the prefetched plane j+2 and the halo of plane j+1; prefetch j+3 and the halo of j+2
-        T hcur[4];
+        if (!out) return;
+        const int n0 = cm.n0;
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-#pragma unroll
-            for (int k = 0; k < RY; ++k) ring[S_P2][A][k] = nxt[A][k];
-            hcur[A] = hnxt[A];
+            const T* pa = P + A * G::PPLANE + pidx;
+            T o1 = T(0), o2 = T(0);  // outside first / second neighbours
+            if (j + 1 > n0 - 3) o1 += ring[SP1][A];
+            if (j - 1 < 2) o1 += ring[SM1][A];
+            if (j + 2 > n0 - 3) o2 += ring[SP2][A];
+            if (j - 2 < 2) o2 += ring[SM2][A];
+            if (outside & O_YP1) o1 += pa[G::PW];
+            if (outside & O_YM1) o1 += pa[-G::PW];
+            if (outside & O_ZP1) o1 += pa[1];
+            if (outside & O_ZM1) o1 += pa[-1];
+            if (outside & O_YP2) o2 += pa[2 * G::PW];
+            if (outside & O_YM2) o2 += pa[-2 * G::PW];
+            if (outside & O_ZP2) o2 += pa[2];
+            if (outside & O_ZM2) o2 += pa[-2];
+            // + 1/2 the outside terms of Lap phi: 12 h^2 x that is 8 o1 - o2 / 2, and L^ enters
+            // the scaled gradient with weight lapw < 0 and the opposite sign
+            acc[S0][A] = fmaT(k.lapw, fmaT(T(0.5), o2, T(-8) * o1), acc[S0][A]);
         }
-        load_plane(j + 3, nxt);
-        load_halo(j + 2, hnxt);
-        // velocity of the output plane j-2, used at the end of this step
-        T vcur[4][RY];
+    }
+
+    template <int U> __device__ __forceinline__ void step(int j, int pb)
+    {
+        constexpr int SM2 = U % 5, SM1 = (U + 1) % 5, S0 = (U + 2) % 5, SP1 = (U + 3) % 5, SP2 = (U + 4) % 5;
+        const int qb = pb ^ 1;
+        // Opaque to the optimiser from here on: the LDS and global addresses and the x-stencil
+        // arithmetic of this plane are then formed within it, not carried over from an
+        // earlier plane in registers across the barriers.
+        asm volatile("" : "+v"(pidx), "+v"(qidx), "+v"(off));
+#pragma unroll
+        for (int sl = 0; sl < 5; ++sl)
+            asm volatile("" : "+v"(ring[sl][0]), "+v"(ring[sl][1]), "+v"(ring[sl][2]), "+v"(ring[sl][3]));
+        // stage phi(j+1) into the other phi buffer (its last reads, of phi(j-1), came before
+        // the last barrier), then prefetch
+        {
+            T* Q = &sm.phi[qb][0][0];
+#pragma unroll
+            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx] = ring[SP1][A];
+        }
+#pragma unroll
+        for (int A = 0; A < 4; ++A) ring[SP2][A] = nxt[A];
+        cm.load(off, j + 3, nxt);
+        T vcur[4];
         if constexpr (MODE == MODE_STEP) {
-            const unsigned vb = (unsigned)clampi(j - 2, 0, n0 - 1) * plane_b;
+            const unsigned vb = (unsigned)clampi(j - 2, 0, cm.n0 - 1) * cm.plane_b;
 #pragma unroll
             for (int A = 0; A < 4; ++A)
-#pragma unroll
-                for (int k = 0; k < RY; ++k) vcur[A][k] = redo ? T(0) : ldb((fptr<FROM_TABLE, const T>)vel[A], vb + offk[k]);
+                vcur[A] = cm.redo ? T(0) : ldb((gptr<const T>)cm.vel[A], vb + off);
         }
+        const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
+        const bool j_out = (j >= xa) && (j < xe);
 
-        const bool j_in = (j >= 2) && (j <= n0 - 3);
-        const bool j_out = (j >= xb) && (j < xe);
-        const bool j_near = (j <= 3) || (j >= n0 - 4);
-        const bool full = !(kHaloFast && halo_wave);  // uniform over the wave
-
+        const T* P = &sm.phi[pb][0][0];
+        T c[4], ax[4], ay[4], az[4];
+        T cl = T(0);
 #pragma unroll
-        for (int k = 0; k < RY; ++k) {
-            const int r = rg + k * R0 + 2;  // LDS row and column of this position in sm.phi
-            const int cz = zl + 2;
-            T c[4], ax[4], ay[4], az[4];
-            T cl = T(0);  // phi . Lap phi
-#pragma unroll
-            for (int A = 0; A < 4; ++A) {
-                c[A] = ring[S_0][A][k];
-                const T xm2 = ring[S_M2][A][k], xm1 = ring[S_M1][A][k];
-                const T xp1 = ring[S_P1][A][k], xp2 = ring[S_P2][A][k];
-                const T ym2 = sm.phi[pb][A][r - 2][cz], ym1 = sm.phi[pb][A][r - 1][cz];
-                const T yp1 = sm.phi[pb][A][r + 1][cz], yp2 = sm.phi[pb][A][r + 2][cz];
-                const T zm2 = sm.phi[pb][A][r][cz - 2], zm1 = sm.phi[pb][A][r][cz - 1];
-                const T zp1 = sm.phi[pb][A][r][cz + 1], zp2 = sm.phi[pb][A][r][cz + 2];
-                ax[A] = c1h * (xp1 - xm1) + c2h * (xp2 - xm2);
-                ay[A] = c1h * (yp1 - ym1) + c2h * (yp2 - ym2);
-                az[A] = c1h * (zp1 - zm1) + c2h * (zp2 - zm2);
-                if (full && j_out) {
-                    // the five-point weights sum to zero, so the Laplacian is a weighted sum of
+        for (int A = 0; A < 4; ++A) {
+            const T* pa = P + A * G::PPLANE + pidx;
+            const T cc = ring[S0][A];
+            const T xm2 = ring[SM2][A], xm1 = ring[SM1][A], xp1 = ring[SP1][A], xp2 = ring[SP2][A];
+            const T ym2 = pa[-2 * G::PW], ym1 = pa[-G::PW], yp1 = pa[G::PW], yp2 = pa[2 * G::PW];
+            const T zm2 = pa[-2], zm1 = pa[-1], zp1 = pa[1], zp2 = pa[2];
+            c[A] = cc;
+            ax[A] = fmaT(T(8), xp1 - xm1, xm2 - xp2);
+            ay[A] = fmaT(T(8), yp1 - ym1, ym2 - yp2);
+            az[A] = fmaT(T(8), zp1 - zm1, zm2 - zp2);
+            if (j_out) {
+                T lap;  // 12 h^2 Lap phi
+                if constexpr (sizeof(T) == 4) {
                     // differences from the centre: no cancellation of O(1) terms in single precision
-                    const T lap = d1h * (((xp1 - c[A]) + (xm1 - c[A])) + ((yp1 - c[A]) + (ym1 - c[A])) +
-                                         ((zp1 - c[A]) + (zm1 - c[A]))) +
-                                  d2h * (((xp2 - c[A]) + (xm2 - c[A])) + ((yp2 - c[A]) + (ym2 - c[A])) +
-                                         ((zp2 - c[A]) + (zm2 - c[A])));
-                    cl += c[A] * lap;
-                    // E2 part of the gradient: -1/2 (Lap phi + Lap(1_I phi)) = -Lap phi + 1/2 (the
-                    // terms of Lap phi whose neighbour lies outside I); only sites within two of a
-                    // face of I have such terms, one direction at a time
-                    T o1 = T(0), o2 = T(0);  // sums of the outside first / second neighbours
-                    if (j_near) {            // uniform over the block
-                        if (j + 1 > n0 - 3) o1 += xp1;
-                        if (j - 1 < 2) o1 += xm1;
-                        if (j + 2 > n0 - 3) o2 += xp2;
-                        if (j - 2 < 2) o2 += xm2;
-                    }
-                    if (y_near[k]) {
-                        const int y = yk[k];
-                        o1 += ((y + 1 > n1 - 3) ? yp1 : T(0)) + ((y - 1 < 2) ? ym1 : T(0));
-                        o2 += ((y + 2 > n1 - 3) ? yp2 : T(0)) + ((y - 2 < 2) ? ym2 : T(0));
-                    }
-                    if (z_near) {
-                        o1 += ((z + 1 > n2 - 3) ? zp1 : T(0)) + ((z - 1 < 2) ? zm1 : T(0));
-                        o2 += ((z + 2 > n2 - 3) ? zp2 : T(0)) + ((z - 2 < 2) ? zm2 : T(0));
-                    }
-                    acc[S_0][A][k] += (hd1h * o1 + hd2h * o2) - lap;
+                    const T s1 = ((xp1 - cc) + (xm1 - cc)) + ((yp1 - cc) + (ym1 - cc)) + ((zp1 - cc) + (zm1 - cc));
+                    const T s2 = ((xp2 - cc) + (xm2 - cc)) + ((yp2 - cc) + (ym2 - cc)) + ((zp2 - cc) + (zm2 - cc));
+                    lap = fmaT(T(16), s1, -s2);
+                } else {
+                    const T s1 = ((xp1 + xm1) + (yp1 + ym1)) + (zp1 + zm1);
+                    const T s2 = ((xp2 + xm2) + (yp2 + ym2)) + (zp2 + zm2);
+                    lap = fmaT(T(-90), cc, fmaT(T(16), s1, -s2));
                 }
+                cl = fmaT(cc, lap, cl);
+                acc[S0][A] = fmaT(k.lapw, lap, acc[S0][A]);
             }
+        }
+        // The E2 part of the gradient is -1/2 (Lap phi + Lap(1_I phi)): the terms of Lap phi
+        // whose neighbour lies outside I count half.  Only sites within two of a face of I
+        // have such terms; a wave none of whose sites has one skips this.
+        const bool x_near = (j <= 3) || (j >= cm.n0 - 4);
+        if (j_out && (x_near || __builtin_amdgcn_ballot_w64(yz_near) != 0)) boundary_terms<SM2, SM1, S0, SP1, SP2>(j, P);
 
-            if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
-            const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
-            const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
-            const bool valid = yz_in[k] && j_in;
-            // the flux vanishes outside I: zero the Gram entries it is built from
-            const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
-            const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
-            T e6 = T(0);
-            if constexpr (EXT < EXT_SEXTIC) {
+        const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
+        const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
+        const bool valid = out && j_in;
+        // the flux vanishes outside I: zero the Gram entries it is built from
+        const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
+        const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
+        const T sx = fyy + fzz, sy = fxx + fzz, sz = fxx + fyy;
+        T qx[4], qy[4], qz[4];
 #pragma unroll
-                for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
-                if (full) {
-#pragma unroll
-                    for (int A = 0; A < 4; ++A) {
-                        const T qx = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
-                        sm.qz[pb][A][r][zl] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
-                        // push the x-flux: g(j-1) -= D q, g(j+1) += D q (weights c1/h), g(j-2), g(j+2) (c2/h)
-                        acc[S_M1][A][k] -= c1h * qx;
-                        acc[S_P1][A][k] += c1h * qx;
-                        acc[S_M2][A][k] -= c2h * qx;
-                        acc[S_P2][A][k] += c2h * qx;
-                    }
-                }
-            } else {
-                T qx[4], qy[4], qz[4];
+        for (int A = 0; A < 4; ++A) {
+            qx[A] = fmaT(sx, ax[A], -fmaT(fxy, ay[A], fxz * az[A]));
+            qy[A] = fmaT(sy, ay[A], -fmaT(fxy, ax[A], fyz * az[A]));
+            qz[A] = fmaT(sz, az[A], -fmaT(fxz, ax[A], fyz * ay[A]));
+        }
+        T e6 = T(0);
+        if constexpr (EXT == EXT_SEXTIC) {
+            if (k.sextic) {
+                // e6 = c6 det^2 / 2, det = det[phi, a_x, a_y, a_z]: flux c6 det ddet/da_i (zero
+                // outside I) and the local term c6 det ddet/dphi
+                T C0[4], C1[4], C2[4], C3[4];
+                const T det = det4_cofactors(c, ax, ay, az, C0, C1, C2, C3);
+                const T dv = valid ? k.c6q * det : T(0);
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    qx[A] = (fyy + fzz) * ax[A] - fxy * ay[A] - fxz * az[A];
-                    qy[A] = (fxx + fzz) * ay[A] - fxy * ax[A] - fyz * az[A];
-                    qz[A] = (fxx + fyy) * az[A] - fxz * ax[A] - fyz * ay[A];
+                    qx[A] = fmaT(dv, C1[A], qx[A]);
+                    qy[A] = fmaT(dv, C2[A], qy[A]);
+                    qz[A] = fmaT(dv, C3[A], qz[A]);
+                    acc[S0][A] = fmaT(dv, C0[A], acc[S0][A]);
                 }
-                if (sextic) {
-                    // e6 = c6 det^2 / 2, det = det[phi, a_x, a_y, a_z]: flux c6 det dDet/da_i
-                    // (zero outside I) and the local term c6 det dDet/dphi
-                    T C0[4], C1[4], C2[4], C3[4];
-                    const T det = det4_cofactors(c, ax, ay, az, C0, C1, C2, C3);
-                    const T dv = valid ? c6 * det : T(0);
-#pragma unroll
-                    for (int A = 0; A < 4; ++A) {
-                        qx[A] += dv * C1[A];
-                        qy[A] += dv * C2[A];
-                        qz[A] += dv * C3[A];
-                        acc[S_0][A][k] += dv * C0[A];
-                    }
-                    e6 = T(0.5) * c6 * det * det;
-                }
-#pragma unroll
-                for (int A = 0; A < 4; ++A) sm.qy[pb][A][r][zl] = qy[A];
-                if (full) {
-#pragma unroll
-                    for (int A = 0; A < 4; ++A) {
-                        sm.qz[pb][A][r][zl] = qz[A];
-                        acc[S_M1][A][k] -= c1h * qx[A];
-                        acc[S_P1][A][k] += c1h * qx[A];
-                        acc[S_M2][A][k] -= c2h * qx[A];
-                        acc[S_P2][A][k] += c2h * qx[A];
-                    }
-                }
+                e6 = k.c6e * det * det;
             }
-            if (full) {
-                if (row_out[k] && j_out) {
-                    const T e2 = T(-0.5) * cl;
-                    const T e4 = T(0.5) * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
-                    const T e0 = potential(c[0]);
-                    if constexpr (MODE == MODE_STEP) {
-                        if constexpr (EXT == EXT_SEXTIC)
-                            pe2 += (double)(e2 + e4 + e0 + e6);  // the flow needs the total energy only
-                        else
-                            pe2 += (double)(e2 + e4 + e0);
-                    } else {
-                        pe2 += (double)e2;
-                        pe4 += (double)e4;
-                        pe0 += (double)e0;
-                        if constexpr (EXT == EXT_SEXTIC) pe6 += (double)e6;
-                        if (baryon) pb_sum += (double)det4(c, ax, ay, az);
-                    }
-                }
+        }
+#pragma unroll
+        for (int A = 0; A < 4; ++A) {
+            sm.q[pb][0][A][qidx] = qy[A];
+            sm.q[pb][1][A][qidx] = qz[A];
+            // x-divergence pushed to the accumulators of planes j-2 .. j+2
+            acc[SM1][A] = fmaT(T(-8), qx[A], acc[SM1][A]);
+            acc[SP1][A] = fmaT(T(8), qx[A], acc[SP1][A]);
+            acc[SM2][A] += qx[A];
+            acc[SP2][A] -= qx[A];
+        }
+        if (out && j_out) {
+            const T e2 = k.ke2 * cl;
+            const T e4 = k.ke4 * (gxx * gyy + gxx * gzz + gyy * gzz - gxy * gxy - gxz * gxz - gyz * gyz);
+            const T e0 = potential(c[0]);
+            if constexpr (MODE == MODE_STEP) {
+                pe2 += (double)(e2 + e4 + e0 + e6);  // the flow needs the total energy only
+            } else {
+                pe2 += (double)e2;
+                pe4 += (double)e4;
+                pe0 += (double)e0;
+                pe6 += (double)e6;
+                if (cm.baryon) pb_sum += (double)det4(c, ax, ay, az);
             }
         }
 
         // y- and z-divergence of the flux of plane j-1 (written before the last barrier)
-        if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
-        if (full && j - 1 >= xb && j - 1 < xe) {
+        if (j - 1 >= xa && j - 1 < xe) {
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                const int o = (rg + k * R0 + 2) * LW + zl;
-#pragma unroll
-                for (int A = 0; A < 4; ++A) {
-                    const T* qy = &sm.qy[qb][A][0][0] + o;
-                    const T* qz = &sm.qz[qb][A][0][0] + o;
-                    const T dy = c1h * (qy[LW] - qy[-LW]) + c2h * (qy[2 * LW] - qy[-2 * LW]);
-                    const T dz = c1h * (qz[1] - qz[-1]) + c2h * (qz[2] - qz[-2]);
-                    acc[S_M1][A][k] -= dy + dz;
-                }
+            for (int A = 0; A < 4; ++A) {
+                const T* fy = &sm.q[qb][0][A][qidx];
+                const T* fz = &sm.q[qb][1][A][qidx];
+                const T t = (fy[-G::QW] - fy[G::QW]) + (fz[-1] - fz[1]);
+                const T u = (fy[2 * G::QW] - fy[-2 * G::QW]) + (fz[2] - fz[-2]);
+                acc[SM1][A] = fmaT(T(8), t, acc[SM1][A]) + u;
             }
         }
 
-        if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
         // output plane j-2 is complete
-        if (full && j - 2 >= xb && j - 2 < xe) {
-            const unsigned base = (unsigned)(j - 2) * plane_b;
+        if (j - 2 >= xa && j - 2 < xe && out) {
+            const unsigned base = (unsigned)(j - 2) * cm.plane_b + off;
+            T g[4], p[4], f[4];
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
-                if (row_out[k]) {
-                    T g[4], p[4], f[4];
+            for (int A = 0; A < 4; ++A) {
+                g[A] = acc[SM2][A];
+                p[A] = ring[SM2][A];
+            }
+            g[0] += slopeK(p[0]);
+            const T gp = dot4(g, p);
+#pragma unroll
+            for (int A = 0; A < 4; ++A) f[A] = fmaT(gp, p[A], -g[A]);  // F^ = (g^.phi) phi - g^
+            pf2 = fmax_nonneg(pf2, dot4(f, f));
+            if constexpr (MODE == MODE_STEP) {
+                pp += (double)f[0] * vcur[0] + (double)f[1] * vcur[1] + (double)f[2] * vcur[2] + (double)f[3] * vcur[3];
+                if (cm.restore) {
+#pragma unroll
+                    for (int A = 0; A < 4; ++A)
+                        stb(cm.vel[A], base, cm.restore == RESTORE_ZERO ? T(0) : fmaT(-k.dtK, f[A], vcur[A]));
+                } else {
+                    T v[4], q[4], pn[4];
 #pragma unroll
                     for (int A = 0; A < 4; ++A) {
-                        g[A] = acc[S_M2][A][k];
-                        p[A] = ring[S_M2][A][k];
-                    }
-                    g[0] += potential_slope(p[0]);
-                    const T gp = dot4(g, p);
-#pragma unroll
-                    for (int A = 0; A < 4; ++A) f[A] = gp * p[A] - g[A];  // F = -(g - (g.phi) phi)
-                    pf2 = fmax_nonneg(pf2, dot4(f, f));
-                    if constexpr (MODE == MODE_STEP) {
-                        // power of the incoming velocity (zero on a redo sweep, where v = 0)
-                        pp += (double)f[0] * vcur[0][k] + (double)f[1] * vcur[1][k] + (double)f[2] * vcur[2][k] +
-                              (double)f[3] * vcur[3][k];
-                        if (restore) {
-#pragma unroll
-                            for (int A = 0; A < 4; ++A)
-                                stb(vel[A], base + offk[k], restore == RESTORE_ZERO ? T(0) : vcur[A][k] - dt * f[A]);
-                            continue;
-                        }
-                        T v[4], q[4], pn[4];
-#pragma unroll
-                        for (int A = 0; A < 4; ++A) {
-                            if constexpr (EXT) {
-                                v[A] = grad_flow ? T(0) : vcur[A][k] + dt * f[A];
-                                q[A] = p[A] + dt * (grad_flow ? f[A] : v[A]);
-                            } else {
-                                v[A] = vcur[A][k] + dt * f[A];
-                                q[A] = p[A] + dt * v[A];
-                            }
-                        }
-                        if (renorm64) {
-                            const double s2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
-                                              (double)q[3] * q[3];
-                            const double inv = 1.0 / sqrt(s2);
-#pragma unroll
-                            for (int A = 0; A < 4; ++A) pn[A] = T((double)q[A] * inv);
+                        if constexpr (EXT) {
+                            v[A] = k.grad_flow ? T(0) : fmaT(k.dtK, f[A], vcur[A]);
+                            q[A] = k.grad_flow ? fmaT(k.dtK, f[A], p[A]) : fmaT(k.dt, v[A], p[A]);
                         } else {
-                            const T inv = rnorm(dot4(q, q));
-#pragma unroll
-                            for (int A = 0; A < 4; ++A) pn[A] = q[A] * inv;
-                        }
-#pragma unroll
-                        for (int A = 0; A < 4; ++A) {
-                            stb(pout[A], base + offk[k], pn[A]);
-                            stb(vel[A], base + offk[k], v[A]);
-                        }
-                    } else {
-                        if (has_grad) {
-#pragma unroll
-                            for (int A = 0; A < 4; ++A) stb(gout[A], base + offk[k], projected ? -f[A] : g[A]);
+                            v[A] = fmaT(k.dtK, f[A], vcur[A]);
+                            q[A] = fmaT(k.dt, v[A], p[A]);
                         }
                     }
+                    if (cm.renorm64) {
+                        const double s2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] +
+                                          (double)q[3] * q[3];
+                        const double inv = 1.0 / sqrt(s2);
+#pragma unroll
+                        for (int A = 0; A < 4; ++A) pn[A] = T((double)q[A] * inv);
+                    } else {
+                        const T inv = rnorm(dot4(q, q));
+#pragma unroll
+                        for (int A = 0; A < 4; ++A) pn[A] = q[A] * inv;
+                    }
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        stb(cm.pout[A], base, pn[A]);
+                        stb(cm.vel[A], base, v[A]);
+                    }
+                }
+            } else {
+                if (cm.has_grad) {
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) stb(cm.gout[A], base, (cm.projected ? -f[A] : g[A]) * k.invK);
                 }
             }
         }
-
-        // stage phi(j+1) and its halo for the next plane
 #pragma unroll
-        for (int A = 0; A < 4; ++A) {
-#pragma unroll
-            for (int k = 0; k < RY; ++k) sm.phi[qb][A][rg + k * R0 + 2][zl + 2] = ring[S_P1][A][k];
-            if (halo_loader) sm.phi[qb][A][hrow][hcol] = hcur[A];
-        }
+        for (int A = 0; A < 4; ++A) acc[SM2][A] = T(0);  // the slot starts plane j+3
         __syncthreads();
+    }
 
-        // advance the rings by one plane; the freed accumulator starts plane j+3
+    // the march over one segment
+    __device__ __forceinline__ void march()
+    {
 #pragma unroll
-        for (int A = 0; A < 4; ++A)
+        for (int s = 0; s < 5; ++s)
 #pragma unroll
-            for (int k = 0; k < RY; ++k) {
+            for (int A = 0; A < 4; ++A) acc[s][A] = T(0);
+        // the march runs in groups of five planes; it starts `lead` planes early so that the
+        // last group ends with output plane xe-1 (the early planes reach no output plane)
+        const int lead = march_lead(xa, xe);
+        const int js = xa - 2 - lead;  // first flux plane; ring slots 0 .. 3 hold planes js-2 .. js+1
+        cm.load(off, js - 2, ring[0]);
+        cm.load(off, js - 1, ring[1]);
+        cm.load(off, js, ring[2]);
+        cm.load(off, js + 1, ring[3]);
+        cm.load(off, js + 2, nxt);
+        T* Q = &sm.phi[0][0][0];
 #pragma unroll
-                for (int sl = 0; sl < 4; ++sl) {
-                    ring[sl][A][k] = ring[sl + 1][A][k];
-                    acc[sl][A][k] = acc[sl + 1][A][k];
-                }
-                acc[4][A][k] = T(0);
-            }
+        for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx] = ring[2][A];
+        __syncthreads();
+        const int nst = (xe - xa) + 4 + lead;
+        for (int st = 0; st < nst; st += 5) {
+            const int j = js + st, pb = st & 1;
+            step<0>(j, pb);
+            step<1>(j + 1, pb ^ 1);
+            step<2>(j + 2, pb);
+            step<3>(j + 3, pb ^ 1);
+            step<4>(j + 4, pb);
+        }
     }
 };
 
-// One block's share of one field: logical block b of nb blocks covering the
-// field's work items.  Used by the single-field and the batched kernels
-// (FROM_TABLE: the arguments were read from the batch's job table).
-template <typename T, int NW, int LW, int RY, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE>
-__device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
-                                            typename Sweeper<T, NW, LW, RY, MODE, FROM_TABLE, EXT>::Smem& smem)
-{
-    using SW = Sweeper<T, NW, LW, RY, MODE, FROM_TABLE, EXT>;
-    using TL = typename SW::TL;
-    constexpr int PY = TL::PY;
-    constexpr int R0 = TL::R0;
+// ------------------------------------------------------------------ halo role
+// HPT halo positions per lane; each supplies one flux component: Q_y on the y-halo
+// rows, Q_z on the z-halo columns.
+template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
+    using Smem = SweepSmem<T, G>;
+    static constexpr int HPT = G::HPT;
+    Smem& sm;
+    const SweepConst<T>& k;
+    const SweepCommon<T, FROM_TABLE>& cm;
+    int pos[HPT];        // halo position index (>= NHALO: none)
+    int pidx[HPT];       // LDS index in a phi plane
+    int qidx[HPT];       // LDS index of the supplied flux (Q_y or Q_z plane, component 0)
+    unsigned off[HPT];
+    bool active[HPT], is_y[HPT], vyz[HPT];
+    int hr[HPT], hc[HPT];  // tile-relative row and column
+    static constexpr int FPT = G::FPT;
+    bool floader[FPT];     // frame sites of this lane
+    int fr[FPT], fc[FPT];  // their tile-relative rows and columns
+    int fidx[FPT];         // LDS index in a phi plane
+    unsigned foff[FPT];    // byte offset in the current segment
+    int xa, xe;
+    T ring[HPT][5][4];
+    T nxt[HPT][4];
+    T fnxt[FPT][4];        // prefetched frame sites of phi(j+2)
 
-    const Ctl* ctl = a.ctl;
-    int cur = 0;
-    SW sw(smem);
-    sw.redo = false;
-    sw.renorm64 = false;
-    sw.restore = RESTORE_NONE;
-    if constexpr (MODE == MODE_STEP) {
-        sw.restore = ctl->restore;
-        if (ctl->done && !sw.restore) return;  // uniform: the flow has stopped
-        cur = ctl->cur;
-        sw.redo = ctl->redo != 0;
-        const int kr = ctl->renorm64_every;
-        sw.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
+    __device__ __forceinline__ Halo(Smem& s, const SweepConst<T>& kk, const SweepCommon<T, FROM_TABLE>& c, int u)
+        : sm(s), k(kk), cm(c)
+    {
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int p = u + i * G::NWH * 64;
+            active[i] = p < G::NHALO;
+            const int pp = active[i] ? p : 0;
+            int r, cc;
+            bool yh;
+            if (pp < 4 * G::OZ) {
+                const int q = pp / G::OZ;
+                r = q < 2 ? q - 2 : G::OY + q - 2;
+                cc = pp - q * G::OZ;
+                yh = true;
+            } else {
+                const int g = pp - 4 * G::OZ, q = g & 3;
+                r = g >> 2;
+                cc = q < 2 ? q - 2 : G::OZ + q - 2;
+                yh = false;
+            }
+            hr[i] = r;
+            hc[i] = cc;
+            is_y[i] = yh;
+            pidx[i] = (r + 4) * G::PW + cc + 4;
+            qidx[i] = (yh ? 0 : 4 * G::QPLANE) + (r + 2) * G::QW + cc + 2;
+        }
+#pragma unroll
+        for (int i = 0; i < FPT; ++i) {
+            const int f0 = u + i * G::NWH * 64;
+            floader[i] = f0 < G::NFRAME;
+            const int f = floader[i] ? f0 : 0;
+            int r, cc;
+            if (f < 4 * G::OZ) {
+                const int q = f / G::OZ;
+                r = q < 2 ? q - 4 : G::OY + q;
+                cc = f - q * G::OZ;
+            } else if (f < 4 * G::OZ + 4 * G::OY) {
+                const int g = f - 4 * G::OZ, q = g & 3;
+                r = g >> 2;
+                cc = q < 2 ? q - 4 : G::OZ + q;
+            } else {
+                const int g = f - 4 * G::OZ - 4 * G::OY, qr = g >> 2, qc = g & 3;
+                r = qr < 2 ? qr - 2 : G::OY + qr - 2;
+                cc = qc < 2 ? qc - 2 : G::OZ + qc - 2;
+            }
+            fr[i] = r;
+            fc[i] = cc;
+            fidx[i] = (r + 4) * G::PW + cc + 4;
+        }
     }
-    sw.n0 = a.n0;
-    sw.n1 = a.n1;
-    sw.n2 = a.n2;
-    const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
-    sw.plane_b = (unsigned)(n1 * n2) * (unsigned)sizeof(T);
-    const long long N3 = (long long)n0 * n1 * n2;
+
+    __device__ __forceinline__ void setup(const Segment& s, int tiles_z_start)
+    {
+        const int y0 = 2 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            const int y = y0 + hr[i], z = z0 + hc[i];
+            vyz[i] = (y >= 2) && (y <= cm.n1 - 3) && (z >= 2) && (z <= cm.n2 - 3);
+            off[i] = cm.site_off(y, z);
+        }
+#pragma unroll
+        for (int i = 0; i < FPT; ++i) foff[i] = cm.site_off(y0 + fr[i], z0 + fc[i]);
+        xa = s.xa;
+        xe = s.xe;
+    }
+
+    template <int U> __device__ __forceinline__ void step(int j, int pb)
+    {
+        constexpr int SM2 = U % 5, SM1 = (U + 1) % 5, S0 = (U + 2) % 5, SP1 = (U + 3) % 5, SP2 = (U + 4) % 5;
+        const int qb = pb ^ 1;
+        T* Pn = &sm.phi[qb][0][0];
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            asm volatile("" : "+v"(pidx[i]), "+v"(qidx[i]), "+v"(off[i]));
+#pragma unroll
+            for (int sl = 0; sl < 5; ++sl)
+                asm volatile("" : "+v"(ring[i][sl][0]), "+v"(ring[i][sl][1]), "+v"(ring[i][sl][2]), "+v"(ring[i][sl][3]));
+            // stage phi(j+1) into the other phi buffer, then prefetch
+            if (active[i]) {
+#pragma unroll
+                for (int A = 0; A < 4; ++A) Pn[A * G::PPLANE + pidx[i]] = ring[i][SP1][A];
+            }
+#pragma unroll
+            for (int A = 0; A < 4; ++A) ring[i][SP2][A] = nxt[i][A];
+            if (active[i]) cm.load(off[i], j + 3, nxt[i]);
+        }
+        // the frame sites of phi(j+1) likewise
+#pragma unroll
+        for (int i = 0; i < FPT; ++i) {
+            asm volatile("" : "+v"(fidx[i]), "+v"(foff[i]));
+            if (floader[i]) {
+#pragma unroll
+                for (int A = 0; A < 4; ++A) Pn[A * G::PPLANE + fidx[i]] = fnxt[i][A];
+                cm.load(foff[i], j + 2, fnxt[i]);
+            }
+        }
+        const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
+        const T* P = &sm.phi[pb][0][0];
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            if (!active[i]) continue;
+            T c[4], ax[4], ap[4], aq[4];
+            const bool yh = is_y[i];
+#pragma unroll
+            for (int A = 0; A < 4; ++A) {
+                const T* pa = P + A * G::PPLANE + pidx[i];
+                c[A] = ring[i][S0][A];
+                ax[A] = fmaT(T(8), ring[i][SP1][A] - ring[i][SM1][A], ring[i][SM2][A] - ring[i][SP2][A]);
+                const T ay = fmaT(T(8), pa[G::PW] - pa[-G::PW], pa[-2 * G::PW] - pa[2 * G::PW]);
+                const T az = fmaT(T(8), pa[1] - pa[-1], pa[-2] - pa[2]);
+                ap[A] = yh ? ay : az;
+                aq[A] = yh ? az : ay;
+            }
+            const bool valid = vyz[i] && j_in;
+            const T gxx = valid ? dot4(ax, ax) : T(0), gqq = valid ? dot4(aq, aq) : T(0);
+            const T gpx = valid ? dot4(ap, ax) : T(0), gpq = valid ? dot4(ap, aq) : T(0);
+            const T sp = gxx + gqq;
+            T qp[4];
+#pragma unroll
+            for (int A = 0; A < 4; ++A) qp[A] = fmaT(sp, ap[A], -fmaT(gpx, ax[A], gpq * aq[A]));
+            if constexpr (EXT == EXT_SEXTIC) {
+                if (k.sextic) {
+                    // the sextic flux of the supplied direction, c6 det ddet/da_p
+                    T ay[4], az[4], C0[4], C1[4], C2[4], C3[4];
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) {
+                        ay[A] = yh ? ap[A] : aq[A];
+                        az[A] = yh ? aq[A] : ap[A];
+                    }
+                    const T det = det4_cofactors(c, ax, ay, az, C0, C1, C2, C3);
+                    const T dv = valid ? k.c6q * det : T(0);
+#pragma unroll
+                    for (int A = 0; A < 4; ++A) qp[A] = fmaT(dv, yh ? C2[A] : C3[A], qp[A]);
+                }
+            }
+            T* Q = &sm.q[pb][0][0][0];
+#pragma unroll
+            for (int A = 0; A < 4; ++A) Q[qidx[i] + A * G::QPLANE] = qp[A];
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void march()
+    {
+        const int lead = march_lead(xa, xe);
+        const int js = xa - 2 - lead;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            if (!active[i]) continue;
+            cm.load(off[i], js - 2, ring[i][0]);
+            cm.load(off[i], js - 1, ring[i][1]);
+            cm.load(off[i], js, ring[i][2]);
+            cm.load(off[i], js + 1, ring[i][3]);
+            cm.load(off[i], js + 2, nxt[i]);
+        }
+        T* Q = &sm.phi[0][0][0];
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
+            if (!active[i]) continue;
+#pragma unroll
+            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx[i]] = ring[i][2][A];
+        }
+#pragma unroll
+        for (int i = 0; i < FPT; ++i) {
+            if (!floader[i]) continue;
+            T f0[4];
+            cm.load(foff[i], js, f0);
+            cm.load(foff[i], js + 1, fnxt[i]);
+#pragma unroll
+            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + fidx[i]] = f0[A];
+        }
+        __syncthreads();
+        const int nst = (xe - xa) + 4 + lead;
+        for (int st = 0; st < nst; st += 5) {
+            const int j = js + st, pb = st & 1;
+            step<0>(j, pb);
+            step<1>(j + 1, pb ^ 1);
+            step<2>(j + 2, pb);
+            step<3>(j + 3, pb ^ 1);
+            step<4>(j + 4, pb);
+        }
+    }
+};
+
+// One block's share of one field: logical block b of nb blocks, which takes units
+// [W b / nb, W (b+1) / nb) of the field's W = tiles x (n0 - 4) units of work.  Used by
+// the single-field and the batched kernels (FROM_TABLE: the arguments were read from
+// the batch's job table).
+template <typename T, class G, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE>
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, SweepSmem<T, G>& sm)
+{
+    const Ctl* ctl = a.ctl;
+    SweepCommon<T, FROM_TABLE> cm;
+    int cur = 0;
+    cm.redo = false;
+    cm.renorm64 = false;
+    cm.restore = RESTORE_NONE;
+    if constexpr (MODE == MODE_STEP) {
+        cm.restore = ctl->restore;
+        if (ctl->done && !cm.restore) return;  // uniform: the flow has stopped
+        cur = ctl->cur;
+        cm.redo = ctl->redo != 0;
+        const int kr = ctl->renorm64_every;
+        cm.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
+    }
+    cm.n0 = a.n0;
+    cm.n1 = a.n1;
+    cm.n2 = a.n2;
+    cm.plane_b = (unsigned)(a.n1 * a.n2) * (unsigned)sizeof(T);
+    const long long N3 = (long long)a.n0 * a.n1 * a.n2;
     {
         const T* pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
         T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
@@ -641,190 +932,112 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb,
             pout = uniform_ptr(pout);
             pvel = uniform_ptr(pvel);
         }
+        if constexpr (!FROM_TABLE) pgrad = uniform_ptr(pgrad);
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-            sw.pin[A] = (fptr<FROM_TABLE, const T>)(pin + A * N3);
-            sw.pout[A] = (fptr<FROM_TABLE, T>)(pout ? pout + A * N3 : nullptr);
-            sw.vel[A] = (fptr<FROM_TABLE, T>)(pvel ? pvel + A * N3 : nullptr);
-            sw.gout[A] = (fptr<FROM_TABLE, T>)(pgrad ? pgrad + A * N3 : nullptr);
+            cm.pin[A] = (gptr<const T>)(pin + A * N3);
+            cm.pout[A] = (gptr<T>)(pout ? pout + A * N3 : nullptr);
+            cm.vel[A] = (gptr<T>)(pvel ? pvel + A * N3 : nullptr);
+            cm.gout[A] = (gptr<T>)(pgrad ? pgrad + A * N3 : nullptr);
         }
     }
-    sw.has_grad = a.grad != nullptr;
-    sw.projected = a.projected != 0;
-    sw.baryon = a.baryon != 0;
-
-    sw.c1h = T(Coef<double>::c1 / a.h);
-    sw.c2h = T(Coef<double>::c2 / a.h);
-    sw.d1h = T(Coef<double>::d1 / (a.h * a.h));
-    sw.d2h = T(Coef<double>::d2 / (a.h * a.h));
-    sw.hd1h = T(0.5 * Coef<double>::d1 / (a.h * a.h));
-    sw.hd2h = T(0.5 * Coef<double>::d2 / (a.h * a.h));
-    sw.dt = T(a.dt);
-    sw.m2 = T(a.m * a.m);
-    sw.my2 = T(a.m_y * a.m_y);
-    sw.mz2 = T(a.m_z * a.m_z);
-    sw.mw2 = T(a.m_w * a.m_w);
-    sw.more_pot = a.m_y != 0.0 || a.m_z != 0.0 || a.m_w != 0.0;
-    sw.c6 = T(a.c6);
-    sw.sextic = a.c6 != 0.0;
-    sw.grad_flow = MODE == MODE_STEP && a.gradient_flow != 0;
+    cm.has_grad = a.grad != nullptr;
+    cm.projected = a.projected != 0;
+    cm.baryon = a.baryon != 0;
+    SweepConst<T> k;
+    k.init(a, MODE == MODE_STEP);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    sw.zl = lane % LW;
-    sw.rg = wave * TL::RPW + lane / LW;
-    sw.halo_loader = tid < TL::NH;
-    if (tid < TL::NH_ROWS) {
-        const int q = tid / (LW + 4);
-        sw.hrow = q < 2 ? q : PY + q;
-        sw.hcol = tid % (LW + 4);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tiles = a.tiles_y * a.tiles_z;
+    const int nx = a.n0 - 4;
+    const long long W = (long long)tiles * nx;
+    const long long u0 = W * b / nb, u1 = W * (b + 1) / nb;
+
+    double vals[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (wave < G::NWI) {
+        Interior<T, G, MODE, FROM_TABLE, EXT> it(sm, k, cm, tid);
+        long long u = u0;
+        Segment s;
+        while (next_segment(u, u1, tiles, a.tiles_z, nx, a.xchunk, s)) {
+            it.setup(s, a.zstart);
+            it.march();
+        }
+        vals[0] = it.pe2;
+        vals[1] = it.pe4;
+        vals[2] = it.pe0;
+        vals[3] = it.pb_sum * k.dinv12h3;
+        vals[4] = (double)it.pf2 * k.dinvK2;
+        vals[5] = it.pp * k.dinvK;
+        vals[6] = it.pe6;
     } else {
-        const int u = min(tid, TL::NH - 1) - TL::NH_ROWS;  // 0 .. 4 PY - 1
-        const int q = u & 3;
-        sw.hrow = 2 + (u >> 2);
-        sw.hcol = q < 2 ? q : LW + q;
-    }
-    {
-        // rows of this wave: w*RPW + (0..RPW-1) + k*R0; all of them in {0, 1, PY-2, PY-1}?
-        const int wv = __builtin_amdgcn_readfirstlane(wave);
-        bool all_halo = true;
-        for (int k = 0; k < RY; ++k)
-            for (int q = 0; q < TL::RPW; ++q) {
-                const int r = wv * TL::RPW + q + k * R0;
-                all_halo = all_halo && (r < 2 || r >= PY - 2);
-            }
-        sw.halo_wave = all_halo;
-    }
-
-    // Work items: x is cut into slabs of `xchunk` planes; an item is one (y, z) tile of
-    // one slab, items ordered slab-major with the tiles of a slab consecutive.  Items are
-    // divided evenly over the nb logical blocks of this field.
-    const int nx = n0 - 4;
-    const int ncols = a.tiles_z * a.tiles_y;
-    const int nslabs = (nx + a.xchunk - 1) / a.xchunk;
-    const long long W = (long long)ncols * nslabs;
-    const long long w1 = W * (b + 1) / nb;
-    for (long long w = W * b / nb; w < w1; ++w) {
-        const int slab = (int)(w / ncols);
-        const int tile = (int)(w % ncols);
-        const int x0 = slab * a.xchunk;
-        const int x1 = min(nx, x0 + a.xchunk);
-        const int tz = tile % a.tiles_z;
-        const int ty = tile / a.tiles_z;
-        const int z0 = 2 + tz * TL::OZ;
-        const int y0 = 2 + ty * TL::OY;
-        sw.xb = 2 + x0;
-        sw.xe = 2 + x1;
-        sw.z = z0 - 2 + sw.zl;
-        const int zc = clampi(sw.z, 0, n2 - 1);
-        const bool lane_out = (sw.zl >= 2) && (sw.zl < LW - 2) && (sw.z <= n2 - 3);
-        const bool z_in = (sw.z >= 2) && (sw.z <= n2 - 3);
-        sw.z_near = (sw.z <= 3) || (sw.z >= n2 - 4);
-#pragma unroll
-        for (int k = 0; k < RY; ++k) {
-            const int r = sw.rg + k * R0;
-            const int y = y0 - 2 + r;
-            sw.yk[k] = y;
-            sw.offk[k] = (unsigned)(clampi(y, 0, n1 - 1) * n2 + zc) * (unsigned)sizeof(T);
-            sw.row_out[k] = (r >= 2) && (r < PY - 2) && (y <= n1 - 3) && lane_out;
-            sw.yz_in[k] = z_in && (y >= 2) && (y <= n1 - 3);
-            sw.y_near[k] = (y <= 3) || (y >= n1 - 4);
+        Halo<T, G, FROM_TABLE, EXT> hl(sm, k, cm, tid - G::NWI * 64);
+        long long u = u0;
+        Segment s;
+        while (next_segment(u, u1, tiles, a.tiles_z, nx, a.xchunk, s)) {
+            hl.setup(s, a.zstart);
+            hl.march();
         }
-        // halo site of the phi plane loaded by this thread
-        sw.hoff = (unsigned)(clampi(y0 - 4 + sw.hrow, 0, n1 - 1) * n2 + clampi(z0 - 4 + sw.hcol, 0, n2 - 1)) *
-                  (unsigned)sizeof(T);
-
-#pragma unroll
-        for (int s = 0; s < 5; ++s)
-#pragma unroll
-            for (int A = 0; A < 4; ++A)
-#pragma unroll
-                for (int k = 0; k < RY; ++k) sw.acc[s][A][k] = T(0);
-
-        // prologue: ring slots 0..3 hold planes jstart-2 .. jstart+1; nxt holds jstart+2
-        const int jstart = sw.xb - 2;
-        const int nst = (sw.xe - sw.xb) + 4;
-        sw.load_plane(jstart - 2, sw.ring[0]);
-        sw.load_plane(jstart - 1, sw.ring[1]);
-        sw.load_plane(jstart, sw.ring[2]);
-        sw.load_plane(jstart + 1, sw.ring[3]);
-        sw.load_plane(jstart + 2, sw.nxt);
-        // phi(jstart) and its halo go to LDS buffer 0 before the first plane; the halo of
-        // jstart+1 is prefetched
-        {
-            T h0[4];
-            sw.load_halo(jstart, h0);
-            sw.load_halo(jstart + 1, sw.hnxt);
-#pragma unroll
-            for (int A = 0; A < 4; ++A) {
-#pragma unroll
-                for (int k = 0; k < RY; ++k) smem.phi[0][A][sw.rg + k * R0 + 2][sw.zl + 2] = sw.ring[2][A][k];
-                if (sw.halo_loader) smem.phi[0][A][sw.hrow][sw.hcol] = h0[A];
-            }
-        }
-        __syncthreads();
-        for (int st = 0; st < nst; ++st) sw.step(jstart + st, st & 1);
     }
 
     // block reduction of the partial sums (fixed order)
-    double vals[7] = {sw.pe2, sw.pe4, sw.pe0, sw.pb_sum, (double)sw.pf2, sw.pp, sw.pe6};
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         double v = vals[i];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_xor(v, off);
-            v = (i == 4) ? fmax(v, o) : v + o;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double w = __shfl_xor(v, o);
+            v = (i == P_F2) ? fmax(v, w) : v + w;
         }
         vals[i] = v;
     }
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 7; ++i) smem.red[wave][i] = vals[i];
+        for (int i = 0; i < 7; ++i) sm.red[wave][i] = vals[i];
     }
     __syncthreads();
     if (tid == 0) {
         double sum[7] = {0, 0, 0, 0, 0, 0, 0};
-        for (int wv = 0; wv < NW; ++wv) {
-            for (int i = 0; i < 7; ++i) sum[i] = (i == 4) ? fmax(sum[i], smem.red[wv][i]) : sum[i] + smem.red[wv][i];
-        }
-        double* out = a.partials + (size_t)b * NPART;
-        for (int i = 0; i < 7; ++i) out[i] = sum[i];
+        for (int wv = 0; wv < G::NWI; ++wv)
+            for (int i = 0; i < 7; ++i) sum[i] = (i == P_F2) ? fmax(sum[i], sm.red[wv][i]) : sum[i] + sm.red[wv][i];
+        double* o = a.partials + (size_t)b * NPART;
+        for (int i = 0; i < 7; ++i) o[i] = sum[i];
     }
 }
 
 // Blocks are dispatched round-robin over the eight XCDs (block i to XCD i % 8).
-// The logical index gives each XCD a contiguous run: neighbouring tiles of one
-// slab, which march through the same planes and share halo rows in one L2.
+// The logical index gives each XCD a contiguous run of the work: neighbouring
+// tiles of one slab, which march through the same planes and share halo rows
+// in one L2.
 __device__ __forceinline__ int xcd_logical_block(int i, int n)
 {
     const int xcd = i % 8, q8 = n / 8, r8 = n % 8;
     return xcd * q8 + min(xcd, r8) + i / 8;
 }
 
-template <typename T, int NW, int LW, int RY, int MODE, int EXT>
-__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+template <typename T, class G, int MODE, int EXT>
+__global__ __launch_bounds__(G::THREADS) void sweep_kernel(SweepArgs a)
 {
-    __shared__ typename Sweeper<T, NW, LW, RY, MODE, false, EXT>::Smem smem;
+    __shared__ SweepSmem<T, G> smem;
     const int nb = gridDim.x;
-    sweep_block<T, NW, LW, RY, MODE, false, EXT>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
+    sweep_block<T, G, MODE, false, EXT>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
 }
 
 // Many fields in one launch: block i (after the XCD remap) belongs to field
 // job_of_block[i] and is its block (i - first_block[job]); every field's blocks
 // and partial sums are exactly those of a launch of that field alone.
-template <typename T, int NW, int LW, int RY, int EXT>
-__global__ __launch_bounds__(NW * 64) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
-                                                              const int* __restrict__ job_of_block,
-                                                              const int* __restrict__ first_block,
-                                                              const int* __restrict__ blocks_of_job)
+template <typename T, class G, int EXT>
+__global__ __launch_bounds__(G::THREADS) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
+                                                                 const int* __restrict__ job_of_block,
+                                                                 const int* __restrict__ first_block,
+                                                                 const int* __restrict__ blocks_of_job)
 {
-    __shared__ typename Sweeper<T, NW, LW, RY, MODE_STEP, true, EXT>::Smem smem;
+    __shared__ SweepSmem<T, G> smem;
     const int i = xcd_logical_block(blockIdx.x, gridDim.x);
     const int j = job_of_block[i];
     const SweepArgs a = jobs[j];
-    sweep_block<T, NW, LW, RY, MODE_STEP, true, EXT>(a, i - first_block[j], blocks_of_job[j], smem);
+    sweep_block<T, G, MODE_STEP, true, EXT>(a, i - first_block[j], blocks_of_job[j], smem);
 }
 
 }  // namespace skyr
