@@ -288,16 +288,16 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
  * is taken on the first call on a device, with that device current, and the
  * array is held until the process ends).  The call allocates nothing and runs
  * the same kernels as skyr_anf_step, so its results are the same bit for bit.
- * A lattice whose flow needs more workspace than the array holds (the control
- * block, 512 bytes of observables and 64 bytes per sweep block: room for 1012
- * blocks, which every exact-gradient flow fits; the printed form on lattices
- * of more than about 1000 (y, z) tiles of 16 x 32 sites does not) gives
- * SKYR_E_INVAL before any device work.  Every call on one
+ * A flow whose sweep needs more workspace than the array holds (the control
+ * block, 512 bytes of observables and 64 bytes per sweep block: room for 4084
+ * blocks, which the default tiles of every lattice fit; a tile setting with
+ * many short slabs on a large lattice may not) gives SKYR_E_INVAL before any
+ * device work.  Every call on one
  * device shares that device's array and leaves its last contents there (each
  * call initialises what it reads): calls that overlap in time on one device,
  * from any stream or thread, race and give undefined results.  Synchronises
  * `stream`. */
-#define SKYR_NOALLOC_SCRATCH_BYTES (1u << 16)
+#define SKYR_NOALLOC_SCRATCH_BYTES (1u << 18)
 SKYR_API skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel,
                                            skyr_anf_state* st, int64_t nsteps, void* stream);

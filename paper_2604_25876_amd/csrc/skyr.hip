@@ -42,9 +42,9 @@ static skyr_status fail(skyr_status s, const std::string& msg)
 // ------------------------------------------------------------ tile choice
 // A tile shape is (interior waves, halo waves, halo positions per halo lane,
 // output columns); a tile has interior waves x 64 / columns rows.  A few shapes
-// are compiled per precision.  A field's work, one unit per (tile, plane),
-// is ordered slab by slab (slabs of `xchunk` planes along x) and split evenly
-// over the launch's blocks, one round of the chip for large lattices.  The
+// are compiled per precision.  x is cut into slabs of `xchunk` planes; a launch
+// has one block per (slab, tile) item, so that the blocks of neighbouring tiles
+// march through the same planes together and share their halo lines in L2.  The
 // choice for a (lattice, precision) pair is a process-wide setting
 // (skyr_set_tile / skyr_autotune).
 struct Shape {
@@ -56,18 +56,17 @@ struct Shape {
 };
 
 #ifndef SKYR_SHAPES_F64
-#define SKYR_SHAPES_F64(X) X(6, 2, 2, 32, 1) X(6, 2, 2, 16, 1)
+#define SKYR_SHAPES_F64(X) X(4, 4, 1, 16, 1) X(4, 4, 1, 32, 1) X(6, 2, 2, 32, 1)
 #endif
 #ifndef SKYR_SHAPES_F32
-#define SKYR_SHAPES_F32(X) X(12, 4, 1, 32, 1) X(14, 2, 2, 32, 1) X(6, 2, 2, 32, 2)
+#define SKYR_SHAPES_F32(X) X(8, 4, 1, 32, 1) X(6, 2, 2, 32, 2) X(12, 4, 1, 32, 1)
 #endif
 #define SKYR_SHAPE_ENTRY(a, b, c, d, e) Shape{a, b, c, d, e},
 static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
 static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
-constexpr int kMinChunk = 16;   // shortest slab a tile setting may name (planes)
-constexpr int kMaxSlabs = 8;    // the autotuner tries 1 .. kMaxSlabs slabs
-constexpr int kCUs = 256;       // compute units of the device the launches are sized for
-constexpr int kMinPlanes = 32;  // planes of work per block at least, where the lattice allows
+constexpr int kMinChunk = 16;  // shortest slab (planes)
+constexpr int kMaxSlabs = 8;   // the default and the autotuner use 1 .. kMaxSlabs slabs
+constexpr int kCUs = 256;      // compute units of the device the launches are sized for
 
 static int shape_count(skyr_precision prec)
 {
@@ -81,8 +80,7 @@ struct Launch {
     Shape shape;
     int xchunk;  // planes per slab
     int tiles_z, tiles_y, zstart, slabs;
-    int nblocks;
-    int blocks() const { return nblocks; }
+    int blocks() const { return tiles_z * tiles_y * slabs; }
     int threads() const { return shape.threads(); }
 };
 
@@ -97,7 +95,8 @@ static std::mutex g_tile_mu;
 static std::map<TileKey, std::pair<int, int>> g_tiles;  // (variant, planes per slab)
 
 // Tiles of the (y, z) plane: rows from y = 2; columns from z = 0 (so that tile rows
-// start on 128-byte lines) unless starting at z = 2 saves a tile.
+// start on 128-byte lines when the row length allows) unless starting at z = 2 saves a
+// tile.
 static void tile_grid(const skyr_lattice* lat, const Shape& sh, int& tiles_y, int& tiles_z, int& zstart)
 {
     const int iy = lat->n[1] - 4, n2 = lat->n[2];
@@ -106,14 +105,6 @@ static void tile_grid(const skyr_lattice* lat, const Shape& sh, int& tiles_y, in
     const int inner = (n2 - 4 + sh.oz() - 1) / sh.oz();
     zstart = aligned <= inner ? 0 : 2;
     tiles_z = aligned <= inner ? aligned : inner;
-}
-
-// blocks of a launch: one round of the chip, fewer when that would leave a block less
-// than kMinPlanes planes of work
-static int plan_blocks(long long units, const Shape& sh)
-{
-    const long long round = (long long)kCUs * sh.per_cu;
-    return (int)std::max<long long>(1, std::min(round, units / kMinPlanes));
 }
 
 static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int variant, int xchunk)
@@ -125,51 +116,55 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
     tile_grid(lat, L.shape, L.tiles_y, L.tiles_z, L.zstart);
     const int nx = lat->n[0] - 4;
     L.slabs = (nx + xchunk - 1) / xchunk;
-    L.nblocks = plan_blocks((long long)L.tiles_y * L.tiles_z * nx, L.shape);
     return L;
 }
 
-// Relative cost of one output site of a tile for each compiled shape, in the order of
-// the shape lists (sweep time per tile site at 256^3).
-static const double kShapeCostF64[] = {1.0, 1.0};
-static const double kShapeCostF32[] = {1.0, 1.07, 1.08};
+// Relative time of one output site and plane of an item, in a full round of the chip, for
+// each compiled shape in the order of the shape lists (measured at 256^3; a shape that
+// puts two blocks on a CU takes about twice as long per item).
+static const double kShapeCostF64[] = {1.0, 1.02, 0.95};
+static const double kShapeCostF32[] = {1.0, 2.0, 0.9};
+// a launch of more than one round loses some of the lockstep between neighbouring tiles
+// and ends with a partly idle round
+constexpr double kMultiRoundCost = 1.15;
 static_assert(sizeof(kShapeCostF64) / sizeof(double) == sizeof(kShapesF64) / sizeof(Shape), "one cost per shape");
 static_assert(sizeof(kShapeCostF32) / sizeof(double) == sizeof(kShapesF32) / sizeof(Shape), "one cost per shape");
 
-// Tile shape of a lattice the autotuner has not seen: the one with the least cost of
-// its padded (y, z) tiling (the sites of all tiles, each priced by its shape), the
-// lowest shape on ties.
-static int default_variant(const skyr_lattice* lat, skyr_precision prec)
-{
-    int best_v = 0;
-    double best = INFINITY;
-    for (int v = 0; v < shape_count(prec); ++v) {
-        const Shape& sh = shape_of(prec, v);
-        int ty = 0, tz = 0, zs = 0;
-        tile_grid(lat, sh, ty, tz, zs);
-        const double c = (double)ty * tz * sh.oy() * sh.oz() * (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
-        if (c < best) {
-            best = c;
-            best_v = v;
-        }
-    }
-    return best_v;
-}
-
-// Slab length of a lattice the autotuner has not seen, for shape v: the even split
-// of x into about as many slabs as there are blocks per tile, so that a block's
-// work mostly stays within one tile of one slab (neighbouring blocks then march
-// through the same planes of neighbouring tiles).
-static int default_chunk(const skyr_lattice* lat, skyr_precision prec, int v)
+// Estimated sweep cost of shape v with the even split of x into `slabs` slabs: rounds of
+// the chip times the (padded) work of one item, the march's four extra planes included.
+static double plan_cost(const skyr_lattice* lat, skyr_precision prec, int v, int slabs)
 {
     const Shape& sh = shape_of(prec, v);
     int ty = 0, tz = 0, zs = 0;
     tile_grid(lat, sh, ty, tz, zs);
     const int nx = lat->n[0] - 4;
-    const int nb = plan_blocks((long long)ty * tz * nx, sh);
-    const int most = std::max(1, nx / kMinChunk);
-    const int slabs = std::max(1, std::min(most, (nb + ty * tz / 2) / std::max(1, ty * tz)));
-    return std::max(kMinChunk, (nx + slabs - 1) / slabs);
+    const int xc = (nx + slabs - 1) / slabs;
+    const long long items = (long long)ty * tz * ((nx + xc - 1) / xc);
+    const long long per_round = (long long)kCUs * sh.per_cu;
+    const long long rounds = (items + per_round - 1) / per_round;
+    return (double)rounds * (rounds > 1 ? kMultiRoundCost : 1.0) * sh.oy() * sh.oz() * (xc + 4) *
+           (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
+}
+
+// Tile shape and slab length of a lattice the autotuner has not seen: the pair of least
+// estimated cost over the compiled shapes and 1 .. kMaxSlabs slabs (of at least kMinChunk
+// planes), the fewer items on ties.
+static void default_tile(const skyr_lattice* lat, skyr_precision prec, int& v_out, int& xc_out)
+{
+    const int nx = lat->n[0] - 4;
+    const int most = std::max(1, std::min(kMaxSlabs, nx / kMinChunk));
+    double best = INFINITY;
+    v_out = 0;
+    xc_out = nx;
+    for (int v = 0; v < shape_count(prec); ++v)
+        for (int sl = 1; sl <= most; ++sl) {
+            const double c = plan_cost(lat, prec, v, sl);
+            if (c < best * (1.0 - 1e-9)) {
+                best = c;
+                v_out = v;
+                xc_out = std::max(1, (nx + sl - 1) / sl);
+            }
+        }
 }
 
 static Launch plan(const skyr_lattice* lat, skyr_precision prec)
@@ -183,10 +178,7 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
             xc = it->second.second;
         }
     }
-    if (xc == 0) {
-        v = default_variant(lat, prec);
-        xc = default_chunk(lat, prec, v);
-    }
+    if (xc == 0) default_tile(lat, prec, v, xc);
     return plan_with(lat, prec, v, xc);
 }
 
@@ -1261,7 +1253,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     for (int v = 0; v < shape_count(prec); ++v) {
         int prev = -1;
         for (int sl = 1; sl <= kMaxSlabs; ++sl) {
-            const int xc = std::max(kMinChunk, (nx + sl - 1) / sl);
+            const int xc = std::max(std::min(kMinChunk, nx), (nx + sl - 1) / sl);
             if (xc == prev) continue;
             prev = xc;
             cands.push_back({v, xc, INFINITY});
@@ -1311,7 +1303,8 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
         return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
     double best = INFINITY;
-    int bv = 0, bx = default_chunk(lat, prec, 0);
+    int bv = 0, bx = 0;
+    default_tile(lat, prec, bv, bx);
     for (const Cand& cd : cands)
         if (cd.us < best) {
             best = cd.us;

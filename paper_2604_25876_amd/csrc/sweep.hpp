@@ -26,9 +26,10 @@
 //   * y- and z-neighbours go through LDS: phi planes (with the frame of sites only the halo
 //     positions read, loaded by the halo lanes) and planes of Q_y and Q_z, each
 //     double-buffered by plane parity, so one block barrier per plane suffices;
-//   * a launch's blocks share the (tile, plane) work of a field evenly: the work is
-//     ordered slab by slab, tile by tile, plane by plane, and every block takes one
-//     contiguous run of it (one or two marches).
+//   * x is cut into slabs; a launch has one block per (slab, tile) item, so that the
+//     blocks of neighbouring tiles march through the same planes together and read the
+//     phi lines of their shared halo from L2 once; the velocity read and the outputs are
+//     streamed past L2 (non-temporal) so that they do not displace those lines.
 // Stencils are evaluated in the scaled form 8 (f[+1] - f[-1]) - (f[+2] - f[-2]) =
 // 12 h D f (and 16 (...) - (...) = 12 h^2 L f); the constant factors are folded into
 // the weights of the final sums.  Energy, charge and force sums are accumulated in
@@ -138,6 +139,17 @@ template <typename T> __device__ __forceinline__ T ldb(gptr<const T> base, unsig
 {
     return *(gptr<const T>)((SKYR_GLOBAL const char*)base + off);
 }
+// Streamed accesses (the velocity read and the outputs written, used once per sweep):
+// non-temporal, so that they do not displace from L2 the phi lines that neighbouring
+// blocks read as their halo.
+template <typename T> __device__ __forceinline__ T ldb_nt(gptr<const T> base, unsigned off)
+{
+    return __builtin_nontemporal_load((gptr<const T>)((SKYR_GLOBAL const char*)base + off));
+}
+template <typename T> __device__ __forceinline__ void stb_nt(gptr<T> base, unsigned off, T v)
+{
+    __builtin_nontemporal_store(v, (gptr<T>)((SKYR_GLOBAL char*)base + off));
+}
 template <typename T> __device__ __forceinline__ void stb(gptr<T> base, unsigned off, T v)
 {
     *(gptr<T>)((SKYR_GLOBAL char*)base + off) = v;
@@ -225,6 +237,31 @@ __device__ __forceinline__ T det4_cofactors(const T* c0, const T* c1, const T* c
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// The four components of a site, contiguous in LDS: one 16-byte (float) or two
+// 16-byte (double) LDS accesses per site.
+template <typename T> struct alignas(4 * sizeof(T)) Site4 {
+    T v[4];
+};
+template <typename T> __device__ __forceinline__ void ld4(const Site4<T>* p, T (&o)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 t = *(const float4*)p;
+        o[0] = t.x, o[1] = t.y, o[2] = t.z, o[3] = t.w;
+    } else {
+        const double2 a = *(const double2*)p, b = *((const double2*)p + 1);
+        o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
+    }
+}
+template <typename T> __device__ __forceinline__ void st4(Site4<T>* p, const T (&i)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        *(float4*)p = make_float4(i[0], i[1], i[2], i[3]);
+    } else {
+        *(double2*)p = make_double2(i[0], i[1]);
+        *((double2*)p + 1) = make_double2(i[2], i[3]);
+    }
+}
+
 // Tile geometry of a shape: NWI interior waves of 64 / OZ rows of OZ lanes, NWH halo
 // waves whose lanes hold HPT halo positions each.
 template <int NWI_, int NWH_, int HPT_, int OZ_> struct Geo {
@@ -249,8 +286,8 @@ template <int NWI_, int NWH_, int HPT_, int OZ_> struct Geo {
 };
 
 template <typename T, class G> struct SweepSmem {
-    T phi[2][4][G::PPLANE];     // [plane parity][component]
-    T q[2][2][4][G::QPLANE];    // [plane parity][0: Q_y, 1: Q_z][component]
+    Site4<T> phi[2][G::PPLANE];     // [plane parity][site]
+    Site4<T> q[2][2][G::QPLANE];    // [plane parity][0: Q_y, 1: Q_z][site]
     double red[G::NW][NPART];
 };
 
@@ -303,33 +340,25 @@ template <typename T> struct SweepConst {
     }
 };
 
-// One contiguous run of a field's work: output planes [xa, xe) of tile (ty, tz).
+// One item of a field's work: output planes [xa, xe) of tile (ty, tz).
 struct Segment {
     int ty, tz, xa, xe;
 };
 
-// The work of a field is ordered slab by slab (slabs of xchunk planes along x), tile by
-// tile within a slab, plane by plane within a tile; unit u is one plane of one tile.
-// Takes the segment that starts at unit u and ends at u1 or at the end of its (slab,
-// tile), whichever comes first, and advances u past it.
-__device__ __forceinline__ bool next_segment(long long& u, long long u1, int tiles, int tiles_z, int nx, int xchunk,
-                                             Segment& s)
+// The work of a field is cut into items, one (slab, tile) pair each (slabs of xchunk
+// planes along x), numbered slab by slab and tile by tile within a slab.  Logical block
+// b of nb takes items b, b + nb, ...; a launch normally has one block per item, so that
+// the blocks of neighbouring tiles march through the same planes at the same time and
+// the phi lines of their shared halo are read from L2 once.
+__device__ __forceinline__ Segment item_segment(int item, int tiles, int tiles_z, int nx, int xchunk)
 {
-    if (u >= u1) return false;
-    const long long per_slab = (long long)tiles * xchunk;
-    const int slab = (int)(u / per_slab);
-    const int x0 = slab * xchunk;
-    const int len = min(nx, x0 + xchunk) - x0;
-    const long long r = u - (long long)tiles * x0;
-    const int tile = (int)(r / len);
-    const int xo = (int)(r - (long long)tile * len);
-    const long long e = min(u1, u - xo + len);
+    const int slab = item / tiles, tile = item - slab * tiles;
+    Segment s;
     s.ty = tile / tiles_z;
     s.tz = tile - s.ty * tiles_z;
-    s.xa = 2 + x0 + xo;
-    s.xe = s.xa + (int)(e - u);
-    u = e;
-    return true;
+    s.xa = 2 + slab * xchunk;
+    s.xe = 2 + min(nx, (slab + 1) * xchunk);
+    return s;
 }
 
 // A march over output planes [xa, xe) takes (xe - xa) + 4 steps (flux planes xa-2 ..
@@ -379,6 +408,7 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
     T ring[5][4];  // phi of planes j-2 .. j+2 (slot = plane offset + 2 + step, mod 5)
     T acc[5][4];   // scaled gradient accumulators of planes j-2 .. j+2 (same slots)
     T nxt[4];      // prefetched phi(j+3)
+    T vnxt[4];     // prefetched velocity of plane j-1
 
     double pe2 = 0.0, pe4 = 0.0, pe0 = 0.0, pe6 = 0.0, pb_sum = 0.0;
     double pp = 0.0;  // scaled power F^ . v of the incoming velocity
@@ -430,26 +460,28 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
     }
 
     template <int SM2, int SM1, int S0, int SP1, int SP2>
-    __device__ __forceinline__ void boundary_terms(int j, const T* P)
+    __device__ __forceinline__ void boundary_terms(int j, const Site4<T>* P)
     {
         if (!out) return;
         const int n0 = cm.n0;
+        const T* pa0 = P[pidx].v;
+        constexpr int W = 4 * G::PW;  // one row of sites, in elements
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-            const T* pa = P + A * G::PPLANE + pidx;
+            const T* pa = pa0 + A;
             T o1 = T(0), o2 = T(0);  // outside first / second neighbours
             if (j + 1 > n0 - 3) o1 += ring[SP1][A];
             if (j - 1 < 2) o1 += ring[SM1][A];
             if (j + 2 > n0 - 3) o2 += ring[SP2][A];
             if (j - 2 < 2) o2 += ring[SM2][A];
-            if (outside & O_YP1) o1 += pa[G::PW];
-            if (outside & O_YM1) o1 += pa[-G::PW];
-            if (outside & O_ZP1) o1 += pa[1];
-            if (outside & O_ZM1) o1 += pa[-1];
-            if (outside & O_YP2) o2 += pa[2 * G::PW];
-            if (outside & O_YM2) o2 += pa[-2 * G::PW];
-            if (outside & O_ZP2) o2 += pa[2];
-            if (outside & O_ZM2) o2 += pa[-2];
+            if (outside & O_YP1) o1 += pa[W];
+            if (outside & O_YM1) o1 += pa[-W];
+            if (outside & O_ZP1) o1 += pa[4];
+            if (outside & O_ZM1) o1 += pa[-4];
+            if (outside & O_YP2) o2 += pa[2 * W];
+            if (outside & O_YM2) o2 += pa[-2 * W];
+            if (outside & O_ZP2) o2 += pa[8];
+            if (outside & O_ZM2) o2 += pa[-8];
             // + 1/2 the outside terms of Lap phi: 12 h^2 x that is 8 o1 - o2 / 2, and L^ enters
             // the scaled gradient with weight lapw < 0 and the opposite sign
             acc[S0][A] = fmaT(k.lapw, fmaT(T(0.5), o2, T(-8) * o1), acc[S0][A]);
@@ -469,34 +501,48 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
             asm volatile("" : "+v"(ring[sl][0]), "+v"(ring[sl][1]), "+v"(ring[sl][2]), "+v"(ring[sl][3]));
         // stage phi(j+1) into the other phi buffer (its last reads, of phi(j-1), came before
         // the last barrier), then prefetch
-        {
-            T* Q = &sm.phi[qb][0][0];
+        st4(&sm.phi[qb][pidx], ring[SP1]);
+        // the velocity of output plane j-2 was prefetched one plane earlier; the velocity of
+        // plane j-1 is loaded now, before the prefetch of phi(j+3) (loads complete in order)
+        T vcur[4];
+        if constexpr (MODE == MODE_STEP) {
+            const unsigned vb = (unsigned)clampi(j - 1, 0, cm.n0 - 1) * cm.plane_b;
 #pragma unroll
-            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx] = ring[SP1][A];
+            for (int A = 0; A < 4; ++A) {
+                vcur[A] = vnxt[A];
+                vnxt[A] = ldb_nt((gptr<const T>)cm.vel[A], vb + off);
+            }
         }
 #pragma unroll
         for (int A = 0; A < 4; ++A) ring[SP2][A] = nxt[A];
         cm.load(off, j + 3, nxt);
-        T vcur[4];
         if constexpr (MODE == MODE_STEP) {
-            const unsigned vb = (unsigned)clampi(j - 2, 0, cm.n0 - 1) * cm.plane_b;
+            if (cm.redo) {  // a redo sweep starts from zero velocity
 #pragma unroll
-            for (int A = 0; A < 4; ++A)
-                vcur[A] = cm.redo ? T(0) : ldb((gptr<const T>)cm.vel[A], vb + off);
+                for (int A = 0; A < 4; ++A) vcur[A] = T(0);
+            }
         }
         const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
         const bool j_out = (j >= xa) && (j < xe);
 
-        const T* P = &sm.phi[pb][0][0];
+        const Site4<T>* P = sm.phi[pb];
         T c[4], ax[4], ay[4], az[4];
+        T Ym2[4], Ym1[4], Yp1[4], Yp2[4], Zm2[4], Zm1[4], Zp1[4], Zp2[4];
+        ld4(P + pidx - 2 * G::PW, Ym2);
+        ld4(P + pidx - G::PW, Ym1);
+        ld4(P + pidx + G::PW, Yp1);
+        ld4(P + pidx + 2 * G::PW, Yp2);
+        ld4(P + pidx - 2, Zm2);
+        ld4(P + pidx - 1, Zm1);
+        ld4(P + pidx + 1, Zp1);
+        ld4(P + pidx + 2, Zp2);
         T cl = T(0);
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-            const T* pa = P + A * G::PPLANE + pidx;
             const T cc = ring[S0][A];
             const T xm2 = ring[SM2][A], xm1 = ring[SM1][A], xp1 = ring[SP1][A], xp2 = ring[SP2][A];
-            const T ym2 = pa[-2 * G::PW], ym1 = pa[-G::PW], yp1 = pa[G::PW], yp2 = pa[2 * G::PW];
-            const T zm2 = pa[-2], zm1 = pa[-1], zp1 = pa[1], zp2 = pa[2];
+            const T ym2 = Ym2[A], ym1 = Ym1[A], yp1 = Yp1[A], yp2 = Yp2[A];
+            const T zm2 = Zm2[A], zm1 = Zm1[A], zp1 = Zp1[A], zp2 = Zp2[A];
             c[A] = cc;
             ax[A] = fmaT(T(8), xp1 - xm1, xm2 - xp2);
             ay[A] = fmaT(T(8), yp1 - ym1, ym2 - yp2);
@@ -555,10 +601,10 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
                 e6 = k.c6e * det * det;
             }
         }
+        st4(&sm.q[pb][0][qidx], qy);
+        st4(&sm.q[pb][1][qidx], qz);
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
-            sm.q[pb][0][A][qidx] = qy[A];
-            sm.q[pb][1][A][qidx] = qz[A];
             // x-divergence pushed to the accumulators of planes j-2 .. j+2
             acc[SM1][A] = fmaT(T(-8), qx[A], acc[SM1][A]);
             acc[SP1][A] = fmaT(T(8), qx[A], acc[SP1][A]);
@@ -582,12 +628,21 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
 
         // y- and z-divergence of the flux of plane j-1 (written before the last barrier)
         if (j - 1 >= xa && j - 1 < xe) {
+            const Site4<T>* fy = sm.q[qb][0] + qidx;
+            const Site4<T>* fz = sm.q[qb][1] + qidx;
+            T ym2[4], ym1[4], yp1[4], yp2[4], zm2[4], zm1[4], zp1[4], zp2[4];
+            ld4(fy - 2 * G::QW, ym2);
+            ld4(fy - G::QW, ym1);
+            ld4(fy + G::QW, yp1);
+            ld4(fy + 2 * G::QW, yp2);
+            ld4(fz - 2, zm2);
+            ld4(fz - 1, zm1);
+            ld4(fz + 1, zp1);
+            ld4(fz + 2, zp2);
 #pragma unroll
             for (int A = 0; A < 4; ++A) {
-                const T* fy = &sm.q[qb][0][A][qidx];
-                const T* fz = &sm.q[qb][1][A][qidx];
-                const T t = (fy[-G::QW] - fy[G::QW]) + (fz[-1] - fz[1]);
-                const T u = (fy[2 * G::QW] - fy[-2 * G::QW]) + (fz[2] - fz[-2]);
+                const T t = (ym1[A] - yp1[A]) + (zm1[A] - zp1[A]);
+                const T u = (yp2[A] - ym2[A]) + (zp2[A] - zm2[A]);
                 acc[SM1][A] = fmaT(T(8), t, acc[SM1][A]) + u;
             }
         }
@@ -607,11 +662,11 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
             for (int A = 0; A < 4; ++A) f[A] = fmaT(gp, p[A], -g[A]);  // F^ = (g^.phi) phi - g^
             pf2 = fmax_nonneg(pf2, dot4(f, f));
             if constexpr (MODE == MODE_STEP) {
-                pp += (double)f[0] * vcur[0] + (double)f[1] * vcur[1] + (double)f[2] * vcur[2] + (double)f[3] * vcur[3];
+                pp += (double)dot4(f, vcur);  // the product in the field precision, the sum in double
                 if (cm.restore) {
 #pragma unroll
                     for (int A = 0; A < 4; ++A)
-                        stb(cm.vel[A], base, cm.restore == RESTORE_ZERO ? T(0) : fmaT(-k.dtK, f[A], vcur[A]));
+                        stb_nt(cm.vel[A], base, cm.restore == RESTORE_ZERO ? T(0) : fmaT(-k.dtK, f[A], vcur[A]));
                 } else {
                     T v[4], q[4], pn[4];
 #pragma unroll
@@ -637,14 +692,14 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
                     }
 #pragma unroll
                     for (int A = 0; A < 4; ++A) {
-                        stb(cm.pout[A], base, pn[A]);
-                        stb(cm.vel[A], base, v[A]);
+                        stb_nt(cm.pout[A], base, pn[A]);
+                        stb_nt(cm.vel[A], base, v[A]);
                     }
                 }
             } else {
                 if (cm.has_grad) {
 #pragma unroll
-                    for (int A = 0; A < 4; ++A) stb(cm.gout[A], base, (cm.projected ? -f[A] : g[A]) * k.invK);
+                    for (int A = 0; A < 4; ++A) stb_nt(cm.gout[A], base, (cm.projected ? -f[A] : g[A]) * k.invK);
                 }
             }
         }
@@ -669,9 +724,12 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
         cm.load(off, js, ring[2]);
         cm.load(off, js + 1, ring[3]);
         cm.load(off, js + 2, nxt);
-        T* Q = &sm.phi[0][0][0];
+        if constexpr (MODE == MODE_STEP) {
+            const unsigned vb = (unsigned)clampi(js - 2, 0, cm.n0 - 1) * cm.plane_b;
 #pragma unroll
-        for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx] = ring[2][A];
+            for (int A = 0; A < 4; ++A) vnxt[A] = ldb_nt((gptr<const T>)cm.vel[A], vb + off);
+        }
+        st4(&sm.phi[0][pidx], ring[2]);
         __syncthreads();
         const int nst = (xe - xa) + 4 + lead;
         for (int st = 0; st < nst; st += 5) {
@@ -735,7 +793,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
             hc[i] = cc;
             is_y[i] = yh;
             pidx[i] = (r + 4) * G::PW + cc + 4;
-            qidx[i] = (yh ? 0 : 4 * G::QPLANE) + (r + 2) * G::QW + cc + 2;
+            qidx[i] = (yh ? 0 : G::QPLANE) + (r + 2) * G::QW + cc + 2;
         }
 #pragma unroll
         for (int i = 0; i < FPT; ++i) {
@@ -781,7 +839,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
     {
         constexpr int SM2 = U % 5, SM1 = (U + 1) % 5, S0 = (U + 2) % 5, SP1 = (U + 3) % 5, SP2 = (U + 4) % 5;
         const int qb = pb ^ 1;
-        T* Pn = &sm.phi[qb][0][0];
+        Site4<T>* Pn = sm.phi[qb];
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             asm volatile("" : "+v"(pidx[i]), "+v"(qidx[i]), "+v"(off[i]));
@@ -789,10 +847,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
             for (int sl = 0; sl < 5; ++sl)
                 asm volatile("" : "+v"(ring[i][sl][0]), "+v"(ring[i][sl][1]), "+v"(ring[i][sl][2]), "+v"(ring[i][sl][3]));
             // stage phi(j+1) into the other phi buffer, then prefetch
-            if (active[i]) {
-#pragma unroll
-                for (int A = 0; A < 4; ++A) Pn[A * G::PPLANE + pidx[i]] = ring[i][SP1][A];
-            }
+            if (active[i]) st4(Pn + pidx[i], ring[i][SP1]);
 #pragma unroll
             for (int A = 0; A < 4; ++A) ring[i][SP2][A] = nxt[i][A];
             if (active[i]) cm.load(off[i], j + 3, nxt[i]);
@@ -802,25 +857,33 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
         for (int i = 0; i < FPT; ++i) {
             asm volatile("" : "+v"(fidx[i]), "+v"(foff[i]));
             if (floader[i]) {
-#pragma unroll
-                for (int A = 0; A < 4; ++A) Pn[A * G::PPLANE + fidx[i]] = fnxt[i][A];
+                st4(Pn + fidx[i], fnxt[i]);
                 cm.load(foff[i], j + 2, fnxt[i]);
             }
         }
         const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
-        const T* P = &sm.phi[pb][0][0];
+        const Site4<T>* P = sm.phi[pb];
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             if (!active[i]) continue;
             T c[4], ax[4], ap[4], aq[4];
             const bool yh = is_y[i];
+            T Ym2[4], Ym1[4], Yp1[4], Yp2[4], Zm2[4], Zm1[4], Zp1[4], Zp2[4];
+            const Site4<T>* pa = P + pidx[i];
+            ld4(pa - 2 * G::PW, Ym2);
+            ld4(pa - G::PW, Ym1);
+            ld4(pa + G::PW, Yp1);
+            ld4(pa + 2 * G::PW, Yp2);
+            ld4(pa - 2, Zm2);
+            ld4(pa - 1, Zm1);
+            ld4(pa + 1, Zp1);
+            ld4(pa + 2, Zp2);
 #pragma unroll
             for (int A = 0; A < 4; ++A) {
-                const T* pa = P + A * G::PPLANE + pidx[i];
                 c[A] = ring[i][S0][A];
                 ax[A] = fmaT(T(8), ring[i][SP1][A] - ring[i][SM1][A], ring[i][SM2][A] - ring[i][SP2][A]);
-                const T ay = fmaT(T(8), pa[G::PW] - pa[-G::PW], pa[-2 * G::PW] - pa[2 * G::PW]);
-                const T az = fmaT(T(8), pa[1] - pa[-1], pa[-2] - pa[2]);
+                const T ay = fmaT(T(8), Yp1[A] - Ym1[A], Ym2[A] - Yp2[A]);
+                const T az = fmaT(T(8), Zp1[A] - Zm1[A], Zm2[A] - Zp2[A]);
                 ap[A] = yh ? ay : az;
                 aq[A] = yh ? az : ay;
             }
@@ -846,9 +909,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
                     for (int A = 0; A < 4; ++A) qp[A] = fmaT(dv, yh ? C2[A] : C3[A], qp[A]);
                 }
             }
-            T* Q = &sm.q[pb][0][0][0];
-#pragma unroll
-            for (int A = 0; A < 4; ++A) Q[qidx[i] + A * G::QPLANE] = qp[A];
+            st4(sm.q[pb][0] + qidx[i], qp);
         }
         __syncthreads();
     }
@@ -866,12 +927,11 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
             cm.load(off[i], js + 1, ring[i][3]);
             cm.load(off[i], js + 2, nxt[i]);
         }
-        T* Q = &sm.phi[0][0][0];
+        Site4<T>* Q = sm.phi[0];
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             if (!active[i]) continue;
-#pragma unroll
-            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + pidx[i]] = ring[i][2][A];
+            st4(Q + pidx[i], ring[i][2]);
         }
 #pragma unroll
         for (int i = 0; i < FPT; ++i) {
@@ -879,8 +939,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
             T f0[4];
             cm.load(foff[i], js, f0);
             cm.load(foff[i], js + 1, fnxt[i]);
-#pragma unroll
-            for (int A = 0; A < 4; ++A) Q[A * G::PPLANE + fidx[i]] = f0[A];
+            st4(Q + fidx[i], f0);
         }
         __syncthreads();
         const int nst = (xe - xa) + 4 + lead;
@@ -895,26 +954,30 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
     }
 };
 
-// One block's share of one field: logical block b of nb blocks, which takes units
-// [W b / nb, W (b+1) / nb) of the field's W = tiles x (n0 - 4) units of work.  Used by
-// the single-field and the batched kernels (FROM_TABLE: the arguments were read from
-// the batch's job table).
+// One block's share of one field: logical block b of nb blocks, which takes the items b,
+// b + nb, ... of the field's work.  Used by the single-field and the batched kernels
+// (FROM_TABLE: the arguments were read from the batch's job table).
 template <typename T, class G, int MODE, bool FROM_TABLE = false, int EXT = EXT_NONE>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, SweepSmem<T, G>& sm)
 {
-    const Ctl* ctl = a.ctl;
     SweepCommon<T, FROM_TABLE> cm;
     int cur = 0;
     cm.redo = false;
     cm.renorm64 = false;
     cm.restore = RESTORE_NONE;
     if constexpr (MODE == MODE_STEP) {
-        cm.restore = ctl->restore;
-        if (ctl->done && !cm.restore) return;  // uniform: the flow has stopped
-        cur = ctl->cur;
-        cm.redo = ctl->redo != 0;
-        const int kr = ctl->renorm64_every;
-        cm.renorm64 = (kr > 0) && (((ctl->steps + 1) % kr) == 0);
+        // the control block is the same for the whole block: its fields are read as uniform values
+        const gptr<const Ctl> ctl = (gptr<const Ctl>)uniform_ptr(a.ctl);
+        const auto rd = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+        cm.restore = rd(ctl->restore);
+        if (rd(ctl->done) && !cm.restore) return;  // the flow has stopped
+        cur = rd(ctl->cur);
+        cm.redo = rd(ctl->redo) != 0;
+        const int kr = rd(ctl->renorm64_every);
+        const long long st = ctl->steps;
+        const int st_lo = rd((int)(unsigned)(st & 0xffffffff)), st_hi = rd((int)(unsigned)(st >> 32));
+        const long long steps = (long long)(((unsigned long long)(unsigned)st_hi << 32) | (unsigned)st_lo);
+        cm.renorm64 = (kr > 0) && (((steps + 1) % kr) == 0);
     }
     cm.n0 = a.n0;
     cm.n1 = a.n1;
@@ -926,13 +989,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
         T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);
         T* pvel = (T*)a.vel;
         T* pgrad = (T*)a.grad;
-        if constexpr (FROM_TABLE) {
-            // read from the job table: the same for the whole block, kept in SGPRs
-            pin = uniform_ptr(pin);
-            pout = uniform_ptr(pout);
-            pvel = uniform_ptr(pvel);
-        }
-        if constexpr (!FROM_TABLE) pgrad = uniform_ptr(pgrad);
+        // the same for the whole block (kernel arguments or the job table): kept in SGPRs
+        pin = uniform_ptr(pin);
+        pout = uniform_ptr(pout);
+        pvel = uniform_ptr(pvel);
+        pgrad = uniform_ptr(pgrad);
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
             cm.pin[A] = (gptr<const T>)(pin + A * N3);
@@ -952,16 +1013,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tiles = a.tiles_y * a.tiles_z;
     const int nx = a.n0 - 4;
-    const long long W = (long long)tiles * nx;
-    const long long u0 = W * b / nb, u1 = W * (b + 1) / nb;
+    const int items = tiles * ((nx + a.xchunk - 1) / a.xchunk);
 
     double vals[7] = {0, 0, 0, 0, 0, 0, 0};
     if (wave < G::NWI) {
         Interior<T, G, MODE, FROM_TABLE, EXT> it(sm, k, cm, tid);
-        long long u = u0;
-        Segment s;
-        while (next_segment(u, u1, tiles, a.tiles_z, nx, a.xchunk, s)) {
-            it.setup(s, a.zstart);
+        for (int item = b; item < items; item += nb) {
+            it.setup(item_segment(item, tiles, a.tiles_z, nx, a.xchunk), a.zstart);
             it.march();
         }
         vals[0] = it.pe2;
@@ -973,10 +1031,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
         vals[6] = it.pe6;
     } else {
         Halo<T, G, FROM_TABLE, EXT> hl(sm, k, cm, tid - G::NWI * 64);
-        long long u = u0;
-        Segment s;
-        while (next_segment(u, u1, tiles, a.tiles_z, nx, a.xchunk, s)) {
-            hl.setup(s, a.zstart);
+        for (int item = b; item < items; item += nb) {
+            hl.setup(item_segment(item, tiles, a.tiles_z, nx, a.xchunk), a.zstart);
             hl.march();
         }
     }

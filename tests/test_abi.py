@@ -120,18 +120,18 @@ def test_invalid_arguments_rejected_without_device_work():
 
 def test_noalloc_flow_rejects_a_lattice_beyond_its_scratch():
     """skyr_anf_step_noalloc refuses, before any device work, a flow whose sweep
-    has more blocks than its fixed scratch holds partial sums for (here the
-    printed-form sweep on 812^3: 51 x 26 tiles of 16 x 32 sites, one slab, 1326
-    blocks against room for 1012), and checks its other arguments like
+    has more blocks than its fixed scratch holds partial sums for (here 800^3 in
+    single precision with 16-plane slabs: 50 x 25 tiles x 50 slabs, 62,500
+    blocks against room for 4084), and checks its other arguments like
     skyr_anf_step."""
     L = skyr.lib()
-    lat = skyr.Lattice.cube(812, 0.1)
+    lat = skyr.Lattice.cube(800, 0.1)
+    skyr.set_tile(lat, skyr.F32_BULK, 0, 16)
     st = skyr.anf_state()
     model, flow = skyr.Model(1.0), skyr.Flow(0.01, 0.0, 10, 0, 0)
-    printed = skyr.Model(1.0, 0.0, 0.0, 0.0, 0.0, skyr.FORM_PRINTED)
     a, b, c = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
-    rc = L.skyr_anf_step_noalloc(ctypes.byref(lat), skyr.F32_BULK, ctypes.byref(printed), ctypes.byref(flow), a, b,
-                                 c, ctypes.byref(st), 1, None)
+    rc = L.skyr_anf_step_noalloc(ctypes.byref(lat), skyr.F32_BULK, ctypes.byref(model), ctypes.byref(flow), a, b, c,
+                                 ctypes.byref(st), 1, None)
     assert rc == skyr.E_INVAL and "scratch" in L.skyr_last_error().decode()
     small = skyr.Lattice.cube(40, 0.2)
     bad_flow = skyr.Flow(0.0, 0.0, 10, 0, 0)
@@ -223,34 +223,30 @@ def test_orientation_zyz_is_the_product_of_axis_rotations():
 
 
 def _default_tile(n, prec):
-    """The default tile rule, restated: the compiled shape whose padded (y, z)
-    tiling costs least (sites of all tiles times a per-shape price, the lowest
-    shape on ties; z tiles start at z = 0 unless starting at z = 2 saves one),
-    then about as many slabs as the launch has blocks per tile, where the
-    launch has one round of blocks (256 CUs times the blocks a CU holds) or
-    fewer, so that each block gets at least 32 planes of work."""
+    """The default tile rule, restated: over the compiled shapes and the even
+    splits of x into 1 .. 8 slabs (of at least 16 planes), the pair of least
+    estimated cost = rounds of the chip (one block per (slab, tile) item, 256
+    CUs times the blocks a CU holds), times 1.15 beyond one round, x rows x
+    columns x (slab planes + 4) x a per-shape price, the first on ties; z tiles
+    start at z = 0 unless starting at z = 2 saves one."""
     import math
-    # (interior waves, halo waves, halo positions per lane, columns, blocks per CU), price
-    shapes = {skyr.F64: [((6, 2, 2, 32, 1), 1.0), ((6, 2, 2, 16, 1), 1.0)],
-              skyr.F32_BULK: [((12, 4, 1, 32, 1), 1.0), ((14, 2, 2, 32, 1), 1.07), ((6, 2, 2, 32, 2), 1.08)]}[prec]
+    # (interior waves, columns, blocks per CU), price
+    shapes = {skyr.F64: [((4, 16, 1), 1.0), ((4, 32, 1), 1.02), ((6, 32, 1), 0.95)],
+              skyr.F32_BULK: [((8, 32, 1), 1.0), ((6, 32, 2), 2.0), ((12, 32, 1), 0.9)]}[prec]
     i = n - 4
-
-    def grid(nwi, oz):
+    best = None
+    for v, ((nwi, oz, per_cu), price) in enumerate(shapes):
         oy = nwi * 64 // oz
         ty = math.ceil(i / oy)
         tz = min((n - 3) // oz + 1, math.ceil(i / oz))
-        return oy, ty, tz
-
-    best = None
-    for v, ((nwi, nwh, hpt, oz, per_cu), price) in enumerate(shapes):
-        oy, ty, tz = grid(nwi, oz)
-        cost = ty * tz * oy * oz * price
-        if best is None or cost < best[0]:
-            best = (cost, v, ty * tz, per_cu)
-    _, v, tiles, per_cu = best
-    nb = max(1, min(256 * per_cu, tiles * i // 32))
-    slabs = max(1, min(max(1, i // 16), (nb + tiles // 2) // tiles))
-    return v, max(16, math.ceil(i / slabs))
+        for sl in range(1, max(1, min(8, i // 16)) + 1):
+            xc = math.ceil(i / sl)
+            items = ty * tz * math.ceil(i / xc)
+            rounds = math.ceil(items / (256 * per_cu))
+            cost = rounds * (1.15 if rounds > 1 else 1.0) * oy * oz * (xc + 4) * price
+            if best is None or cost < best[0] * (1 - 1e-9):
+                best = (cost, v, xc)
+    return best[1], max(1, best[2])
 
 
 @pytest.mark.parametrize("n", [9, 24, 48, 66, 100, 118, 176, 182, 256, 400])

@@ -44,8 +44,9 @@ def _with_tile(skyr, lat, prec, v, xchunk, fn):
         skyr.set_tile(lat, prec, *saved)
 
 
-# the compiled shapes: FP64 (8, 32, 1), (8, 16, 1); FP32 (16, 32, 1), (8, 32, 2), (16, 64, 1)
-SHAPES = {0: 2, 1: 3}
+# the compiled shapes (threads, output rows, output columns): FP64 (512, 16, 16), (512, 8, 32),
+# (512, 12, 32); FP32 (768, 16, 32), (512, 12, 32), (1024, 24, 32)
+SHAPES = {0: 3, 1: 3}
 CASES = [(prec, v) for prec, n in SHAPES.items() for v in range(n)]
 
 
