@@ -302,6 +302,68 @@ SKYR_API skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precisi
                                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel,
                                            skyr_anf_state* st, int64_t nsteps, void* stream);
 
+/* ---- One block of a 3D block decomposition (the one-device share of a lattice that is
+ * split over devices; Sec. 3 stencils) ----
+ * The block owns the sites origin[d] .. origin[d] + extent[d] - 1 of the whole lattice
+ * `lattice` (frozen layers included) and stores each of its fields padded: extent[d] + 8
+ * sites per axis, in the field layout above, own site g at padded index g - origin + 4.
+ * The shell four sites deep around the own box holds neighbouring blocks' sites: the
+ * exact gradient at a site reads phi up to four sites away along the axes (the quartic
+ * flux needs phi within two sites, its divergence the flux within two), so one exchange
+ * of the shell per sweep is all a block needs from its neighbours.
+ * Shell buffer: the shell's sites in the row-major order of the padded box with the own
+ * box left out, component-major (4 x skyr_block_shell_sites elements of the field
+ * precision): the data the neighbouring blocks send.  Entries for sites outside the
+ * lattice are ignored; such shell sites are filled with the nearest lattice site, the
+ * value a sweep over the whole lattice reads there. */
+typedef struct {
+    skyr_lattice lattice; /* the whole lattice */
+    int32_t origin[3];    /* its site of the block's first own site, per axis */
+    int32_t extent[3];    /* own sites per axis, >= 1; origin + extent <= lattice.n */
+} skyr_block;
+
+/* Sites per component of a padded block field, and of its shell (0 on an invalid block;
+ * a padded block obeys the size limit of a lattice). */
+SKYR_API int64_t skyr_block_sites(const skyr_block* blk);
+SKYR_API int64_t skyr_block_shell_sites(const skyr_block* blk);
+
+/* Bytes of device workspace skyr_block_sweep needs (0 on invalid arguments); 256-byte
+ * aligned, not shared by calls that overlap in time. */
+SKYR_API size_t skyr_block_workspace_bytes(const skyr_block* blk, skyr_precision prec);
+
+/* The block's share of the sums of one sweep, over its own sites in I: added over all
+ * blocks (maximum for max_force) they are the sums of the whole lattice. */
+typedef struct {
+    double E;         /* energy (both modes)                                        */
+    double E2, E4, E0, E6; /* its parts (gradient mode; 0 in step mode)             */
+    double power;     /* h^3 sum F . v of the incoming velocity (step mode)          */
+    double max_force; /* max |F|                                                    */
+} skyr_block_sums;
+
+typedef enum { SKYR_BLOCK_GRADIENT = 0, SKYR_BLOCK_STEP = 1 } skyr_block_mode;
+
+/* One sweep over the block's own sites in the lattice's interior I:
+ *   1. the shell of phi is written from `shell` (as described above); the block's own
+ *      sites of phi are only read;
+ *   2. SKYR_BLOCK_GRADIENT: out = g, the exact gradient of E_h (skyr_energy_gradient's
+ *      values, bit for bit), or its tangential part g - (g.phi) phi when projected != 0;
+ *      SKYR_BLOCK_STEP: one kick-drift step of Sec. 3 from (phi, vel):
+ *      vel <- v + dt F, out <- (phi + dt vel) / |phi + dt vel|, with v = 0 when
+ *      redo != 0 (the restart after an arrest); renorm64 != 0 makes a SKYR_F32_BULK
+ *      step normalise in double, as skyr_anf_step does every renorm64_every steps (it is
+ *      ignored for SKYR_F64, which computes in double throughout).  The values are those
+ *      of the corresponding step of skyr_anf_step, bit for bit.  The flow's
+ *      decision (arrest, convergence) belongs to the caller, from every block's sums.
+ * out and vel are padded block fields written (and vel read) at the block's own sites
+ * in I only; the model must use the exact form.
+ *   sums   nullable host output; the call synchronises `stream` when it is non-null
+ *   work   device workspace of skyr_block_workspace_bytes(blk, prec) bytes
+ * A block with no site in I does nothing (sums zero). */
+SKYR_API skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const skyr_model* model,
+                                      int32_t mode, int32_t projected, double dt, int32_t redo, int32_t renorm64,
+                                      void* phi, const void* shell, void* out, void* vel, skyr_block_sums* sums,
+                                      void* work, void* stream);
+
 /* Energy parts, baryon number, virial and largest projected force of phi
  * (Sec. 2.1 eq. B0_components, Sec. 5.6 eq. Virial).  Synchronises `stream`. */
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,

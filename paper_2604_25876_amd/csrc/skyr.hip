@@ -351,7 +351,6 @@ __global__ void copy_frozen_kernel(const T* __restrict__ src, T* __restrict__ ds
 // Fixed-order reduction of the per-block partials: thread t sums blocks
 // t, t + 256, ... in order, then a fixed tree.
 // out = {E2, E4, E0, Bsum, maxF2, power, E6}.
-constexpr int NRED = 7;
 __device__ static void reduce_partials(const double* __restrict__ part, int nblocks, double out[NRED])
 {
     __shared__ double red[256][NRED];
@@ -393,10 +392,8 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
     }
 }
 
-// The flow's decision after the sweep over phi_k (Sec. 3): arrest when
-// E_k > E_{k-1} (energy rule) or when the power h^3 sum F_k . v_k < 0 (power
-// rule), re-running the sweep with v_k = 0; stop when max|F_k| < tol;
-// otherwise accept the update (swap buffers).
+// The separate finaliser of a sweep that does not take the decision itself (the printed
+// form): fixed-order reduction, then the flow's decision.
 __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
 {
     if (ctl->done) {  // uniform
@@ -406,59 +403,10 @@ __device__ static void finalize_flow(const double* __restrict__ part, Ctl* __res
     }
     double s[NRED];
     reduce_partials(part, ctl->nblocks, s);
-    if (threadIdx.x != 0) return;
-    // the flow sweep sums the whole energy density in slot 0 (slots 1, 2, 6 are zero)
-    const double E = ctl->h3 * s[P_E2];
-    const double r = sqrt(s[P_F2]);
-    ctl->sweeps += 1;
-    ctl->E = E;
-    ctl->P = ctl->h3 * s[P_POW];
-    ctl->max_force = r;
-    if (!isfinite(E) || !isfinite(r)) {
-        ctl->done = 1;
-        ctl->status = 3;
-        return;
-    }
-    bool arrest = false;
-    if (!ctl->redo && ((ctl->flow_mode == SKYR_ARREST_POWER && ctl->P < 0.0) ||
-                       (ctl->flow_mode == SKYR_ARREST_ENERGY && E > ctl->E_prev))) {
-        arrest = true;
-        ctl->arrests += 1;
-    }
-    if (r < ctl->tol) {
-        ctl->done = 1;
-        ctl->status = 1;
-        // the sweep wrote v_k + dt F_k over v_k; the next one puts v_k back (zero if v_k was
-        // reset by an arrest at this step or was zero on this redo sweep)
-        const bool v_zero = ctl->redo || arrest || ctl->flow_mode == SKYR_GRADIENT_FLOW;
-        ctl->restore = v_zero ? RESTORE_ZERO : RESTORE_UNKICK;
-        ctl->redo = 0;
-        return;
-    }
-    if (arrest) {
-        ctl->redo = 1;
-        ctl->redo_sweeps += 1;
-        return;
-    }
-    ctl->cur ^= 1;
-    ctl->redo = 0;
-    ctl->E_prev = E;
-    ctl->steps += 1;
-    if (ctl->steps >= ctl->target) {
-        ctl->done = 1;
-        ctl->status = 2;
-    }
+    if (threadIdx.x == 0) flow_decide(s, ctl);
 }
 
 __global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl) { finalize_flow(part, ctl); }
-
-// one block per field of one group of a batch: block i finalises field list[i]
-__global__ void batch_finalize_kernel(const SweepArgs* __restrict__ jobs, const int* __restrict__ list, int n)
-{
-    if ((int)blockIdx.x >= n) return;
-    const int j = list[blockIdx.x];
-    finalize_flow(jobs[j].partials, jobs[j].ctl);
-}
 
 // ------------------------------------------------------------- launches
 // the kernel variant with the extra potentials and the gradient flow is used only
@@ -512,6 +460,36 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
     return hipErrorInvalidValue;
 }
 
+// The step-sweep kernel of a tile shape at a kernel variant, and its block size (for
+// the nodes of a graph).
+template <typename T, class G> static const void* step_fn(int ext, int& threads)
+{
+    threads = G::THREADS;
+    if (ext == EXT_SEXTIC) return (const void*)sweep_kernel<T, G, MODE_STEP, EXT_SEXTIC>;
+    if (ext == EXT_POT) return (const void*)sweep_kernel<T, G, MODE_STEP, EXT_POT>;
+    return (const void*)sweep_kernel<T, G, MODE_STEP, EXT_NONE>;
+}
+
+static const void* step_kernel(skyr_precision prec, int variant, int ext, int& threads)
+{
+    int v = 0;
+    if (prec == SKYR_F64) {
+#define SKYR_S64(a, b, c, d, e)                                              \
+    if (variant == v) return step_fn<double, Geo<a, b, c, d>>(ext, threads); \
+    ++v;
+        SKYR_SHAPES_F64(SKYR_S64)
+#undef SKYR_S64
+    } else {
+#define SKYR_S32(a, b, c, d, e)                                             \
+    if (variant == v) return step_fn<float, Geo<a, b, c, d>>(ext, threads); \
+    ++v;
+        SKYR_SHAPES_F32(SKYR_S32)
+#undef SKYR_S32
+    }
+    threads = 0;
+    return nullptr;
+}
+
 template <typename T>
 static void launch_printed(int mode, bool ext, dim3 grid, dim3 block, const SweepArgs& args, hipStream_t s)
 {
@@ -542,50 +520,47 @@ static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattic
     return hipGetLastError();
 }
 
-// The batched sweep of one (precision, tile shape) group.
-template <typename T, class G>
-static hipError_t launch_batch(int ext, int blocks, const SweepArgs* jobs, const int* map, const int* first,
-                               const int* count, hipStream_t s)
+// The batched-sweep kernel of one (precision, tile shape) group at a kernel variant, and
+// its block size.
+template <typename T, class G> static const void* batch_fn(int ext, int& threads)
 {
-    if (ext == EXT_SEXTIC)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_SEXTIC>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
-                           first, count);
-    else if (ext == EXT_POT)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_POT>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
-                           first, count);
-    else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, G, EXT_NONE>), dim3(blocks), dim3(G::THREADS), 0, s, jobs, map,
-                           first, count);
-    return hipGetLastError();
+    threads = G::THREADS;
+    if (ext == EXT_SEXTIC) return (const void*)batch_sweep_kernel<T, G, EXT_SEXTIC>;
+    if (ext == EXT_POT) return (const void*)batch_sweep_kernel<T, G, EXT_POT>;
+    return (const void*)batch_sweep_kernel<T, G, EXT_NONE>;
 }
 
-// the batched sweep of the jobs of one (precision, tile shape) group
-static hipError_t batch_sweep(skyr_precision prec, int variant, int ext, int blocks, const SweepArgs* jobs,
-                              const int* map, const int* first, const int* count, hipStream_t s)
+static const void* batch_kernel(skyr_precision prec, int variant, int ext, int& threads)
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_B64(a, b, c, d, e)                                                                             \
-    if (variant == v) return launch_batch<double, Geo<a, b, c, d>>(ext, blocks, jobs, map, first, count, s);  \
+#define SKYR_B64(a, b, c, d, e)                                               \
+    if (variant == v) return batch_fn<double, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F64(SKYR_B64)
 #undef SKYR_B64
     } else {
-#define SKYR_B32(a, b, c, d, e)                                                                             \
-    if (variant == v) return launch_batch<float, Geo<a, b, c, d>>(ext, blocks, jobs, map, first, count, s);   \
+#define SKYR_B32(a, b, c, d, e)                                              \
+    if (variant == v) return batch_fn<float, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F32(SKYR_B32)
 #undef SKYR_B32
     }
-    return hipErrorInvalidValue;
+    threads = 0;
+    return nullptr;
 }
 
 static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_model* model, double dt)
 {
-    SweepArgs a{};
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);  // padding too: flow graphs are looked up by these bytes
     a.n0 = lat->n[0];
     a.n1 = lat->n[1];
     a.n2 = lat->n[2];
+    for (int d = 0; d < 3; ++d) {  // a whole lattice: I and the output region are its interior
+        a.ilo[d] = a.olo[d] = 2;
+        a.ihi[d] = a.ohi[d] = lat->n[d] - 3;
+    }
     a.tiles_z = L.tiles_z;
     a.tiles_y = L.tiles_y;
     a.zstart = L.zstart;
@@ -1018,10 +993,86 @@ static size_t flow_work_bytes(const skyr_lattice* lat, skyr_precision prec, cons
     return CTL_BYTES + OBS_BYTES + (size_t)nb * NPART * sizeof(double);
 }
 
-// the flow itself, after the argument checks; timed: record sweep events (skyr_timing_enable)
+// ------------------------------------------------------------ flow graphs
+// The single-field exact-form flow replays its step sweeps in groups of kFlowGraphSweeps
+// from a graph instantiated once per launch (the sweep's arguments, tile shape, kernel
+// variant and device); a small cache keeps the most recently used.  Launches happen under
+// the cache lock, so that no graph is destroyed while another thread enqueues it.
+constexpr int kFlowGraphSweeps = 32;
+constexpr size_t kFlowGraphCache = 8;
+struct FlowGraph {
+    int device;
+    int prec, variant, ext;
+    SweepArgs args;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+static std::mutex g_flow_graph_mu;
+static std::vector<FlowGraph> g_flow_graphs;  // least recently used first
+
+// enqueue reps x kFlowGraphSweeps step sweeps of the flow with arguments a on stream s
+static skyr_status flow_graph_launch(skyr_precision prec, const Launch& L, const SweepArgs& a, int reps,
+                                     hipStream_t s)
+{
+    int dev = 0;
+    SKYR_HIP(hipGetDevice(&dev));
+    const int ext = ext_level(a);
+    std::lock_guard<std::mutex> lock(g_flow_graph_mu);
+    size_t i = 0;
+    for (; i < g_flow_graphs.size(); ++i) {
+        const FlowGraph& f = g_flow_graphs[i];
+        if (f.device == dev && f.prec == (int)prec && f.variant == L.variant && f.ext == ext &&
+            std::memcmp(&f.args, &a, sizeof a) == 0)
+            break;
+    }
+    if (i == g_flow_graphs.size()) {
+        int threads = 0;
+        const void* fn = step_kernel(prec, L.variant, ext, threads);
+        if (!fn) return fail(SKYR_E_INVAL, "no step kernel for this tile shape");
+        FlowGraph f{dev, (int)prec, L.variant, ext, a, nullptr, nullptr};
+        void* argv[1] = {&f.args};
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(fn);
+        p.gridDim = dim3(L.blocks());
+        p.blockDim = dim3(threads);
+        p.sharedMemBytes = 0;
+        p.kernelParams = argv;
+        p.extra = nullptr;
+        hipError_t e = hipGraphCreate(&f.graph, 0);
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < kFlowGraphSweeps && e == hipSuccess; ++k) {
+            hipGraphNode_t node = nullptr;
+            e = hipGraphAddKernelNode(&node, f.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+            prev = node;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&f.exec, f.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (f.graph) (void)hipGraphDestroy(f.graph);
+            return fail(SKYR_E_DEVICE, std::string("flow graph: ") + hipGetErrorString(e));
+        }
+        if (g_flow_graphs.size() == kFlowGraphCache) {
+            // the evicted graph may still run on some stream of this process
+            SKYR_HIP(hipDeviceSynchronize());
+            (void)hipGraphExecDestroy(g_flow_graphs.front().exec);
+            (void)hipGraphDestroy(g_flow_graphs.front().graph);
+            g_flow_graphs.erase(g_flow_graphs.begin());
+        }
+        g_flow_graphs.push_back(f);
+        i = g_flow_graphs.size() - 1;
+    } else if (i + 1 != g_flow_graphs.size()) {
+        std::rotate(g_flow_graphs.begin() + i, g_flow_graphs.begin() + i + 1, g_flow_graphs.end());
+        i = g_flow_graphs.size() - 1;
+    }
+    for (int r = 0; r < reps; ++r) SKYR_HIP(hipGraphLaunch(g_flow_graphs[i].exec, s));
+    return SKYR_OK;
+}
+
+// the flow itself, after the argument checks.  timed: record sweep events while timing is
+// enabled (skyr_timing_enable; every sweep is then launched directly); graphs: replay whole
+// groups of sweeps from a cached graph (exact form, timing off)
 static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
-                           int64_t nsteps, void* work, hipStream_t s, bool timed)
+                           int64_t nsteps, void* work, hipStream_t s, bool timed, bool graphs)
 {
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
     if (st->converged || target <= st->steps) return SKYR_OK;
@@ -1068,25 +1119,35 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
         SKYR_HIP(hipGetLastError());
     }
     // sweeps are enqueued in groups; the host looks at the control block between groups
+    // (sweeps after the flow has stopped return at once)
+    graphs = graphs && !printed && !(timed && g_timing.on);
+    const int64_t max_group = graphs ? 4 * kFlowGraphSweeps : 32;
     const int64_t remaining = target - st->steps;
-    int64_t group = std::min<int64_t>(std::max<int64_t>(remaining, 1), 32);
+    int64_t group = std::min<int64_t>(std::max<int64_t>(remaining, 1), max_group);
     int64_t budget = 2 * remaining + 2;  // every step takes at most one redo sweep
     auto enqueue_sweep = [&](bool timed) -> hipError_t {
         hipError_t e = timed ? timing_mark(s) : hipSuccess;
         if (e == hipSuccess) e = printed ? sweep_printed(prec, MODE_STEP, lat, a, s) : sweep(prec, MODE_STEP, L, a, s);
         if (e == hipSuccess && timed) e = timing_mark(s);
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || !printed) return e;  // the exact-form sweep takes the decision itself
         hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
         return hipGetLastError();
     };
     for (;;) {
-        for (int64_t i = 0; i < group; ++i) SKYR_HIP(enqueue_sweep(timed));
+        if (graphs && group >= kFlowGraphSweeps) {
+            const int reps = (int)(group / kFlowGraphSweeps);
+            const skyr_status rc = flow_graph_launch(prec, L, a, reps, s);
+            if (rc != SKYR_OK) return rc;
+            group = (int64_t)reps * kFlowGraphSweeps;
+        } else {
+            for (int64_t i = 0; i < group; ++i) SKYR_HIP(enqueue_sweep(timed));
+        }
         budget -= group;
         SKYR_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
         SKYR_HIP(hipStreamSynchronize(s));
         if (timed) SKYR_HIP(timing_collect());
         if (h.done || budget <= 0) break;
-        group = std::min<int64_t>(std::max<int64_t>(h.target - h.steps, 1), 32);
+        group = std::min<int64_t>(std::max<int64_t>(h.target - h.steps, 1), max_group);
     }
     if (h.restore) {
         // converged in the last sweep of a group: one more sweep puts v_k back
@@ -1150,7 +1211,7 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
 {
     const skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work);
     if (rc != SKYR_OK) return rc;
-    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true);
+    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true, true);
 }
 
 skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
@@ -1169,7 +1230,269 @@ skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, 
     void* work = nullptr;
     rc = scratch_on_current_device(&work);
     if (rc != SKYR_OK) return rc;
-    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, false);
+    // direct launches only: instantiating a graph may allocate
+    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, false, false);
+}
+
+}  // extern "C"
+
+// ============================================================ block sweeps
+namespace skyr {
+
+// Geometry of a block: padded extents and the ranges, in padded coordinates, of the own
+// box, of I (the lattice's interior) and of the output region (own sites in I).
+struct BlockGeo {
+    int P[3];         // padded extent per axis
+    int e[3];         // own extent
+    int org[3];       // origin
+    int n[3];         // lattice
+    int ilo[3], ihi[3];
+    int olo[3], ohi[3];
+    bool empty;       // no own site in I
+    __host__ __device__ long long sites() const { return (long long)P[0] * P[1] * P[2]; }
+    __host__ __device__ long long shell() const { return sites() - (long long)e[0] * e[1] * e[2]; }
+};
+
+static skyr_status block_geo(const skyr_block* blk, BlockGeo& g)
+{
+    if (!blk) return fail(SKYR_E_INVAL, "block is null");
+    const skyr_lattice& L = blk->lattice;
+    for (int d = 0; d < 3; ++d)
+        if (L.n[d] < 5) return fail(SKYR_E_INVAL, "every lattice dimension must be at least 5");
+    if (!(L.h > 0.0) || !std::isfinite(L.h)) return fail(SKYR_E_INVAL, "lattice spacing must be positive");
+    g.empty = false;
+    for (int d = 0; d < 3; ++d) {
+        const int o = blk->origin[d], e = blk->extent[d];
+        if (e < 1 || o < 0 || (long long)o + e > L.n[d]) return fail(SKYR_E_INVAL, "block outside its lattice");
+        g.e[d] = e;
+        g.org[d] = o;
+        g.n[d] = L.n[d];
+        g.P[d] = e + 8;
+        // padded index p holds lattice site p + o - 4
+        g.ilo[d] = 2 - (o - 4);
+        g.ihi[d] = L.n[d] - 3 - (o - 4);
+        g.olo[d] = std::max(4, g.ilo[d]);
+        g.ohi[d] = std::min(e + 3, g.ihi[d]);
+        if (g.olo[d] > g.ohi[d]) g.empty = true;
+    }
+    if (g.sites() >= (1LL << 31) / 4) return fail(SKYR_E_INVAL, "padded block too large for 32-bit component offsets");
+    return SKYR_OK;
+}
+
+// tile shape, slab length and tile grid of a block's output region
+static Launch plan_block(const BlockGeo& g, skyr_precision prec)
+{
+    int oe[3];
+    for (int d = 0; d < 3; ++d) oe[d] = std::max(1, g.ohi[d] - g.olo[d] + 1);
+    // the shape and slabs of a lattice whose interior has the region's extents
+    skyr_lattice pseudo{};
+    for (int d = 0; d < 3; ++d) pseudo.n[d] = oe[d] + 4;
+    pseudo.h = 1.0;
+    Launch L = plan(&pseudo, prec);
+    L.tiles_y = (oe[1] + L.shape.oy() - 1) / L.shape.oy();
+    L.tiles_z = (oe[2] + L.shape.oz() - 1) / L.shape.oz();
+    L.zstart = g.olo[2];
+    L.slabs = (oe[0] + L.xchunk - 1) / L.xchunk;
+    return L;
+}
+
+static size_t block_work_bytes(const BlockGeo& g, skyr_precision prec)
+{
+    return CTL_BYTES + OBS_BYTES + (size_t)plan_block(g, prec).blocks() * NPART * sizeof(double);
+}
+
+// rank of padded site (x, y, z) among the shell sites (row-major order, own box left out)
+__device__ __forceinline__ long long shell_rank(int x, int y, int z, int P1, int P2, int e0, int e1, int e2)
+{
+    const long long plane = (long long)P1 * P2, ring = plane - (long long)e1 * e2;
+    if (x < 4) return x * plane + (long long)y * P2 + z;
+    if (x >= 4 + e0) return 4 * plane + e0 * ring + (long long)(x - 4 - e0) * plane + (long long)y * P2 + z;
+    long long r = 4 * plane + (long long)(x - 4) * ring;
+    if (y < 4) return r + (long long)y * P2 + z;
+    if (y >= 4 + e1) return r + 4LL * P2 + (long long)e1 * (P2 - e2) + (long long)(y - 4 - e1) * P2 + z;
+    return r + 4LL * P2 + (long long)(y - 4) * (P2 - e2) + (z < 4 ? z : z - e2);
+}
+
+// The shell of a padded block field.  Pass 0: shell sites inside the lattice from the
+// shell buffer.  Pass 1 (after pass 0): shell sites outside the lattice from the nearest
+// lattice site, which pass 0 or the own box has filled.
+template <typename T>
+__global__ void block_shell_kernel(T* __restrict__ phi, const T* __restrict__ shell, BlockGeo g, int pass)
+{
+    const long long N = g.sites(), S = g.shell();
+    const int P1 = g.P[1], P2 = g.P[2];
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < N; s += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(s % P2), y = (int)((s / P2) % P1), x = (int)(s / ((long long)P1 * P2));
+        const int p[3] = {x, y, z};
+        bool own = true, inside = true;
+        int q[3];
+        for (int d = 0; d < 3; ++d) {
+            own = own && p[d] >= 4 && p[d] < 4 + g.e[d];
+            const int gl = p[d] + g.org[d] - 4;  // lattice site
+            inside = inside && gl >= 0 && gl < g.n[d];
+            q[d] = min(max(gl, 0), g.n[d] - 1) - g.org[d] + 4;  // padded index of the nearest lattice site
+        }
+        if (own) continue;
+        if (pass == 0 && inside) {
+            const long long r = shell_rank(x, y, z, P1, P2, g.e[0], g.e[1], g.e[2]);
+            for (int A = 0; A < 4; ++A) phi[A * N + s] = shell[A * S + r];
+        } else if (pass == 1 && !inside) {
+            const long long t = ((long long)q[0] * P1 + q[1]) * P2 + q[2];
+            for (int A = 0; A < 4; ++A) phi[A * N + s] = phi[A * N + t];
+        }
+    }
+}
+
+// the control block of one block step: no decision taken (the caller's), state as given
+__global__ void block_ctl_kernel(Ctl* __restrict__ ctl, int redo, int renorm64, int nblocks)
+{
+    if (threadIdx.x != 0) return;
+    Ctl c{};
+    c.redo = redo;
+    c.renorm64_every = renorm64 ? 1 : 0;
+    c.nblocks = nblocks;
+    c.hold = 1;
+    c.target = INT64_MAX;
+    c.E_prev = INFINITY;
+    *ctl = c;
+}
+
+// out = {E, E2, E4, E0, E6, power, max_force}
+__global__ void block_sums_kernel(const double* __restrict__ part, int nblocks, double h, int step,
+                                  double* __restrict__ out)
+{
+    double s[NRED];
+    reduce_partials(part, nblocks, s);
+    if (threadIdx.x == 0) {
+        const double h3 = h * h * h;
+        const double E2 = h3 * s[P_E2], E4 = h3 * s[P_E4], E0 = h3 * s[P_E0], E6 = h3 * s[P_E6];
+        out[0] = E2 + E4 + E0 + E6;  // in step mode the whole density is summed in the first slot
+        out[1] = step ? 0.0 : E2;
+        out[2] = E4;
+        out[3] = E0;
+        out[4] = E6;
+        out[5] = h3 * s[P_POW];
+        out[6] = sqrt(s[P_F2]);
+    }
+}
+
+}  // namespace skyr
+
+extern "C" {
+
+int64_t skyr_block_sites(const skyr_block* blk)
+{
+    BlockGeo g;
+    return block_geo(blk, g) == SKYR_OK ? g.sites() : 0;
+}
+
+int64_t skyr_block_shell_sites(const skyr_block* blk)
+{
+    BlockGeo g;
+    return block_geo(blk, g) == SKYR_OK ? g.shell() : 0;
+}
+
+size_t skyr_block_workspace_bytes(const skyr_block* blk, skyr_precision prec)
+{
+    BlockGeo g;
+    if (block_geo(blk, g) != SKYR_OK) return 0;
+    if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return 0;
+    return block_work_bytes(g, prec);
+}
+
+skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const skyr_model* model, int32_t mode,
+                             int32_t projected, double dt, int32_t redo, int32_t renorm64, void* phi,
+                             const void* shell, void* out, void* vel, skyr_block_sums* sums, void* work, void* stream)
+{
+    BlockGeo g;
+    skyr_status rc = block_geo(blk, g);
+    if (rc != SKYR_OK) return rc;
+    rc = check_common(&blk->lattice, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "block sweeps use the exact-gradient form");
+    if (mode != SKYR_BLOCK_GRADIENT && mode != SKYR_BLOCK_STEP) return fail(SKYR_E_INVAL, "unknown block mode");
+    if (!shell || !out) return fail(SKYR_E_INVAL, "shell and out must be non-null");
+    const bool step = mode == SKYR_BLOCK_STEP;
+    if (step && !vel) return fail(SKYR_E_INVAL, "a step needs vel");
+    if (step && (!(dt > 0.0) || !std::isfinite(dt))) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (out == phi || (step && (vel == phi || vel == out))) return fail(SKYR_E_INVAL, "phi, out and vel must differ");
+    hipStream_t s = (hipStream_t)stream;
+    if (g.empty) {
+        if (sums) *sums = skyr_block_sums{};
+        return SKYR_OK;
+    }
+    // the shell
+    {
+        const int blocks = (int)std::min<long long>((g.sites() + 255) / 256, 8192);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (prec == SKYR_F64)
+                hipLaunchKernelGGL(block_shell_kernel<double>, dim3(blocks), dim3(256), 0, s, (double*)phi,
+                                   (const double*)shell, g, pass);
+            else
+                hipLaunchKernelGGL(block_shell_kernel<float>, dim3(blocks), dim3(256), 0, s, (float*)phi,
+                                   (const float*)shell, g, pass);
+            SKYR_HIP(hipGetLastError());
+        }
+    }
+    const Launch L = plan_block(g, prec);
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n0 = g.P[0];
+    a.n1 = g.P[1];
+    a.n2 = g.P[2];
+    for (int d = 0; d < 3; ++d) {
+        a.ilo[d] = g.ilo[d];
+        a.ihi[d] = g.ihi[d];
+        a.olo[d] = g.olo[d];
+        a.ohi[d] = g.ohi[d];
+    }
+    a.tiles_z = L.tiles_z;
+    a.tiles_y = L.tiles_y;
+    a.zstart = L.zstart;
+    a.xchunk = L.xchunk;
+    a.h = blk->lattice.h;
+    a.m = model->m;
+    a.m_y = model->m_y;
+    a.m_z = model->m_z;
+    a.m_w = model->m_w;
+    a.c6 = model->c6;
+    a.dt = step ? dt : 0.0;
+    char* w = (char*)work;
+    Ctl* ctl = (Ctl*)w;
+    double* res = (double*)(w + CTL_BYTES);
+    a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
+    a.phi0 = phi;
+    if (step) {
+        a.phi1 = out;
+        a.vel = vel;
+        a.ctl = ctl;
+        hipLaunchKernelGGL(block_ctl_kernel, dim3(1), dim3(64), 0, s, ctl, redo ? 1 : 0,
+                           (prec == SKYR_F32_BULK && renorm64) ? 1 : 0, L.blocks());
+        SKYR_HIP(hipGetLastError());
+    } else {
+        a.grad = out;
+        a.projected = projected ? 1 : 0;
+    }
+    SKYR_HIP(timing_mark(s));
+    SKYR_HIP(sweep(prec, step ? MODE_STEP : MODE_GRAD, L, a, s));
+    SKYR_HIP(timing_mark(s));
+    if (sums) {
+        hipLaunchKernelGGL(block_sums_kernel, dim3(1), dim3(256), 0, s, a.partials, L.blocks(), blk->lattice.h,
+                           step ? 1 : 0, res);
+        SKYR_HIP(hipGetLastError());
+        double o[7];
+        SKYR_HIP(hipMemcpyAsync(o, res, sizeof o, hipMemcpyDeviceToHost, s));
+        SKYR_HIP(hipStreamSynchronize(s));
+        SKYR_HIP(timing_collect());
+        sums->E = o[0];
+        sums->E2 = o[1];
+        sums->E4 = o[2];
+        sums->E0 = o[3];
+        sums->E6 = o[4];
+        sums->power = o[5];
+        sums->max_force = o[6];
+    }
+    return SKYR_OK;
 }
 
 int32_t skyr_tile_variants(skyr_precision prec)
@@ -1223,8 +1546,10 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)work;
     Ctl* ctl = (Ctl*)w;
-    // every candidate runs the same sweep: phi -> phi_alt with zero incoming velocity
+    // every candidate runs the same sweep: phi -> phi_alt with zero incoming velocity, on a
+    // held control block (the sweeps take no decision)
     Ctl h{};
+    h.hold = 1;
     h.redo = 1;
     h.target = INT64_MAX;
     h.E_prev = INFINITY;
@@ -1327,7 +1652,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
 }  // extern "C"
 
 // ================================================================ batches
-// A batch owns only its job table, the control blocks and the captured graph;
+// A batch owns only its job table, the control blocks and the graph of its sweep slots;
 // field, velocity and workspace memory stay with the caller.
 struct skyr_batch {
     struct Job {
@@ -1340,7 +1665,6 @@ struct skyr_batch {
     };
     int max_jobs = 0;
     hipStream_t stream = nullptr;    // caller's stream (work is launched here)
-    hipStream_t capture = nullptr;   // private stream used only to capture the graph
     std::vector<Job> jobs;
     std::vector<SweepArgs> args;     // host mirror of d_args
     std::vector<Ctl> ctl;            // host mirror of d_ctl (valid after a run / poll)
@@ -1351,29 +1675,25 @@ struct skyr_batch {
     // Jobs are grouped by (precision, tile shape): group g < F64 shape count is F64 shape g,
     // the rest F32 shape g - (F64 shape count); one kernel serves a group.  A group's jobs
     // are split into one or more chains (balanced by blocks); a chain is one batched launch
-    // and one finaliser of its own jobs per sweep slot.  Chains share no field, so their
-    // sequences of sweep slots are independent: the captured graph forks them onto side
-    // streams, where one chain's blocks fill the CUs another chain's last round leaves
-    // idle, and joins them at its end.
+    // of its own jobs per sweep slot (the sweep takes each job's flow decision itself).
+    // Chains share no field, so the graph holds them as independent branches, where one
+    // chain's blocks fill the CUs another chain's last round leaves idle.
     static constexpr int kGroups = 16;
-    static constexpr int kSide = 3;
-    static constexpr int kStreams = 1 + kSide;
-    static constexpr int kChains = kGroups * kStreams;
+    static constexpr int kChains = 2 * kGroups;
     int nchains = 0;
     int chain_group[kChains] = {};
     int* d_map[kChains] = {};  // block -> job, per chain
     int map_cap[kChains] = {};
     int grid[kChains] = {};
-    int* d_list[kChains] = {};  // the jobs of each chain (for its finaliser)
-    int list_cap[kChains] = {};
-    int nlist[kChains] = {};
     int ext[kChains] = {};  // the highest kernel variant a job of the chain needs
-    bool dirty = true;
+    bool dirty = true;       // the job tables need rebuilding
+    bool params_stale = true;  // the graph's launch parameters predate the job tables
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_sweeps = 0;
-    hipStream_t side[kSide] = {};
-    hipEvent_t events[kStreams] = {};  // fork, then the join of each side stream
+    int graph_chains = 0;
+    const void* graph_fn[kChains] = {};     // the kernel of each chain in the graph
+    std::vector<hipGraphNode_t> nodes;      // [chain][sweep slot]
 };
 
 namespace skyr {
@@ -1385,6 +1705,8 @@ static void batch_release_graph(skyr_batch* b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_sweeps = 0;
+    b->graph_chains = 0;
+    b->nodes.clear();
 }
 
 static int batch_group(skyr_precision prec, int variant)
@@ -1421,9 +1743,10 @@ static skyr_status batch_rebuild(skyr_batch* b)
         groups += v.empty() ? 1 : 0;
         v.push_back(j);
     }
-    // chains per group: the streams shared out over the groups present, at most two (four
-    // concurrent chains of one kernel ran the 64-job mix 3% slower than one; two match it)
-    const int parts = std::min(2, std::max(1, skyr_batch::kStreams / std::max(groups, 1)));
+    // chains per group: four branches shared out over the groups present, at most two per
+    // group (four concurrent chains of one kernel ran the 64-job mix 3% slower than one;
+    // two match it)
+    const int parts = std::min(2, std::max(1, 4 / std::max(groups, 1)));
     std::vector<int> map[skyr_batch::kChains], list[skyr_batch::kChains];
     int nc = 0;
     for (int g = 0; g < skyr_batch::kGroups; ++g) {
@@ -1453,65 +1776,86 @@ static skyr_status batch_rebuild(skyr_batch* b)
             map[c].insert(map[c].end(), count[j], j);
         }
         skyr_status rc = upload_ints(map[c], b->d_map[c], b->map_cap[c]);
-        if (rc == SKYR_OK) rc = upload_ints(list[c], b->d_list[c], b->list_cap[c]);
         if (rc != SKYR_OK) return rc;
         b->grid[c] = (int)map[c].size();
-        b->nlist[c] = (int)list[c].size();
     }
     b->nchains = nc;
     SKYR_HIP(hipMemcpy(b->d_first, first.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_count, count.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_args, b->args.data(), sizeof(SweepArgs) * b->max_jobs, hipMemcpyHostToDevice));
-    batch_release_graph(b);
     b->dirty = false;
+    b->params_stale = true;
     return SKYR_OK;
 }
 
-// capture `sweeps` sweep slots of every chain: per slot, the chain's batched sweep and the
-// finaliser of its jobs; chain c runs on stream c mod kStreams (0: the capture stream)
-static skyr_status batch_capture(skyr_batch* b, int sweeps)
+// launch parameters of chain c's batched sweep; argv (four entries) receives the
+// addresses of its arguments, which live in the batch object
+static hipKernelNodeParams chain_params(skyr_batch* b, int c, void** argv)
 {
-    batch_release_graph(b);
+    const int g = b->chain_group[c];
+    const bool f64 = g < shape_count(SKYR_F64);
+    int threads = 0;
+    const void* fn = batch_kernel(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[c],
+                                  threads);
+    argv[0] = &b->d_args;
+    argv[1] = &b->d_map[c];
+    argv[2] = &b->d_first;
+    argv[3] = &b->d_count;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(fn);
+    p.gridDim = dim3(b->grid[c]);
+    p.blockDim = dim3(threads);
+    p.sharedMemBytes = 0;
+    p.kernelParams = argv;
+    p.extra = nullptr;
+    return p;
+}
+
+// The graph of `sweeps` sweep slots: one kernel node per chain and slot, each chain a
+// linear branch of its own.  When only the jobs changed (the same chains with the same
+// kernels), the nodes of the instantiated graph get their new grids and tables in place;
+// otherwise the graph is built and instantiated anew.
+static skyr_status batch_graph(skyr_batch* b, int sweeps)
+{
     const int nc = b->nchains;
-    const int nside = std::min(std::max(nc - 1, 0), skyr_batch::kSide);
-    for (int j = 0; j < nside; ++j) {
-        if (!b->side[j]) SKYR_HIP(hipStreamCreateWithFlags(&b->side[j], hipStreamNonBlocking));
-        if (!b->events[1 + j]) SKYR_HIP(hipEventCreateWithFlags(&b->events[1 + j], hipEventDisableTiming));
+    void* argv[skyr_batch::kChains][4];
+    hipKernelNodeParams prm[skyr_batch::kChains];
+    bool same = b->exec && b->graph_sweeps == sweeps && b->graph_chains == nc;
+    for (int c = 0; c < nc; ++c) {
+        prm[c] = chain_params(b, c, argv[c]);
+        if (!prm[c].func) return fail(SKYR_E_INVAL, "no batched kernel for a job's tile shape");
+        same = same && prm[c].func == b->graph_fn[c];
     }
-    if (nside > 0 && !b->events[0]) SKYR_HIP(hipEventCreateWithFlags(&b->events[0], hipEventDisableTiming));
-    auto stream_of = [&](int c) { return c % (nside + 1) == 0 ? b->capture : b->side[c % (nside + 1) - 1]; };
-    SKYR_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    if (nside > 0) e = hipEventRecord(b->events[0], b->capture);
-    for (int j = 0; j < nside && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->events[0], 0);
-    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
-        for (int c = 0; c < nc && e == hipSuccess; ++c) {
-            const int g = b->chain_group[c];
-            const hipStream_t s = stream_of(c);
-            const bool f64 = g < shape_count(SKYR_F64);
-            e = batch_sweep(f64 ? SKYR_F64 : SKYR_F32_BULK, f64 ? g : g - shape_count(SKYR_F64), b->ext[c], b->grid[c],
-                            b->d_args, b->d_map[c], b->d_first, b->d_count, s);
-            if (e != hipSuccess) break;
-            hipLaunchKernelGGL(batch_finalize_kernel, dim3(b->nlist[c]), dim3(256), 0, s, b->d_args, b->d_list[c],
-                               b->nlist[c]);
-            e = hipGetLastError();
+    if (same) {
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < nc && e == hipSuccess; ++c)
+            for (int k = 0; k < sweeps && e == hipSuccess; ++k)
+                e = hipGraphExecKernelNodeSetParams(b->exec, b->nodes[(size_t)c * sweeps + k], &prm[c]);
+        if (e == hipSuccess) {
+            b->params_stale = false;
+            return SKYR_OK;
         }
+        (void)hipGetLastError();  // rebuild below
     }
-    // join every side stream back, also after an error, so that the capture can end
-    for (int j = 0; j < nside; ++j) {
-        hipError_t ej = hipEventRecord(b->events[1 + j], b->side[j]);
-        if (ej == hipSuccess) ej = hipStreamWaitEvent(b->capture, b->events[1 + j], 0);
-        if (e == hipSuccess) e = ej;
-    }
+    batch_release_graph(b);
     hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->capture, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(SKYR_E_DEVICE, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-    }
+    SKYR_HIP(hipGraphCreate(&g, 0));
     b->graph = g;
+    b->nodes.assign((size_t)nc * sweeps, nullptr);
+    for (int c = 0; c < nc; ++c) {
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < sweeps; ++k) {
+            hipGraphNode_t node = nullptr;
+            SKYR_HIP(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &prm[c]));
+            b->nodes[(size_t)c * sweeps + k] = node;
+            prev = node;
+        }
+        b->graph_fn[c] = prm[c].func;
+    }
     SKYR_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     b->graph_sweeps = sweeps;
+    b->graph_chains = nc;
+    b->params_stale = false;
     return SKYR_OK;
 }
 
@@ -1536,7 +1880,6 @@ skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
         (void)hipFree(b->d_args);
         (void)hipFree(b->d_first);
         (void)hipFree(b->d_count);
-        if (b->capture) (void)hipStreamDestroy(b->capture);
         delete b;
         return fail(SKYR_E_DEVICE, std::string("skyr_batch_create: ") + hipGetErrorString(e));
     };
@@ -1544,7 +1887,6 @@ skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_args, sizeof(SweepArgs) * max_jobs);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_first, sizeof(int) * max_jobs);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_count, sizeof(int) * max_jobs);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemcpy(b->d_ctl, b->ctl.data(), sizeof(Ctl) * max_jobs, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(e);
     // every slot points at its own (done) control block
@@ -1632,8 +1974,8 @@ skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
     int blocks = 0;
     for (int c = 0; c < b->nchains; ++c) blocks += b->grid[c];
     if (blocks > 0) {
-        if (!b->exec || b->graph_sweeps != sweeps) {
-            skyr_status rc = batch_capture(b, sweeps);
+        if (!b->exec || b->graph_sweeps != sweeps || b->params_stale) {
+            skyr_status rc = batch_graph(b, sweeps);
             if (rc != SKYR_OK) return rc;
         }
         SKYR_HIP(hipGraphLaunch(b->exec, b->stream));
@@ -1667,8 +2009,6 @@ static skyr_status batch_settle(skyr_batch* b, int j)
         const auto& J = b->jobs[j];
         const SweepArgs& a = b->args[j];
         SKYR_HIP(sweep(J.prec, MODE_STEP, J.L, a, b->stream));
-        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, b->stream, a.partials, a.ctl);
-        SKYR_HIP(hipGetLastError());
         SKYR_HIP(hipMemcpyAsync(&h, a.ctl, sizeof h, hipMemcpyDeviceToHost, b->stream));
         SKYR_HIP(hipStreamSynchronize(b->stream));
     }
@@ -1709,7 +2049,8 @@ skyr_status skyr_batch_remove(skyr_batch* b, int32_t slot)
     b->ctl[slot] = h;
     b->args[slot] = SweepArgs{};
     b->args[slot].ctl = b->d_ctl + slot;
-    SKYR_HIP(hipMemcpy(b->d_ctl + slot, &h, sizeof h, hipMemcpyHostToDevice));
+    // from the host mirror (it outlives the copy), in order on the batch's stream
+    SKYR_HIP(hipMemcpyAsync(b->d_ctl + slot, &b->ctl[slot], sizeof h, hipMemcpyHostToDevice, b->stream));
     b->dirty = true;
     return SKYR_OK;
 }
@@ -1732,12 +2073,6 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
     (void)hipFree(b->d_first);
     (void)hipFree(b->d_count);
     for (int c = 0; c < skyr_batch::kChains; ++c) (void)hipFree(b->d_map[c]);
-    if (b->capture) (void)hipStreamDestroy(b->capture);
-    for (int c = 0; c < skyr_batch::kChains; ++c) (void)hipFree(b->d_list[c]);
-    for (hipStream_t s : b->side)
-        if (s) (void)hipStreamDestroy(s);
-    for (hipEvent_t ev : b->events)
-        if (ev) (void)hipEventDestroy(ev);
     delete b;
     return SKYR_OK;
 }

@@ -39,6 +39,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/skyr.h"
+
 #include <type_traits>
 
 namespace skyr {
@@ -46,6 +48,7 @@ namespace skyr {
 // partial-sum slots per thread block (doubles)
 constexpr int NPART = 8;
 enum : int { P_E2 = 0, P_E4 = 1, P_E0 = 2, P_B = 3, P_F2 = 4, P_POW = 5, P_E6 = 6 };
+constexpr int NRED = 7;  // slots in use
 
 // Control block of one flow, in device memory at the start of the workspace.
 struct Ctl {
@@ -62,6 +65,8 @@ struct Ctl {
     int32_t nblocks;      // number of partial-sum blocks of the sweep
     int32_t flow_mode;    // skyr_flow_mode
     int32_t restore;      // after convergence: the next sweep over phi_k rewrites v_k (RESTORE_*)
+    int32_t ticket;       // blocks of the running sweep that have finished (zero between sweeps)
+    int32_t hold;         // timing sweeps: the sweep takes no decision (the state stays as it is)
     double E_prev;
     double E;
     double P;             // power h^3 sum F_k . v_k of the last sweep (arrest rule POWER)
@@ -88,9 +93,14 @@ struct SweepArgs {
     void* grad;        // MODE_GRAD: nullable gradient output
     double* partials;  // [nblocks][NPART]
     Ctl* ctl;          // MODE_STEP: control block
-    int n0, n1, n2;
+    int n0, n1, n2;        // extent of the stored array (the whole lattice, or a padded block)
+    // In array coordinates: I, the sites the energy sums over and the flux lives on (the
+    // lattice's interior: [2, n-3] per axis for a whole lattice), and the output region, the
+    // sites this launch updates (a box within I; all of I for a whole lattice).
+    int ilo[3], ihi[3];
+    int olo[3], ohi[3];
     int tiles_z, tiles_y;  // output tiles of the (y, z) plane
-    int zstart;            // z of the first tile's first column (0: line-aligned tiles; 2: the first interior column)
+    int zstart;            // z of the first tile's first column (at most olo[2]; below it for line-aligned tiles)
     int xchunk;            // planes per slab (the work order's outer unit)
     int projected;     // MODE_GRAD: write g - (g.phi) phi instead of g
     int baryon;        // accumulate the baryon density
@@ -289,6 +299,7 @@ template <typename T, class G> struct SweepSmem {
     Site4<T> phi[2][G::PPLANE];     // [plane parity][site]
     Site4<T> q[2][2][G::QPLANE];    // [plane parity][0: Q_y, 1: Q_z][site]
     double red[G::NW][NPART];
+    int last;  // this block is the last of its field to finish the sweep
 };
 
 // EXT: 0 the plain variant (pion-mass potential, kick-drift update); 1 adds the extra
@@ -350,14 +361,14 @@ struct Segment {
 // b of nb takes items b, b + nb, ...; a launch normally has one block per item, so that
 // the blocks of neighbouring tiles march through the same planes at the same time and
 // the phi lines of their shared halo are read from L2 once.
-__device__ __forceinline__ Segment item_segment(int item, int tiles, int tiles_z, int nx, int xchunk)
+__device__ __forceinline__ Segment item_segment(int item, int tiles, int tiles_z, int x0, int nx, int xchunk)
 {
     const int slab = item / tiles, tile = item - slab * tiles;
     Segment s;
     s.ty = tile / tiles_z;
     s.tz = tile - s.ty * tiles_z;
-    s.xa = 2 + slab * xchunk;
-    s.xe = 2 + min(nx, (slab + 1) * xchunk);
+    s.xa = x0 + slab * xchunk;
+    s.xe = x0 + min(nx, (slab + 1) * xchunk);
     return s;
 }
 
@@ -373,6 +384,8 @@ template <typename T, bool FROM_TABLE> struct SweepCommon {
     gptr<T> vel[4];
     gptr<T> gout[4];
     int n0, n1, n2;
+    int ilo[3], ihi[3];  // I in array coordinates
+    int olo1, olo2, ohi1, ohi2;  // the output region in y and z
     unsigned plane_b;  // bytes per x-plane of one component
     bool redo, renorm64, projected, baryon, has_grad;
     int restore;       // RESTORE_*: this sweep only rewrites the velocity
@@ -400,8 +413,9 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
     int pidx, qidx;    // LDS index of the own site in a phi plane and in a flux plane
     unsigned off;      // byte offset of the own site within a plane
     int xa, xe;
-    bool out;          // the own site is in I (in y and z)
-    bool yz_near;      // within two sites of a y or z face of I
+    bool out;          // the own site is in the output region (in y and z)
+    bool in_i;         // the own site is in I (in y and z); the flux there is not zero
+    bool yz_near;      // an output site within two sites of a y or z face of I
     unsigned outside;  // bit d: the y/z neighbour d (O_* below) lies outside I
     enum : unsigned { O_YP1 = 1, O_YM1 = 2, O_YP2 = 4, O_YM2 = 8, O_ZP1 = 16, O_ZM1 = 32, O_ZP2 = 64, O_ZM2 = 128 };
 
@@ -446,13 +460,14 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
 
     __device__ __forceinline__ void setup(const Segment& s, int tiles_z_start)
     {
-        const int y0 = 2 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
-        const int n1 = cm.n1, n2 = cm.n2;
+        const int y0 = cm.olo1 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
         const int y = y0 + row, z = z0 + col;
-        out = (y <= n1 - 3) && (z >= 2) && (z <= n2 - 3);
-        outside = (y + 1 > n1 - 3 ? O_YP1 : 0u) | (y - 1 < 2 ? O_YM1 : 0u) | (y + 2 > n1 - 3 ? O_YP2 : 0u) |
-                  (y - 2 < 2 ? O_YM2 : 0u) | (z + 1 > n2 - 3 ? O_ZP1 : 0u) | (z - 1 < 2 ? O_ZM1 : 0u) |
-                  (z + 2 > n2 - 3 ? O_ZP2 : 0u) | (z - 2 < 2 ? O_ZM2 : 0u);
+        const int ly = cm.ilo[1], hy = cm.ihi[1], lz = cm.ilo[2], hz = cm.ihi[2];
+        out = (y <= cm.ohi1) && (z >= cm.olo2) && (z <= cm.ohi2);
+        in_i = (y >= ly) && (y <= hy) && (z >= lz) && (z <= hz);
+        outside = (y + 1 > hy ? O_YP1 : 0u) | (y - 1 < ly ? O_YM1 : 0u) | (y + 2 > hy ? O_YP2 : 0u) |
+                  (y - 2 < ly ? O_YM2 : 0u) | (z + 1 > hz ? O_ZP1 : 0u) | (z - 1 < lz ? O_ZM1 : 0u) |
+                  (z + 2 > hz ? O_ZP2 : 0u) | (z - 2 < lz ? O_ZM2 : 0u);
         yz_near = out && outside != 0u;
         off = cm.site_off(y, z);
         xa = s.xa;
@@ -463,17 +478,17 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
     __device__ __forceinline__ void boundary_terms(int j, const Site4<T>* P)
     {
         if (!out) return;
-        const int n0 = cm.n0;
+        const int lx = cm.ilo[0], hx = cm.ihi[0];
         const T* pa0 = P[pidx].v;
         constexpr int W = 4 * G::PW;  // one row of sites, in elements
 #pragma unroll
         for (int A = 0; A < 4; ++A) {
             const T* pa = pa0 + A;
             T o1 = T(0), o2 = T(0);  // outside first / second neighbours
-            if (j + 1 > n0 - 3) o1 += ring[SP1][A];
-            if (j - 1 < 2) o1 += ring[SM1][A];
-            if (j + 2 > n0 - 3) o2 += ring[SP2][A];
-            if (j - 2 < 2) o2 += ring[SM2][A];
+            if (j + 1 > hx) o1 += ring[SP1][A];
+            if (j - 1 < lx) o1 += ring[SM1][A];
+            if (j + 2 > hx) o2 += ring[SP2][A];
+            if (j - 2 < lx) o2 += ring[SM2][A];
             if (outside & O_YP1) o1 += pa[W];
             if (outside & O_YM1) o1 += pa[-W];
             if (outside & O_ZP1) o1 += pa[4];
@@ -522,7 +537,7 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
                 for (int A = 0; A < 4; ++A) vcur[A] = T(0);
             }
         }
-        const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
+        const bool j_in = (j >= cm.ilo[0]) && (j <= cm.ihi[0]);
         const bool j_out = (j >= xa) && (j < xe);
 
         const Site4<T>* P = sm.phi[pb];
@@ -566,12 +581,12 @@ template <typename T, class G, int MODE, bool FROM_TABLE, int EXT> struct Interi
         // The E2 part of the gradient is -1/2 (Lap phi + Lap(1_I phi)): the terms of Lap phi
         // whose neighbour lies outside I count half.  Only sites within two of a face of I
         // have such terms; a wave none of whose sites has one skips this.
-        const bool x_near = (j <= 3) || (j >= cm.n0 - 4);
+        const bool x_near = (j <= cm.ilo[0] + 1) || (j >= cm.ihi[0] - 1);
         if (j_out && (x_near || __builtin_amdgcn_ballot_w64(yz_near) != 0)) boundary_terms<SM2, SM1, S0, SP1, SP2>(j, P);
 
         const T gxx = dot4(ax, ax), gyy = dot4(ay, ay), gzz = dot4(az, az);
         const T gxy = dot4(ax, ay), gxz = dot4(ax, az), gyz = dot4(ay, az);
-        const bool valid = out && j_in;
+        const bool valid = in_i && j_in;
         // the flux vanishes outside I: zero the Gram entries it is built from
         const T fxx = valid ? gxx : T(0), fyy = valid ? gyy : T(0), fzz = valid ? gzz : T(0);
         const T fxy = valid ? gxy : T(0), fxz = valid ? gxz : T(0), fyz = valid ? gyz : T(0);
@@ -822,11 +837,11 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
 
     __device__ __forceinline__ void setup(const Segment& s, int tiles_z_start)
     {
-        const int y0 = 2 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
+        const int y0 = cm.olo1 + s.ty * G::OY, z0 = tiles_z_start + s.tz * G::OZ;
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
             const int y = y0 + hr[i], z = z0 + hc[i];
-            vyz[i] = (y >= 2) && (y <= cm.n1 - 3) && (z >= 2) && (z <= cm.n2 - 3);
+            vyz[i] = (y >= cm.ilo[1]) && (y <= cm.ihi[1]) && (z >= cm.ilo[2]) && (z <= cm.ihi[2]);
             off[i] = cm.site_off(y, z);
         }
 #pragma unroll
@@ -861,7 +876,7 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
                 cm.load(foff[i], j + 2, fnxt[i]);
             }
         }
-        const bool j_in = (j >= 2) && (j <= cm.n0 - 3);
+        const bool j_in = (j >= cm.ilo[0]) && (j <= cm.ihi[0]);
         const Site4<T>* P = sm.phi[pb];
 #pragma unroll
         for (int i = 0; i < HPT; ++i) {
@@ -954,6 +969,116 @@ template <typename T, class G, bool FROM_TABLE, int EXT> struct Halo {
     }
 };
 
+// The flow's decision after the sweep over phi_k (Sec. 3), from the sums of that sweep
+// (s: the reduced partial-sum slots): arrest when E_k > E_{k-1} (energy rule) or when the
+// power h^3 sum F_k . v_k < 0 (power rule), re-running the sweep with v_k = 0; stop when
+// max|F_k| < tol; otherwise accept the update (swap the field buffers).  One thread.
+__device__ inline void flow_decide(const double* s, Ctl* ctl)
+{
+    // the flow sweep sums the whole energy density in slot P_E2 (slots P_E4, P_E0, P_E6 are zero)
+    const double E = ctl->h3 * s[P_E2];
+    const double r = sqrt(s[P_F2]);
+    ctl->sweeps += 1;
+    ctl->E = E;
+    ctl->P = ctl->h3 * s[P_POW];
+    ctl->max_force = r;
+    if (!isfinite(E) || !isfinite(r)) {
+        ctl->done = 1;
+        ctl->status = 3;
+        return;
+    }
+    bool arrest = false;
+    if (!ctl->redo && ((ctl->flow_mode == SKYR_ARREST_POWER && ctl->P < 0.0) ||
+                       (ctl->flow_mode == SKYR_ARREST_ENERGY && E > ctl->E_prev))) {
+        arrest = true;
+        ctl->arrests += 1;
+    }
+    if (r < ctl->tol) {
+        ctl->done = 1;
+        ctl->status = 1;
+        // the sweep wrote v_k + dt F_k over v_k; the next one puts v_k back (zero if v_k was
+        // reset by an arrest at this step or was zero on this redo sweep)
+        const bool v_zero = ctl->redo || arrest || ctl->flow_mode == SKYR_GRADIENT_FLOW;
+        ctl->restore = v_zero ? RESTORE_ZERO : RESTORE_UNKICK;
+        ctl->redo = 0;
+        return;
+    }
+    if (arrest) {
+        ctl->redo = 1;
+        ctl->redo_sweeps += 1;
+        return;
+    }
+    ctl->cur ^= 1;
+    ctl->redo = 0;
+    ctl->E_prev = E;
+    ctl->steps += 1;
+    if (ctl->steps >= ctl->target) {
+        ctl->done = 1;
+        ctl->status = 2;
+    }
+}
+
+// End of a step sweep: every block has published its partial sums; the block that
+// finishes last (a ticket counter in the control block, no waiting) sums them all in a
+// fixed order (thread t takes blocks t, t + THREADS, ..., then a fixed butterfly per wave
+// and the waves in order) and takes the flow's decision.  A restore sweep only clears the
+// restore flag; a sweep on a held control block only resets the ticket.
+// The partial sums are agent-scope atomic stores, complete (s_waitcnt) before the block's
+// ticket, and the last block reads them with agent-scope atomic loads: they are coherent
+// across the XCDs' L2 caches without a device-wide fence, which would write back and
+// invalidate the whole L2 of the block's XCD while its neighbours still read halo lines.
+// The fields of the control block other than the ticket change only between launches.
+template <typename T, class G>
+__device__ __forceinline__ void finish_step(const double* part, int nb, Ctl* ctl, bool restore, SweepSmem<T, G>& sm)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        __builtin_amdgcn_s_waitcnt(0);  // this block's partial sums before its ticket
+        sm.last = __hip_atomic_fetch_add(&ctl->ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nb - 1;
+    }
+    __syncthreads();
+    if (!sm.last) return;
+    if (restore || ctl->hold) {
+        if (tid == 0) {
+            if (restore) ctl->restore = RESTORE_NONE;
+            __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    double v[NRED];
+#pragma unroll
+    for (int i = 0; i < NRED; ++i) v[i] = 0.0;
+    for (int b = tid; b < nb; b += G::THREADS) {
+        const double* p = part + (size_t)b * NPART;
+#pragma unroll
+        for (int i = 0; i < NRED; ++i) {
+            const double x = __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v[i] = (i == P_F2) ? fmax(v[i], x) : v[i] + x;
+        }
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < NRED; ++i) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double w = __shfl_xor(v[i], o);
+            v[i] = (i == P_F2) ? fmax(v[i], w) : v[i] + w;
+        }
+        if (lane == 0) sm.red[wave][i] = v[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sum[NRED];
+#pragma unroll
+        for (int i = 0; i < NRED; ++i) sum[i] = 0.0;
+        for (int w = 0; w < G::NW; ++w)
+#pragma unroll
+            for (int i = 0; i < NRED; ++i) sum[i] = (i == P_F2) ? fmax(sum[i], sm.red[w][i]) : sum[i] + sm.red[w][i];
+        flow_decide(sum, ctl);
+        __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // One block's share of one field: logical block b of nb blocks, which takes the items b,
 // b + nb, ... of the field's work.  Used by the single-field and the batched kernels
 // (FROM_TABLE: the arguments were read from the batch's job table).
@@ -982,6 +1107,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     cm.n0 = a.n0;
     cm.n1 = a.n1;
     cm.n2 = a.n2;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        cm.ilo[d] = a.ilo[d];
+        cm.ihi[d] = a.ihi[d];
+    }
+    cm.olo1 = a.olo[1];
+    cm.olo2 = a.olo[2];
+    cm.ohi1 = a.ohi[1];
+    cm.ohi2 = a.ohi[2];
     cm.plane_b = (unsigned)(a.n1 * a.n2) * (unsigned)sizeof(T);
     const long long N3 = (long long)a.n0 * a.n1 * a.n2;
     {
@@ -1012,14 +1146,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tiles = a.tiles_y * a.tiles_z;
-    const int nx = a.n0 - 4;
+    const int x0 = a.olo[0], nx = a.ohi[0] - a.olo[0] + 1;
     const int items = tiles * ((nx + a.xchunk - 1) / a.xchunk);
 
     double vals[7] = {0, 0, 0, 0, 0, 0, 0};
     if (wave < G::NWI) {
         Interior<T, G, MODE, FROM_TABLE, EXT> it(sm, k, cm, tid);
         for (int item = b; item < items; item += nb) {
-            it.setup(item_segment(item, tiles, a.tiles_z, nx, a.xchunk), a.zstart);
+            it.setup(item_segment(item, tiles, a.tiles_z, x0, nx, a.xchunk), a.zstart);
             it.march();
         }
         vals[0] = it.pe2;
@@ -1032,7 +1166,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     } else {
         Halo<T, G, FROM_TABLE, EXT> hl(sm, k, cm, tid - G::NWI * 64);
         for (int item = b; item < items; item += nb) {
-            hl.setup(item_segment(item, tiles, a.tiles_z, nx, a.xchunk), a.zstart);
+            hl.setup(item_segment(item, tiles, a.tiles_z, x0, nx, a.xchunk), a.zstart);
             hl.march();
         }
     }
@@ -1058,8 +1192,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
         for (int wv = 0; wv < G::NWI; ++wv)
             for (int i = 0; i < 7; ++i) sum[i] = (i == P_F2) ? fmax(sum[i], sm.red[wv][i]) : sum[i] + sm.red[wv][i];
         double* o = a.partials + (size_t)b * NPART;
-        for (int i = 0; i < 7; ++i) o[i] = sum[i];
+        for (int i = 0; i < 7; ++i) __hip_atomic_store(o + i, sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if constexpr (MODE == MODE_STEP) finish_step<T, G>(a.partials, nb, a.ctl, cm.restore != RESTORE_NONE, sm);
 }
 
 // Blocks are dispatched round-robin over the eight XCDs (block i to XCD i % 8).

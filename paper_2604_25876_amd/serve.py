@@ -124,7 +124,7 @@ class Server:
     """FIFO admission by slot and HBM footprint; continuous batching."""
 
     def __init__(self, backend, max_jobs: int, hbm_budget: int, sweeps_per_tick: int = 32,
-                 keep_fields: bool = False, clock=time.perf_counter):
+                 keep_fields: bool = False, clock=time.perf_counter, progress=None):
         self.backend = backend
         self.max_jobs = int(max_jobs)
         self.hbm_budget = int(hbm_budget)
@@ -138,6 +138,7 @@ class Server:
         self.t0 = None
         self.ticks = 0
         self.site_updates = 0
+        self.progress = progress  # called with the server after each finished request
 
     def now(self) -> float:
         return self.clock() - self.t0
@@ -178,6 +179,8 @@ class Server:
                     self.in_use -= self.backend.footprint(req.desc)
                     del self.active[slot]
                     self.done.append(req)
+                    if self.progress is not None:
+                        self.progress(self)
         self.ticks += 1
 
     def serve(self, requests, idle_sleep: float = 1e-3, max_seconds: float | None = None) -> dict:
@@ -200,6 +203,7 @@ class Server:
     def report(self) -> dict:
         lat = [r.latency for r in self.done]
         svc = [r.service for r in self.done]
+        conv = [r.latency for r in self.done if r.state.get("converged")]
         wall = self.now() if self.t0 is not None else math.nan
         return {
             "jobs": len(self.done),
@@ -208,8 +212,11 @@ class Server:
             "site_updates_per_s": self.site_updates / wall if wall and wall > 0 else math.nan,
             "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
             "service_p50_s": percentile(svc, 50), "service_p99_s": percentile(svc, 99),
+            "converged_latency_p50_s": percentile(conv, 50), "converged_latency_p99_s": percentile(conv, 99),
             "converged": sum(1 for r in self.done if r.state.get("converged")),
             "capped": sum(1 for r in self.done if not r.state.get("converged") and not r.state.get("nonfinite")),
             "nonfinite": sum(1 for r in self.done if r.state.get("nonfinite")),
             "ticks": self.ticks,
+            "at_cap_fraction": (sum(1 for r in self.done if not r.state.get("converged")
+                                    and not r.state.get("nonfinite")) / len(self.done)) if self.done else math.nan,
         }

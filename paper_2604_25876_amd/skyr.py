@@ -109,6 +109,29 @@ class AnfState(ctypes.Structure):
         return {k: (getattr(self, k)) for k, _ in self._fields_ if not k.startswith("_")}
 
 
+class Block(ctypes.Structure):
+    """Mirror of skyr_block: the whole lattice, the block's first own site per axis and
+    its own sites per axis.  Block fields are stored padded, extent + 8 sites per axis."""
+    _fields_ = [("lattice", Lattice), ("origin", ctypes.c_int32 * 3), ("extent", ctypes.c_int32 * 3)]
+
+    @classmethod
+    def of(cls, lat: Lattice, origin, extent) -> "Block":
+        return cls(lat, (ctypes.c_int32 * 3)(*origin), (ctypes.c_int32 * 3)(*extent))
+
+    @property
+    def padded_shape(self) -> tuple[int, int, int]:
+        return tuple(int(e) + 8 for e in self.extent)
+
+
+class BlockSums(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("E", "E2", "E4", "E0", "E6", "power", "max_force")]
+
+    def as_dict(self) -> dict:
+        return {k: float(getattr(self, k)) for k, _ in self._fields_}
+
+
+BLOCK_GRADIENT, BLOCK_STEP = 0, 1
+
 _lib = None
 
 # exported symbols and their signatures (the list the ABI tests check)
@@ -160,6 +183,12 @@ _SIGNATURES = {
     "skyr_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
     "skyr_batch_active": (ctypes.c_int32, [_P]),
     "skyr_batch_destroy": (ctypes.c_int, [_P]),
+    "skyr_block_sites": (ctypes.c_int64, [ctypes.POINTER(Block)]),
+    "skyr_block_shell_sites": (ctypes.c_int64, [ctypes.POINTER(Block)]),
+    "skyr_block_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Block), ctypes.c_int]),
+    "skyr_block_sweep": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.POINTER(Model), ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
+                                        _P, ctypes.POINTER(BlockSums), _P, _P]),
     "skyr_timing_enable": (None, [ctypes.c_int32]),
     "skyr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -336,6 +365,47 @@ def anf_step_noalloc(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi
                                        _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
                                        _dev_ptr(vel, dt, shape), ctypes.byref(state), int(nsteps), _stream(stream)))
     return state
+
+
+def block_sites(blk: Block) -> int:
+    return int(lib().skyr_block_sites(ctypes.byref(blk)))
+
+
+def block_shell_sites(blk: Block) -> int:
+    return int(lib().skyr_block_shell_sites(ctypes.byref(blk)))
+
+
+def block_workspace_bytes(blk: Block, prec: int) -> int:
+    return int(lib().skyr_block_workspace_bytes(ctypes.byref(blk), prec))
+
+
+def new_block_field(blk: Block, prec: int, device="cuda"):
+    import torch
+    return torch.zeros((4,) + blk.padded_shape, dtype=field_dtype(prec), device=device)
+
+
+def new_block_workspace(blk: Block, prec: int, device="cuda"):
+    import torch
+    return torch.zeros(block_workspace_bytes(blk, prec), dtype=torch.uint8, device=device)
+
+
+def block_sweep(blk: Block, prec: int, model: Model, mode: int, phi, shell, out, vel=None, work=None,
+                projected: bool = False, dt: float = 0.0, redo: bool = False, renorm64: bool = False,
+                want_sums: bool = True, stream=None):
+    """skyr_block_sweep: one sweep over a block's own interior sites (gradient or one
+    kick-drift step) with its shell written from `shell`; returns the block's sums
+    (a dict) when want_sums, else None."""
+    shape = (4,) + blk.padded_shape
+    dt_ = field_dtype(prec)
+    if work is None or not work.is_cuda or work.numel() * work.element_size() < block_workspace_bytes(blk, prec):
+        raise ValueError("a device workspace of block_workspace_bytes(blk, prec) bytes is required")
+    sums = BlockSums()
+    _check(lib().skyr_block_sweep(ctypes.byref(blk), prec, ctypes.byref(model), int(mode), int(bool(projected)),
+                                  float(dt), int(bool(redo)), int(bool(renorm64)), _dev_ptr(phi, dt_, shape),
+                                  _dev_ptr(shell, dt_, (4, block_shell_sites(blk))), _dev_ptr(out, dt_, shape),
+                                  _dev_ptr(vel, dt_, shape), ctypes.byref(sums) if want_sums else None,
+                                  ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+    return sums.as_dict() if want_sums else None
 
 
 def observables(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> dict:
