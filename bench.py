@@ -33,10 +33,11 @@ BYTES_PER_SITE = {"f32": 4 * 4 * 4, "f64": 4 * 4 * 8}
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the sources the sweep kernel is built from."""
+    """sha256 over the sources the sweep kernel is built from: its code and the list of
+    compiled tile shapes (the host runtime around it does not change what it does)."""
     import hashlib
     hsh = hashlib.sha256()
-    for f in ("sweep.hpp", "skyr.hip"):
+    for f in ("sweep.hpp", "shapes.hpp"):
         with open(os.path.join(ROOT, "paper_2604_25876_amd", "csrc", f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()
@@ -170,6 +171,30 @@ def run_flow(skyr, torch, w, prec_name, steps, warmup, tile=None, masses=None, m
         achieved_GBs=achieved, E=obs["E"], B=obs["B"], max_force=obs["max_force"],
         arrest=rule, tile={"variant": tile[0], "shape": skyr.tile_variants(prec)[tile[0]], "xchunk": tile[1]},
         traffic=recorded_traffic(prec_name, tile), valu=valu_roofline(prec_name, tile, kernel_avg_s))
+
+
+def hedgehog_40_smoke(skyr, torch):
+    """The hedgehog-40 configuration as specified (FP64, dt = 0.1, 300 arrested steps from
+    the B = 1 hedgehog on 40^3 at h = 0.2): the arrests it takes, where its energy goes and
+    the wall time of the 300 steps."""
+    from skyr_inputs import HEDGEHOG_40 as w
+    lat = skyr.Lattice.cube(w["n"], w["h"])
+    spec, keep = skyr.spec_from_description(w["init"])
+    dev = torch.device("cuda:0")
+    phi = skyr.new_field(lat, skyr.F64, dev)
+    skyr.init_field(lat, skyr.F64, spec, phi)
+    alt, vel = skyr.new_field(lat, skyr.F64, dev), skyr.new_field(lat, skyr.F64, dev)
+    work = skyr.new_workspace(lat, skyr.F64, dev)
+    E0 = skyr.observables(lat, skyr.F64, skyr.Model(w["m"]), phi, work)["E"]
+    flow = skyr.Flow(w["dt"], w["tol"], w["steps"], 0, skyr.flow_mode("energy"))
+    st = skyr.anf_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    skyr.anf_step(lat, skyr.F64, skyr.Model(w["m"]), flow, phi, alt, vel, st, w["steps"], work)
+    wall = time.perf_counter() - t0
+    obs = skyr.observables(lat, skyr.F64, skyr.Model(w["m"]), phi, work)
+    return {"workload": w["name"], "dt": w["dt"], "steps": st.steps, "arrests": st.arrests, "sweeps": st.sweeps,
+            "E_start": E0, "E_end": obs["E"], "B_end": obs["B"], "max_force_end": obs["max_force"], "wall_s": wall}
 
 
 def time_moments(skyr, torch, w, prec_name, reps=5):
@@ -410,6 +435,8 @@ def main():
     print(f"# f32-bulk, printed form: {rform}", file=sys.stderr, flush=True)
     moments = {p: time_moments(skyr, torch, W, p) for p in ("f32", "f64")}
     print(f"# moments: {moments}", file=sys.stderr, flush=True)
+    c1 = hedgehog_40_smoke(skyr, torch)
+    print(f"# hedgehog-40 as specified: {c1}", file=sys.stderr, flush=True)
     batch = serve = None
     if not args.no_batch:
         from skyr_inputs import batch_jobs
@@ -457,6 +484,7 @@ def main():
                              "sweep_kernel_avg_us": rform["sweep_kernel_avg_us"], "steps": rform["steps"],
                              "E": rform["E"]},
         "moments": moments,
+        "hedgehog_40_as_specified": c1,
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

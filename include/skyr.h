@@ -58,7 +58,15 @@ typedef enum {
     SKYR_E_IO = -6         /* a file could not be opened, read or written    */
 } skyr_status;
 
-typedef enum {
+/* The precision crosses the ABI as an argument: in C++ its type has a fixed 32-bit
+ * representation, so that every int32_t a caller passes is a value of it and an unknown
+ * one can be checked and rejected (C enums are int-sized already). */
+#ifdef __cplusplus
+#define SKYR_ENUM_INT32 : int32_t
+#else
+#define SKYR_ENUM_INT32
+#endif
+typedef enum SKYR_ENUM_INT32 {
     SKYR_F64 = 0,      /* fields, velocities and stencils in double                        */
     SKYR_F32_BULK = 1  /* fields, velocities and stencils in float; energy and charge sums,
                           the arrest comparison and a periodic renormalisation in double  */

@@ -29,15 +29,20 @@ _LIB = _HERE / "liboracle.so"
 _lib = None
 
 
-def build(force: bool = True) -> Path:
-    """Compile the oracle with gcc (plain IEEE double, OpenMP over planes)."""
-    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
-        tmp = _LIB.with_suffix(".so.tmp")
+def build(force: bool = True, sanitize: bool = False, out: Path | None = None) -> Path:
+    """Compile the oracle with gcc (plain IEEE double, OpenMP over planes).  sanitize: with
+    AddressSanitizer and UndefinedBehaviorSanitizer (into `out`; load that build with
+    SKYR_ORACLE_LIB=<out> and gcc's libasan preloaded)."""
+    lib = Path(out) if out is not None else (_HERE / "liboracle_san.so" if sanitize else _LIB)
+    if force or not lib.exists() or lib.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = lib.with_suffix(".so.tmp")
+        extra = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"] if sanitize else []
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", *extra,
              "-o", str(tmp), str(_SRC), "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class AnfState(ctypes.Structure):
@@ -64,9 +69,13 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
-        build(force=True)
-    lib = ctypes.CDLL(str(_LIB))
+    override = os.environ.get("SKYR_ORACLE_LIB")  # another build to load (the sanitizer runs)
+    if override:
+        lib = ctypes.CDLL(override)
+    else:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build(force=True)
+        lib = ctypes.CDLL(str(_LIB))
     i3 = ctypes.POINTER(ctypes.c_int)
     dp = ctypes.POINTER(ctypes.c_double)
     d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32

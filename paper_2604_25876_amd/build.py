@@ -9,7 +9,8 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 SOURCES = [PKG / "csrc" / "skyr.hip"]
-DEPS = SOURCES + [PKG / "csrc" / "sweep.hpp", PKG / "csrc" / "moments.hpp", PKG / "csrc" / "formp.hpp", ROOT / "include" / "skyr.h"]
+DEPS = SOURCES + [PKG / "csrc" / n for n in ("sweep.hpp", "shapes.hpp", "moments.hpp", "formp.hpp")] + \
+    [ROOT / "include" / "skyr.h"]
 LIB = PKG / "libskyr.so"
 
 HIPCC_FLAGS = [
@@ -30,6 +31,38 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> Path:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_sanitized(out: Path, verbose: bool = False) -> Path:
+    """The library with AddressSanitizer and UndefinedBehaviorSanitizer in its host code,
+    for runs of the CPU tests over the host runtime (argument checks, planning, files,
+    host-side draws); nothing in such a run launches a kernel.  The device code is built
+    without sanitizers and with one tile shape per precision, which keeps the build short.
+    Load it with SKYR_LIB=<out> and the clang ASan runtime preloaded."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    out = Path(out)
+    tmp = out.with_suffix(".so.tmp")
+    cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fvisibility=hidden",
+           "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined",
+           "-DSKYR_SHAPES_F64(X)=X(4, 4, 1, 16, 1, 1.0)", "-DSKYR_SHAPES_F32(X)=X(8, 4, 1, 32, 1, 1.0)",
+           "-I", str(ROOT / "include"), "-o", str(tmp), *map(str, SOURCES)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime that a SKYR_LIB sanitizer build needs preloaded."""
+    root = Path(os.environ.get("ROCM_PATH", "/opt/rocm")) / "llvm" / "lib" / "clang"
+    found = sorted(root.glob("*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise FileNotFoundError(f"no libclang_rt.asan-x86_64.so under {root}")
+    return str(found[-1])
 
 
 def stale() -> bool:

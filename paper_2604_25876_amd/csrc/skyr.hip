@@ -46,22 +46,20 @@ static skyr_status fail(skyr_status s, const std::string& msg)
 // has one block per (slab, tile) item, so that the blocks of neighbouring tiles
 // march through the same planes together and share their halo lines in L2.  The
 // choice for a (lattice, precision) pair is a process-wide setting
-// (skyr_set_tile / skyr_autotune).
+// (skyr_set_tile / skyr_autotune).  The last entry of a shape is the relative time of one
+// output site and plane of an item in a full round of the chip (measured at 256^3; a shape
+// that puts two blocks on a CU takes about twice as long per item), for the default choice.
 struct Shape {
     int nwi, nwh, hpt, cols;
-    int per_cu;  // blocks resident on one CU (LDS and registers)
+    int per_cu;   // blocks resident on one CU (LDS and registers)
+    double cost;  // relative time per output site and plane
     int threads() const { return (nwi + nwh) * 64; }
     int oy() const { return nwi * 64 / cols; }
     int oz() const { return cols; }
 };
 
-#ifndef SKYR_SHAPES_F64
-#define SKYR_SHAPES_F64(X) X(4, 4, 1, 16, 1) X(4, 4, 1, 32, 1) X(6, 2, 2, 32, 1)
-#endif
-#ifndef SKYR_SHAPES_F32
-#define SKYR_SHAPES_F32(X) X(8, 4, 1, 32, 1) X(6, 2, 2, 32, 2) X(12, 4, 1, 32, 1)
-#endif
-#define SKYR_SHAPE_ENTRY(a, b, c, d, e) Shape{a, b, c, d, e},
+#include "shapes.hpp"
+#define SKYR_SHAPE_ENTRY(a, b, c, d, e, f) Shape{a, b, c, d, e, f},
 static const Shape kShapesF64[] = {SKYR_SHAPES_F64(SKYR_SHAPE_ENTRY)};
 static const Shape kShapesF32[] = {SKYR_SHAPES_F32(SKYR_SHAPE_ENTRY)};
 constexpr int kMinChunk = 16;  // shortest slab (planes)
@@ -119,16 +117,9 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
     return L;
 }
 
-// Relative time of one output site and plane of an item, in a full round of the chip, for
-// each compiled shape in the order of the shape lists (measured at 256^3; a shape that
-// puts two blocks on a CU takes about twice as long per item).
-static const double kShapeCostF64[] = {1.0, 1.02, 0.95};
-static const double kShapeCostF32[] = {1.0, 2.0, 0.9};
 // a launch of more than one round loses some of the lockstep between neighbouring tiles
 // and ends with a partly idle round
 constexpr double kMultiRoundCost = 1.15;
-static_assert(sizeof(kShapeCostF64) / sizeof(double) == sizeof(kShapesF64) / sizeof(Shape), "one cost per shape");
-static_assert(sizeof(kShapeCostF32) / sizeof(double) == sizeof(kShapesF32) / sizeof(Shape), "one cost per shape");
 
 // Estimated sweep cost of shape v with the even split of x into `slabs` slabs: rounds of
 // the chip times the (padded) work of one item, the march's four extra planes included.
@@ -143,7 +134,7 @@ static double plan_cost(const skyr_lattice* lat, skyr_precision prec, int v, int
     const long long per_round = (long long)kCUs * sh.per_cu;
     const long long rounds = (items + per_round - 1) / per_round;
     return (double)rounds * (rounds > 1 ? kMultiRoundCost : 1.0) * sh.oy() * sh.oz() * (xc + 4) *
-           (prec == SKYR_F64 ? kShapeCostF64[v] : kShapeCostF32[v]);
+           sh.cost;
 }
 
 // Tile shape and slab length of a lattice the autotuner has not seen: the pair of least
@@ -445,13 +436,13 @@ static hipError_t sweep(skyr_precision prec, int mode, const Launch& L, const Sw
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_CASE64(a, b, c, d, e)                                                                          \
+#define SKYR_CASE64(a, b, c, d, e, f)                                                                          \
     if (L.variant == v) return launch_shape<double, Geo<a, b, c, d>>(mode, L, args, s);                      \
     ++v;
         SKYR_SHAPES_F64(SKYR_CASE64)
 #undef SKYR_CASE64
     } else {
-#define SKYR_CASE32(a, b, c, d, e)                                                                          \
+#define SKYR_CASE32(a, b, c, d, e, f)                                                                          \
     if (L.variant == v) return launch_shape<float, Geo<a, b, c, d>>(mode, L, args, s);                       \
     ++v;
         SKYR_SHAPES_F32(SKYR_CASE32)
@@ -474,13 +465,13 @@ static const void* step_kernel(skyr_precision prec, int variant, int ext, int& t
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_S64(a, b, c, d, e)                                              \
+#define SKYR_S64(a, b, c, d, e, f)                                              \
     if (variant == v) return step_fn<double, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F64(SKYR_S64)
 #undef SKYR_S64
     } else {
-#define SKYR_S32(a, b, c, d, e)                                             \
+#define SKYR_S32(a, b, c, d, e, f)                                             \
     if (variant == v) return step_fn<float, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F32(SKYR_S32)
@@ -534,13 +525,13 @@ static const void* batch_kernel(skyr_precision prec, int variant, int ext, int& 
 {
     int v = 0;
     if (prec == SKYR_F64) {
-#define SKYR_B64(a, b, c, d, e)                                               \
+#define SKYR_B64(a, b, c, d, e, f)                                               \
     if (variant == v) return batch_fn<double, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F64(SKYR_B64)
 #undef SKYR_B64
     } else {
-#define SKYR_B32(a, b, c, d, e)                                              \
+#define SKYR_B32(a, b, c, d, e, f)                                              \
     if (variant == v) return batch_fn<float, Geo<a, b, c, d>>(ext, threads); \
     ++v;
         SKYR_SHAPES_F32(SKYR_B32)

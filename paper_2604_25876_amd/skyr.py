@@ -10,10 +10,13 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 from pathlib import Path
 
 _PKG = Path(__file__).resolve().parent
-LIB_PATH = _PKG / "libskyr.so"
+# SKYR_LIB names another build of the library to load instead (the sanitizer runs of the
+# CPU tests use it)
+LIB_PATH = Path(os.environ.get("SKYR_LIB") or (_PKG / "libskyr.so"))
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE, E_BUSY, E_IO = 0, -1, -2, -3, -4, -5, -6
 FILE_BINARY, FILE_TEXT = 0, 1

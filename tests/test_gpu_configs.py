@@ -1,0 +1,108 @@
+"""GPU: the evaluation configurations run as specified and compared with the oracle.
+
+hedgehog-40 (B = 1 hedgehog, 40^3, h = 0.2, m = 1, FP64, dt = 0.1, 300 arrested steps):
+at this step the leapfrog is past its stability bound in the soliton core, the energy
+climbs to several times its start before the arrests tame it and the soliton unwinds.
+The device flow must follow the oracle's step by step -- the same arrest decisions, the
+energy of every step within 1e-11 -- until rounding differences, which such a flow
+amplifies, first change an arrest decision.
+
+cube-b4-128 (the O_h B = 4 rational map of Table RMA, profile pi exp(-r/1.5), 128^3,
+h = 0.15, m = 1, dt = 0.015, max|F| < 1e-4 within 5000 steps): the FP64 flow with the
+energy rule converges to the oracle's energy within 1e-8 and charge within 1e-6, and the
+FP32-bulk flow (power rule, tolerance no less than twice the single-precision force floor)
+to its energy within 1e-6 and charge within 1e-3.  The oracle's relaxation is stored in
+tests/golden/cube_b4_128_oracle.json (written by tests/golden/make_oracle_goldens.py)."""
+import json
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+from skyr_inputs import CUBE_B4_128, HEDGEHOG_40, f32_tolerance
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+GOLDEN = Path(__file__).resolve().parent / "golden" / "cube_b4_128_oracle.json"
+
+
+@pytest.fixture(scope="module")
+def skyr():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2604_25876_amd import skyr as s
+    s.lib()
+    return s
+
+
+def test_hedgehog_40_as_specified_follows_the_oracle(skyr):
+    w = HEDGEHOG_40
+    n, h, m, dt, steps = w["n"], w["h"], w["m"], w["dt"], w["steps"]
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(w["init"])
+    phi = skyr.new_field(lat, skyr.F64, DEV)
+    skyr.init_field(lat, skyr.F64, spec, phi)
+    alt, vel = skyr.new_field(lat, skyr.F64, DEV), skyr.new_field(lat, skyr.F64, DEV)
+    work = skyr.new_workspace(lat, skyr.F64, DEV)
+    flow = skyr.Flow(dt, 0.0, steps, 0, skyr.flow_mode("energy"))
+    st = skyr.anf_state()
+    E_dev, reset_dev = [], []
+    for k in range(steps):
+        a0 = st.arrests
+        skyr.anf_step(lat, skyr.F64, skyr.Model(m), flow, phi, alt, vel, st, 1, work)
+        assert st.steps == k + 1
+        E_dev.append(st.E)  # E of the field the step started from
+        reset_dev.append(int(st.arrests - a0))
+    phi0 = oracle.init_product((n,) * 3, h, [oracle.hedgehog(prof_a=math.pi, prof_lambda=w["init"]["prof_lambda"])])
+    _, _, ost, E_ora, reset_ora = oracle.anf(phi0, np.zeros_like(phi0), h, m, dt, 0.0, steps, rule="energy",
+                                             trace=True)
+    assert ost.steps == steps and len(E_ora) == steps
+    E_dev, reset_dev = np.array(E_dev), np.array(reset_dev)
+    differ = np.flatnonzero(reset_dev != reset_ora)
+    first = int(differ[0]) if len(differ) else steps
+    print(f"hedgehog-40 dt=0.1: oracle E {E_ora[0]:.6f} -> max {E_ora.max():.4f} -> {E_ora[-1]:.6f}, "
+          f"{int(reset_ora.sum())} arrests; device {int(reset_dev.sum())} arrests; "
+          f"first differing arrest decision at step {first}")
+    rel = np.abs(E_dev[:first] - E_ora[:first]) / np.abs(E_ora[:first])
+    assert first >= 100, f"arrest decisions part at step {first}"
+    assert rel.max() <= 1e-11, f"energies part by {rel.max():.2e} before the arrests do"
+
+
+def _relax_cube(skyr, prec, rule, tol):
+    w = CUBE_B4_128
+    lat = skyr.Lattice.cube(w["n"], w["h"])
+    spec, keep = skyr.spec_from_description(w["init"])
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    flow = skyr.Flow(w["dt"], tol, w["steps"], 16, skyr.flow_mode(rule))
+    st = skyr.anf_state()
+    skyr.anf_step(lat, prec, skyr.Model(w["m"]), flow, phi, alt, vel, st, w["steps"], work)
+    return st, skyr.observables(lat, prec, skyr.Model(w["m"]), phi, work)
+
+
+def test_cube_b4_128_f64_matches_the_oracle_relaxation(skyr):
+    g = json.loads(GOLDEN.read_text())
+    st, obs = _relax_cube(skyr, skyr.F64, "energy", CUBE_B4_128["tol"])
+    print(f"cube-b4-128 FP64: device {st.steps} steps {st.arrests} arrests E {obs['E']:.12f}; "
+          f"oracle {g['steps']} steps {g['arrests']} arrests E {g['observables']['E']:.12f}")
+    assert st.converged and g["converged"]
+    assert obs["E"] == pytest.approx(g["observables"]["E"], rel=1e-8)
+    assert abs(obs["B"] - g["observables"]["B"]) <= 1e-6
+    for k in ("E2", "E4", "E0", "virial"):
+        assert obs[k] == pytest.approx(g["observables"][k], rel=1e-6, abs=1e-6), k
+
+
+def test_cube_b4_128_f32_bulk_matches_the_oracle_relaxation(skyr):
+    g = json.loads(GOLDEN.read_text())
+    tol = f32_tolerance(CUBE_B4_128["tol"], CUBE_B4_128["h"])
+    st, obs = _relax_cube(skyr, skyr.F32_BULK, "power", tol)
+    print(f"cube-b4-128 FP32-bulk: {st.steps} steps {st.arrests} arrests E {obs['E']:.9f} B {obs['B']:.6f} "
+          f"(oracle FP64 E {g['observables']['E']:.9f} B {g['observables']['B']:.6f})")
+    assert st.converged
+    assert obs["E"] == pytest.approx(g["observables"]["E"], rel=1e-6)
+    assert abs(obs["B"] - g["observables"]["B"]) <= 1e-3
