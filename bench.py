@@ -59,20 +59,19 @@ def recorded_traffic(prec_name, tile):
     """HBM bytes per sweep launch from the committed counter summary, or None.
 
     The summary holds `key: value` lines (FETCH_SIZE and WRITE_SIZE in KiB per
-    dispatch, the scale factors a plain copy of known size gives for each
-    counter, the tile and the kernel-source hash the counters were taken
-    with).  Counters taken on other kernel sources or another tile do not
-    describe this launch and give None."""
+    dispatch per tile `<prec>_<variant>_<planes per slab>_...`, the scale factors a
+    plain copy of known size gives for each counter and the kernel-source hash the
+    counters were taken with).  Counters taken on other kernel sources or for another
+    tile do not describe this launch and give None."""
     kv = _summary("sweep_traffic_random-b10-256.md")
     if not kv:
         return None
     if kv.get("source_sha256") != kernel_source_hash():
         return None
-    if kv.get(f"{prec_name}_tile") != f"{tile[0]}:{tile[1]}":
-        return None
+    key = f"{prec_name}_{tile[0]}_{tile[1]}"
     try:
-        fetch = float(kv[f"{prec_name}_fetch_kib"]) * float(kv["fetch_scale"])
-        write = float(kv[f"{prec_name}_write_kib"]) * float(kv["write_scale"])
+        fetch = float(kv[f"{key}_fetch_kib"]) * float(kv["fetch_scale"])
+        write = float(kv[f"{key}_write_kib"]) * float(kv["write_scale"])
     except (KeyError, ValueError):
         return None
     return 1024.0 * (fetch + write)
@@ -89,10 +88,8 @@ def recorded_valu(prec_name, tile):
     kv = _summary("sweep_instructions_random-b10-256.md")
     if not kv or kv.get("source_sha256") != kernel_source_hash():
         return None
-    if kv.get(f"{prec_name}_tile") != f"{tile[0]}:{tile[1]}":
-        return None
     try:
-        return float(kv[f"{prec_name}_valu_per_launch"])
+        return float(kv[f"{prec_name}_{tile[0]}_{tile[1]}_valu_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -334,9 +331,46 @@ def served_stream(skyr, torch, count=128, cap=20000, rate=None, throughput=None,
     return rep
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle (as it stands) on the host cores: a few flow steps of the
-    same 256^3 initial field, scaled to site-updates/s."""
+def host_cpu() -> dict:
+    """The host's CPU model, sockets and logical CPUs (from /proc/cpuinfo)."""
+    model, sockets, logical = None, set(), 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    sockets.add(v)
+    except OSError:
+        pass
+    return {"model": model, "sockets": len(sockets) or None, "logical_cpus": logical or os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def _oracle_rate(oracle, np, phi, h, m, dt, budget_s, max_steps):
+    """site-updates/s of the oracle's flow on phi: one untimed step, then as many steps as
+    fit the budget (at least one); returns (rate, steps, seconds)."""
+    vel = np.zeros_like(phi)
+    st = oracle.AnfState.fresh()
+    t0 = time.perf_counter()
+    phi, vel, st, _, _ = oracle.anf(phi, vel, h, m, dt, 0.0, 1, st)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(max_steps, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    phi, vel, st, _, _ = oracle.anf(phi, vel, h, m, dt, 0.0, 1 + k, st)
+    tk = time.perf_counter() - t0
+    interior = np.prod([s - 4 for s in phi.shape[1:]])
+    return k * interior / tk, k, tk
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The FP64 oracle (as it stands) on the host: flow steps of the same 256^3 initial
+    field with all its threads (the reported value), and of the cube-b4-128 input with all
+    threads and with one; site-updates/s each."""
     import math
 
     import numpy as np
@@ -346,19 +380,26 @@ def cpu_baseline(w, budget_s=15.0):
     init = w["init"]
     cs = oracle.random_constituents(init["seed"], init["B"], init["radius"], math.pi, init["prof_lambda"])
     phi = oracle.init_product((n, n, n), h, cs)
-    vel = np.zeros_like(phi)
-    st = oracle.AnfState.fresh()
-    t0 = time.perf_counter()
-    phi, vel, st, _, _ = oracle.anf(phi, vel, h, w["m"], w["dt"], 0.0, 1, st)
-    t1 = time.perf_counter() - t0
-    k = max(1, min(20, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    phi, vel, st, _, _ = oracle.anf(phi, vel, h, w["m"], w["dt"], 0.0, 1 + k, st)
-    tk = time.perf_counter() - t0
-    interior = (n - 4) ** 3
-    return {"value": k * interior / tk, "unit": "site-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+    threads = oracle.num_threads()
+    rate, k, tk = _oracle_rate(oracle, np, phi, h, w["m"], w["dt"], budget_s, 20)
+    from skyr_inputs import CUBE_B4_128 as c2
+    phi2 = oracle.init_product((c2["n"],) * 3, c2["h"],
+                               [oracle.cube_b4(prof_a=math.pi, prof_lambda=c2["init"]["prof_lambda"])])
+    rate2, k2, tk2 = _oracle_rate(oracle, np, phi2, c2["h"], c2["m"], c2["dt"], 4.0, 50)
+    # one thread, on the smaller field (the same work per site)
+    oracle.set_num_threads(1)
+    try:
+        rate1, k1, tk1 = _oracle_rate(oracle, np, phi2, c2["h"], c2["m"], c2["dt"], 4.0, 4)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} FP64 flow steps of the same {n}^3 random B=10 field after 1 untimed step "
-                      f"({tk:.1f} s)"}
+                      f"({tk:.1f} s, {threads} threads)",
+            "host": host_cpu(),
+            "one_thread": {"value": rate1, "sample": f"{k1} FP64 flow steps of the cube-b4-128 field "
+                                                     f"({tk1:.1f} s, 1 thread)"},
+            "cube_b4_128": {"value": rate2, "sample": f"{k2} FP64 flow steps of the cube-b4-128 field "
+                                                      f"({tk2:.1f} s, {threads} threads)"}}
 
 
 def main():
