@@ -406,7 +406,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=64,
+                    help="untimed steps before the timed region (64 also instantiate the flow's graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f32", "f64"], default=None,
                     help="time one precision only (profiling runs)")

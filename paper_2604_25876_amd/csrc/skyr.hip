@@ -173,6 +173,33 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
     return plan_with(lat, prec, v, xc);
 }
 
+// The printed-form sweep: its fixed tile shape, one block per (slab, tile) item, and the
+// slab length whose items cost least in rounds of the chip (as for the exact sweep).
+static Launch plan_printed(const skyr_lattice* lat, skyr_precision prec)
+{
+    const int oy = prec == SKYR_F64 ? FpGeoF64::OY : FpGeoF32::OY;
+    const int oz = prec == SKYR_F64 ? FpGeoF64::OZ : FpGeoF32::OZ;
+    Launch L{};
+    L.variant = 0;
+    L.shape = Shape{oy * oz / 64, 0, 0, oz, 1, 1.0};
+    tile_grid(lat, L.shape, L.tiles_y, L.tiles_z, L.zstart);
+    const int nx = lat->n[0] - 4, tiles = L.tiles_y * L.tiles_z;
+    const int most = std::max(1, std::min(kMaxSlabs, nx / kMinChunk));
+    double best = INFINITY;
+    for (int sl = 1; sl <= most; ++sl) {
+        const int xc = std::max(1, (nx + sl - 1) / sl);
+        const long long items = (long long)tiles * ((nx + xc - 1) / xc);
+        const long long rounds = (items + kCUs - 1) / kCUs;
+        const double c = (double)rounds * (rounds > 1 ? kMultiRoundCost : 1.0) * (xc + 4);
+        if (c < best * (1.0 - 1e-9)) {
+            best = c;
+            L.xchunk = xc;
+        }
+    }
+    L.slabs = (nx + L.xchunk - 1) / L.xchunk;
+    return L;
+}
+
 constexpr size_t CTL_BYTES = 256;
 // observables (8 doubles), then the moments' centre (4 doubles at +64) and result (at +128)
 constexpr size_t OBS_BYTES = 512;
@@ -187,7 +214,7 @@ static size_t workspace_bytes(const skyr_lattice* lat, skyr_precision prec)
 {
     int most = 0;
     for (int v = 0; v < shape_count(prec); ++v) most = std::max(most, plan_with(lat, prec, v, kMinChunk).blocks());
-    most = std::max(most, formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64));
+    most = std::max(most, plan_printed(lat, prec).blocks());
     const size_t sweep_part = (size_t)most * NPART * sizeof(double);
     const size_t mom_part = (size_t)MOM_MAX_BLOCKS * MOM_NACC * sizeof(double);
     return CTL_BYTES + OBS_BYTES + std::max(sweep_part, mom_part);
@@ -383,21 +410,6 @@ __global__ void observe_kernel(const double* __restrict__ part, int nblocks, dou
     }
 }
 
-// The separate finaliser of a sweep that does not take the decision itself (the printed
-// form): fixed-order reduction, then the flow's decision.
-__device__ static void finalize_flow(const double* __restrict__ part, Ctl* __restrict__ ctl)
-{
-    if (ctl->done) {  // uniform
-        // the sweep just before this one restored v_k after convergence
-        if (threadIdx.x == 0 && ctl->restore) ctl->restore = RESTORE_NONE;
-        return;
-    }
-    double s[NRED];
-    reduce_partials(part, ctl->nblocks, s);
-    if (threadIdx.x == 0) flow_decide(s, ctl);
-}
-
-__global__ void finalize_kernel(const double* __restrict__ part, Ctl* __restrict__ ctl) { finalize_flow(part, ctl); }
 
 // ------------------------------------------------------------- launches
 // the kernel variant with the extra potentials and the gradient flow is used only
@@ -481,34 +493,28 @@ static const void* step_kernel(skyr_precision prec, int variant, int ext, int& t
     return nullptr;
 }
 
-template <typename T>
-static void launch_printed(int mode, bool ext, dim3 grid, dim3 block, const SweepArgs& args, hipStream_t s)
+template <typename T> static const void* printed_fn(int mode, bool ext)
 {
-    if (mode == MODE_STEP) {
-        if (ext)
-            hipLaunchKernelGGL((formp_kernel<T, MODE_STEP, true>), grid, block, 0, s, args);
-        else
-            hipLaunchKernelGGL((formp_kernel<T, MODE_STEP, false>), grid, block, 0, s, args);
-    } else {
-        if (ext)
-            hipLaunchKernelGGL((formp_kernel<T, MODE_GRAD, true>), grid, block, 0, s, args);
-        else
-            hipLaunchKernelGGL((formp_kernel<T, MODE_GRAD, false>), grid, block, 0, s, args);
-    }
+    if (mode == MODE_STEP)
+        return ext ? (const void*)formp_kernel<T, MODE_STEP, true> : (const void*)formp_kernel<T, MODE_STEP, false>;
+    return ext ? (const void*)formp_kernel<T, MODE_GRAD, true> : (const void*)formp_kernel<T, MODE_GRAD, false>;
 }
 
-// The printed-form sweep: one launch over formp_blocks() blocks.
-static hipError_t sweep_printed(skyr_precision prec, int mode, const skyr_lattice* lat, SweepArgs args, hipStream_t s)
+// the printed-form kernel of a precision and mode for arguments a, and its block size
+static const void* printed_kernel(skyr_precision prec, int mode, const SweepArgs& a, int& threads)
 {
-    const bool dbl = prec == SKYR_F64;
-    args.xchunk = formp_chunk(lat->n[0], lat->n[1], lat->n[2], dbl);
-    const dim3 grid(formp_blocks(lat->n[0], lat->n[1], lat->n[2], dbl)), block(FP_THREADS);
-    const bool ext = ext_level(args) != EXT_NONE;
-    if (prec == SKYR_F64)
-        launch_printed<double>(mode, ext, grid, block, args, s);
-    else
-        launch_printed<float>(mode, ext, grid, block, args, s);
-    return hipGetLastError();
+    const bool ext = ext_level(a) != EXT_NONE;
+    threads = prec == SKYR_F64 ? FpGeoF64::THREADS : FpGeoF32::THREADS;
+    return prec == SKYR_F64 ? printed_fn<double>(mode, ext) : printed_fn<float>(mode, ext);
+}
+
+// The printed-form sweep: one launch, arguments made by make_args with plan_printed's launch.
+static hipError_t sweep_printed(skyr_precision prec, int mode, const Launch& L, const SweepArgs& args, hipStream_t s)
+{
+    int threads = 0;
+    const void* fn = printed_kernel(prec, mode, args, threads);
+    void* argv[1] = {const_cast<SweepArgs*>(&args)};
+    return hipLaunchKernel(fn, dim3(L.blocks()), dim3(threads), argv, 0, s);
 }
 
 // The batched-sweep kernel of one (precision, tile shape) group at a kernel variant, and
@@ -798,7 +804,8 @@ skyr_status skyr_init_field(const skyr_lattice* lat, skyr_precision prec, const 
 static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const void* phi,
                                 void* grad, int projected, int baryon, double obs_out[7], void* work, hipStream_t s)
 {
-    const Launch L = plan(lat, prec);
+    const bool printed = model->form == SKYR_FORM_PRINTED;
+    const Launch L = printed ? plan_printed(lat, prec) : plan(lat, prec);
     SweepArgs a = make_args(lat, L, model, 0.0);
     a.phi0 = phi;
     a.grad = grad;
@@ -808,14 +815,12 @@ static skyr_status run_gradient(const skyr_lattice* lat, skyr_precision prec, co
     a.partials = (double*)(w + CTL_BYTES + OBS_BYTES);
     double* obs = (double*)(w + CTL_BYTES);
     if (grad) SKYR_HIP(fill(grad, 4 * sites(lat), prec, 0.0, s));
-    const bool printed = model->form == SKYR_FORM_PRINTED;
     if (printed)
-        SKYR_HIP(sweep_printed(prec, MODE_GRAD, lat, a, s));
+        SKYR_HIP(sweep_printed(prec, MODE_GRAD, L, a, s));
     else
         SKYR_HIP(sweep(prec, MODE_GRAD, L, a, s));
     if (obs_out) {
-        const int nb = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64) : L.blocks();
-        hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, nb, lat->h, obs);
+        hipLaunchKernelGGL(observe_kernel, dim3(1), dim3(256), 0, s, a.partials, L.blocks(), lat->h, obs);
         SKYR_HIP(hipGetLastError());
         SKYR_HIP(hipMemcpyAsync(obs_out, obs, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         SKYR_HIP(hipStreamSynchronize(s));
@@ -979,21 +984,21 @@ static skyr_status check_flow(const skyr_lattice* lat, skyr_precision prec, cons
 // sums of the sweep it launches
 static size_t flow_work_bytes(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model)
 {
-    const int nb = model->form == SKYR_FORM_PRINTED ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64)
-                                                    : plan(lat, prec).blocks();
+    const int nb = model->form == SKYR_FORM_PRINTED ? plan_printed(lat, prec).blocks() : plan(lat, prec).blocks();
     return CTL_BYTES + OBS_BYTES + (size_t)nb * NPART * sizeof(double);
 }
 
 // ------------------------------------------------------------ flow graphs
-// The single-field exact-form flow replays its step sweeps in groups of kFlowGraphSweeps
-// from a graph instantiated once per launch (the sweep's arguments, tile shape, kernel
-// variant and device); a small cache keeps the most recently used.  Launches happen under
-// the cache lock, so that no graph is destroyed while another thread enqueues it.
+// The single-field flow replays its step sweeps in groups of kFlowGraphSweeps from a graph
+// instantiated once per launch (kernel, grid, block size, the sweep's arguments, device); a
+// small cache keeps the most recently used.  Launches happen under the cache lock, so that
+// no graph is destroyed while another thread enqueues it.
 constexpr int kFlowGraphSweeps = 32;
 constexpr size_t kFlowGraphCache = 8;
 struct FlowGraph {
     int device;
-    int prec, variant, ext;
+    const void* fn;
+    int grid, threads;
     SweepArgs args;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -1001,30 +1006,28 @@ struct FlowGraph {
 static std::mutex g_flow_graph_mu;
 static std::vector<FlowGraph> g_flow_graphs;  // least recently used first
 
-// enqueue reps x kFlowGraphSweeps step sweeps of the flow with arguments a on stream s
-static skyr_status flow_graph_launch(skyr_precision prec, const Launch& L, const SweepArgs& a, int reps,
+// enqueue reps x kFlowGraphSweeps launches of step kernel fn (grid x threads) with
+// arguments a on stream s
+static skyr_status flow_graph_launch(const void* fn, int grid, int threads, const SweepArgs& a, int reps,
                                      hipStream_t s)
 {
+    if (!fn) return fail(SKYR_E_INVAL, "no step kernel for this tile shape");
     int dev = 0;
     SKYR_HIP(hipGetDevice(&dev));
-    const int ext = ext_level(a);
     std::lock_guard<std::mutex> lock(g_flow_graph_mu);
     size_t i = 0;
     for (; i < g_flow_graphs.size(); ++i) {
         const FlowGraph& f = g_flow_graphs[i];
-        if (f.device == dev && f.prec == (int)prec && f.variant == L.variant && f.ext == ext &&
+        if (f.device == dev && f.fn == fn && f.grid == grid && f.threads == threads &&
             std::memcmp(&f.args, &a, sizeof a) == 0)
             break;
     }
     if (i == g_flow_graphs.size()) {
-        int threads = 0;
-        const void* fn = step_kernel(prec, L.variant, ext, threads);
-        if (!fn) return fail(SKYR_E_INVAL, "no step kernel for this tile shape");
-        FlowGraph f{dev, (int)prec, L.variant, ext, a, nullptr, nullptr};
+        FlowGraph f{dev, fn, grid, threads, a, nullptr, nullptr};
         void* argv[1] = {&f.args};
         hipKernelNodeParams p{};
         p.func = const_cast<void*>(fn);
-        p.gridDim = dim3(L.blocks());
+        p.gridDim = dim3(grid);
         p.blockDim = dim3(threads);
         p.sharedMemBytes = 0;
         p.kernelParams = argv;
@@ -1068,7 +1071,8 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
     if (st->converged || target <= st->steps) return SKYR_OK;
 
-    const Launch L = plan(lat, prec);
+    const bool printed = model->form == SKYR_FORM_PRINTED;
+    const Launch L = printed ? plan_printed(lat, prec) : plan(lat, prec);
     char* w = (char*)work;
     Ctl* ctl = (Ctl*)w;
     SweepArgs a = make_args(lat, L, model, flow->dt);
@@ -1089,8 +1093,7 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     h.sweeps = st->sweeps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
     h.flow_mode = flow->mode;
-    const bool printed = model->form == SKYR_FORM_PRINTED;
-    h.nblocks = printed ? formp_blocks(lat->n[0], lat->n[1], lat->n[2], prec == SKYR_F64) : L.blocks();
+    h.nblocks = L.blocks();
     h.E_prev = st->E_prev;
     h.E = st->E;
     h.max_force = st->max_force;
@@ -1111,23 +1114,25 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     }
     // sweeps are enqueued in groups; the host looks at the control block between groups
     // (sweeps after the flow has stopped return at once)
-    graphs = graphs && !printed && !(timed && g_timing.on);
+    graphs = graphs && !(timed && g_timing.on);
     const int64_t max_group = graphs ? 4 * kFlowGraphSweeps : 32;
     const int64_t remaining = target - st->steps;
     int64_t group = std::min<int64_t>(std::max<int64_t>(remaining, 1), max_group);
     int64_t budget = 2 * remaining + 2;  // every step takes at most one redo sweep
+    // (each sweep takes the flow's decision in its last block)
     auto enqueue_sweep = [&](bool timed) -> hipError_t {
         hipError_t e = timed ? timing_mark(s) : hipSuccess;
-        if (e == hipSuccess) e = printed ? sweep_printed(prec, MODE_STEP, lat, a, s) : sweep(prec, MODE_STEP, L, a, s);
+        if (e == hipSuccess) e = printed ? sweep_printed(prec, MODE_STEP, L, a, s) : sweep(prec, MODE_STEP, L, a, s);
         if (e == hipSuccess && timed) e = timing_mark(s);
-        if (e != hipSuccess || !printed) return e;  // the exact-form sweep takes the decision itself
-        hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a.partials, ctl);
-        return hipGetLastError();
+        return e;
     };
     for (;;) {
         if (graphs && group >= kFlowGraphSweeps) {
             const int reps = (int)(group / kFlowGraphSweeps);
-            const skyr_status rc = flow_graph_launch(prec, L, a, reps, s);
+            int threads = 0;
+            const void* fn = printed ? printed_kernel(prec, MODE_STEP, a, threads)
+                                     : step_kernel(prec, L.variant, ext_level(a), threads);
+            const skyr_status rc = flow_graph_launch(fn, L.blocks(), threads, a, reps, s);
             if (rc != SKYR_OK) return rc;
             group = (int64_t)reps * kFlowGraphSweeps;
         } else {

@@ -1028,8 +1028,9 @@ __device__ inline void flow_decide(const double* s, Ctl* ctl)
 // across the XCDs' L2 caches without a device-wide fence, which would write back and
 // invalidate the whole L2 of the block's XCD while its neighbours still read halo lines.
 // The fields of the control block other than the ticket change only between launches.
-template <typename T, class G>
-__device__ __forceinline__ void finish_step(const double* part, int nb, Ctl* ctl, bool restore, SweepSmem<T, G>& sm)
+// Smem: shared memory with `int last` and `double red[NW][NPART]`; THREADS threads in NW waves.
+template <int THREADS, int NW, class Smem>
+__device__ __forceinline__ void finish_step(const double* part, int nb, Ctl* ctl, bool restore, Smem& sm)
 {
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -1048,7 +1049,7 @@ __device__ __forceinline__ void finish_step(const double* part, int nb, Ctl* ctl
     double v[NRED];
 #pragma unroll
     for (int i = 0; i < NRED; ++i) v[i] = 0.0;
-    for (int b = tid; b < nb; b += G::THREADS) {
+    for (int b = tid; b < nb; b += THREADS) {
         const double* p = part + (size_t)b * NPART;
 #pragma unroll
         for (int i = 0; i < NRED; ++i) {
@@ -1071,7 +1072,7 @@ __device__ __forceinline__ void finish_step(const double* part, int nb, Ctl* ctl
         double sum[NRED];
 #pragma unroll
         for (int i = 0; i < NRED; ++i) sum[i] = 0.0;
-        for (int w = 0; w < G::NW; ++w)
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
             for (int i = 0; i < NRED; ++i) sum[i] = (i == P_F2) ? fmax(sum[i], sm.red[w][i]) : sum[i] + sm.red[w][i];
         flow_decide(sum, ctl);
@@ -1194,7 +1195,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
         double* o = a.partials + (size_t)b * NPART;
         for (int i = 0; i < 7; ++i) __hip_atomic_store(o + i, sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if constexpr (MODE == MODE_STEP) finish_step<T, G>(a.partials, nb, a.ctl, cm.restore != RESTORE_NONE, sm);
+    if constexpr (MODE == MODE_STEP) finish_step<G::THREADS, G::NW>(a.partials, nb, a.ctl, cm.restore != RESTORE_NONE, sm);
 }
 
 // Blocks are dispatched round-robin over the eight XCDs (block i to XCD i % 8).
