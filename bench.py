@@ -194,6 +194,51 @@ def hedgehog_40_smoke(skyr, torch):
             "E_start": E0, "E_end": obs["E"], "B_end": obs["B"], "max_force_end": obs["max_force"], "wall_s": wall}
 
 
+def block_share(skyr, torch, w, prec_name, reps=50):
+    """One device's share of the workload's lattice split 2 x 2 x 2: the step sweep over the
+    128^3 block at (128, 0, 128), its four-deep shell written from a separate buffer (what
+    the neighbouring devices would send), timed with HIP events around the sweep launches
+    (the shell fill is reported beside it)."""
+    prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
+    n, h = w["n"], w["h"]
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(w["init"])
+    dev = torch.device("cuda:0")
+    full = skyr.new_field(lat, prec, dev)
+    skyr.init_field(lat, prec, spec, full)
+    origin, extent = (n // 2, 0, n // 2), (n // 2,) * 3
+    blk = skyr.Block.of(lat, origin, extent)
+    idx = [torch.clamp(torch.arange(e + 8, device=dev) + o - 4, 0, n - 1) for o, e in zip(origin, extent)]
+    padded = full[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]].contiguous()
+    own = torch.zeros(padded.shape[1:], dtype=torch.bool, device=dev)
+    own[4:-4, 4:-4, 4:-4] = True
+    shell = padded[:, ~own].contiguous()
+    out, vel = torch.zeros_like(padded), torch.zeros_like(padded)
+    work = skyr.new_block_workspace(blk, prec, dev)
+    for _ in range(3):
+        skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, padded, shell, out, vel=vel, work=work,
+                         dt=w["dt"], want_sums=False)
+    torch.cuda.synchronize()
+    skyr.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, padded, shell, out, vel=vel, work=work,
+                         dt=w["dt"], want_sums=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, cnt = skyr.timing_read()
+    skyr.timing_enable(False)
+    us = 1e3 * ms / max(cnt, 1)
+    # the block's own sites in I, per axis the overlap of [origin, origin + extent) with [2, n - 2)
+    sites = 1
+    for o, e in zip(origin, extent):
+        sites *= max(0, min(o + e, n - 2) - max(o, 2))
+    eb = 4 if prec_name == "f32" else 8
+    return {"block": {"origin": list(origin), "extent": list(extent)}, "interior_sites": sites,
+            "sweep_kernel_avg_us": us, "achieved_GBs": 16 * eb * sites / us / 1e3,
+            "call_us": 1e6 * wall / reps, "site_updates_per_s": sites / (us / 1e6)}
+
+
 def time_moments(skyr, torch, w, prec_name, reps=5):
     """Wall time of skyr_moments (an observables sweep, then the two FP64
     moment passes; each call synchronises) on the workload's initial field."""
@@ -479,6 +524,8 @@ def main():
     print(f"# moments: {moments}", file=sys.stderr, flush=True)
     c1 = hedgehog_40_smoke(skyr, torch)
     print(f"# hedgehog-40 as specified: {c1}", file=sys.stderr, flush=True)
+    share = {p: block_share(skyr, torch, W, p) for p in ("f32", "f64")}
+    print(f"# one device's block of a 2x2x2 split: {share}", file=sys.stderr, flush=True)
     batch = serve = None
     if not args.no_batch:
         from skyr_inputs import batch_jobs
@@ -527,6 +574,7 @@ def main():
                              "E": rform["E"]},
         "moments": moments,
         "hedgehog_40_as_specified": c1,
+        "block_128_of_256": share,
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

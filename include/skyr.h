@@ -468,22 +468,26 @@ SKYR_API skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk);
 
 /* Autotuner: time every compiled shape with the slab lengths that split the
- * interior x-extent evenly into 1..24 slabs (at least 16 planes each) on this
+ * interior x-extent evenly into 1..8 slabs (at least 16 planes each) on this
  * lattice (flow sweeps, phi read, phi_alt and vel written; a candidate's time
- * is the median of five sweeps, and the four fastest are timed three more
- * times, interleaved, keeping their best median), keep the fastest with
- * skyr_set_tile and return it (outputs nullable; best_us is the sweep time in
- * microseconds).  phi is unchanged; phi_alt is scratch and vel is zero on
- * return.  Synchronises `stream`. */
+ * is the median of five sweeps, and the four fastest and the default choice are
+ * timed three more times, interleaved, keeping their best median), keep the
+ * fastest with skyr_set_tile -- the default choice unless the fastest beats it
+ * by 3% or more, about the spread of such timings between runs -- and return it
+ * (outputs nullable; best_us is its sweep time in microseconds).  phi is
+ * unchanged; phi_alt is scratch and vel is zero on return.  Synchronises
+ * `stream`. */
 SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                                    const skyr_flow* flow, const void* phi, void* phi_alt, void* vel, void* work,
                                    void* stream, int32_t* variant, int32_t* xchunk, double* best_us);
 
 /* Kernel timing for measurement tools.  skyr_timing_enable(1) resets and
  * starts recording a pair of HIP events around every sweep-kernel launch made
- * by skyr_anf_step on the calling thread (on the caller's stream); (0) stops.
- * skyr_timing_read returns the summed event time of those launches in
- * milliseconds and their count (either pointer may be null). */
+ * by skyr_anf_step and skyr_block_sweep on the calling thread (on the caller's
+ * stream; skyr_anf_step then launches every sweep directly instead of replaying
+ * graphs); (0) stops.  skyr_timing_read waits for the launches recorded so far
+ * and returns their summed event time in milliseconds and their count (either
+ * pointer may be null). */
 SKYR_API void skyr_timing_enable(int32_t on);
 SKYR_API skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches);
 

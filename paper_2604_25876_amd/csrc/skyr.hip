@@ -120,6 +120,8 @@ static Launch plan_with(const skyr_lattice* lat, skyr_precision prec, int varian
 // a launch of more than one round loses some of the lockstep between neighbouring tiles
 // and ends with a partly idle round
 constexpr double kMultiRoundCost = 1.15;
+// the autotuner replaces the default tile only by one at least this much faster
+constexpr double kAutotuneMargin = 0.97;
 
 // Estimated sweep cost of shape v with the even split of x into `slabs` slabs: rounds of
 // the chip times the (padded) work of one item, the march's four extra planes included.
@@ -1612,26 +1614,37 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     // the first candidate also warms the device clocks up before anything is compared
     hipError_t e = cands.empty() ? hipSuccess : time_one(cands[0], 24);
     for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) e = time_one(cands[i], 1);
-    // the closest candidates are timed again, interleaved, and keep their best median
+    // the closest candidates and the default choice are timed again, interleaved, and keep
+    // their best median
+    int dv = 0, dx = 0;
+    default_tile(lat, prec, dv, dx);
+    size_t di = cands.size();
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (cands[i].v == dv && cands[i].xc == dx) di = i;
     std::vector<size_t> order(cands.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cands[x].us < cands[y].us; });
-    const size_t top = std::min<size_t>(4, order.size());
+    order.resize(std::min<size_t>(4, order.size()));
+    if (di < cands.size() && std::find(order.begin(), order.end(), di) == order.end()) order.push_back(di);
     for (int round = 0; round < 3 && e == hipSuccess; ++round)
-        for (size_t i = 0; i < top && e == hipSuccess; ++i) e = time_one(cands[order[i]], 1);
+        for (size_t i = 0; i < order.size() && e == hipSuccess; ++i) e = time_one(cands[order[i]], 1);
     if (e != hipSuccess) {
         cleanup();
         return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
     }
+    // the fastest candidate, unless it beats the default by less than the timing spread of
+    // close shapes (a few percent between runs): then the default stays
     double best = INFINITY;
-    int bv = 0, bx = 0;
-    default_tile(lat, prec, bv, bx);
-    for (const Cand& cd : cands)
-        if (cd.us < best) {
-            best = cd.us;
-            bv = cd.v;
-            bx = cd.xc;
-        }
+    int bv = dv, bx = dx;
+    if (!cands.empty()) {
+        size_t pick = 0;
+        for (size_t i = 1; i < cands.size(); ++i)
+            if (cands[i].us < cands[pick].us) pick = i;
+        if (di < cands.size() && !(cands[pick].us < kAutotuneMargin * cands[di].us)) pick = di;
+        best = cands[pick].us;
+        bv = cands[pick].v;
+        bx = cands[pick].xc;
+    }
     cleanup();
     SKYR_HIP(fill(vel, 4 * sites(lat), prec, 0.0, s));
     SKYR_HIP(hipStreamSynchronize(s));
@@ -2086,6 +2099,11 @@ void skyr_timing_enable(int32_t on)
 
 skyr_status skyr_timing_read(double* sweep_ms, int64_t* sweep_launches)
 {
+    Timing& t = g_timing;
+    if (t.used > 0) {  // pairs recorded by calls that returned without waiting for them
+        SKYR_HIP(hipEventSynchronize(t.ev[t.used - 1]));
+        SKYR_HIP(timing_collect());
+    }
     if (sweep_ms) *sweep_ms = g_timing.ms;
     if (sweep_launches) *sweep_launches = g_timing.launches;
     return SKYR_OK;
