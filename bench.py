@@ -308,15 +308,34 @@ def _job_buffers(skyr, torch, d):
     return lat, prec, phi, alt, vel, work, flow
 
 
+def tune_batch_tiles(skyr, torch, jobs):
+    """The batch tile of every (lattice, precision) of `jobs`, by the batch autotuner
+    on copies of the lattice's first job (before any timed region)."""
+    tiles = {}
+    for d in jobs:
+        prec = skyr.F32_BULK if d["precision"] == "f32" else skyr.F64
+        key = (d["n"], d["h"], prec)
+        if key in tiles:
+            continue
+        lat, prec, phi, alt, vel, work, flow = _job_buffers(skyr, torch, d)
+        v, xc, us = skyr.batch_autotune(lat, prec, skyr.Model(d["m"]), flow, phi)
+        tiles[key] = {"n": d["n"], "precision": d["precision"], "variant": v, "xchunk": xc,
+                      "us_per_slot": round(us, 1), "copies": skyr.batch_copies(lat, prec)}
+        del phi, alt, vel, work
+    return list(tiles.values())
+
+
 def batch_throughput(skyr, torch, jobs, sweeps=64):
     """The same jobs stepped `sweeps` times (a) together in one batch (one
-    launch per precision and sweep slot, replayed from a captured graph) and
-    (b) one at a time through skyr_anf_step; site-updates/s of each."""
+    launch per precision and tile shape and sweep slot, replayed from a captured
+    graph; the batch tiles set by the batch autotuner first) and (b) one at a
+    time through skyr_anf_step; site-updates/s of each."""
+    tiles = tune_batch_tiles(skyr, torch, jobs)
     bufs = [_job_buffers(skyr, torch, d) for d in jobs]
     with skyr.Batch(len(jobs)) as b:
         slots = [b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
                  for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs)]
-        b.run(8)  # warm-up, graph capture
+        b.run(sweeps)  # warm-up: the graph of `sweeps` slots is captured here
         steps0 = [b.poll(s).steps for s in slots]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -336,7 +355,7 @@ def batch_throughput(skyr, torch, jobs, sweeps=64):
     t_seq = time.perf_counter() - t0
     return {"jobs": len(jobs), "sweeps": sweeps, "batched_site_updates_per_s": upd_b / t_batch,
             "sequential_site_updates_per_s": steps_s / t_seq, "batched_s": t_batch, "sequential_s": t_seq,
-            "speedup": (upd_b / t_batch) / (steps_s / t_seq)}
+            "speedup": (upd_b / t_batch) / (steps_s / t_seq), "batch_tiles": tiles}
 
 
 # steps to convergence of a typical request of the served stream (median of a

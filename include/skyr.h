@@ -417,17 +417,21 @@ SKYR_API skyr_status skyr_moments(const skyr_lattice* lat, skyr_precision prec, 
 
 /* Batches: many independent flows (uneven lattices, charges, masses and
  * precisions) advanced together.  Fields of one precision and tile shape share
- * a kernel and are split into one or two chains balanced by block count; per
- * sweep slot a chain is one launch over its fields' tiles followed by a
- * finaliser launch for those fields (one block per field).  Chains share no
- * field: skyr_batch_run replays a captured hipGraph of `sweeps` slots that runs
- * the chains on separate streams and joins them at its end.  Each field's
- * blocks, partial sums and decisions are those of the same field flowing alone
- * with its lattice's tile setting, so a field's result does not depend on the
- * other fields in the batch.  A batch object owns only its job
- * table, control blocks and graph; field, velocity and workspace memory stay
- * with the caller and must stay valid while the field is in the batch.  A
- * batch is used by one thread at a time.
+ * a kernel and form one chain; per sweep slot a chain is one launch over its
+ * fields' tiles, whose blocks also take each field's flow decision (the last
+ * block of a field to finish reads its partial sums).  The launch's blocks are
+ * laid out for the device: a field's blocks in pieces of at most one XCD's
+ * compute units, the pieces spread over the XCDs by estimated work and the
+ * longest blocks dispatched first.  Chains share no field: skyr_batch_run
+ * replays a captured hipGraph of `sweeps` slots that runs the chains as
+ * independent branches.  A field's blocks, partial sums and decisions are
+ * those of the same field flowing alone with its lattice's batch tile (see
+ * skyr_get_batch_tile), so a field's result does not depend on the other
+ * fields in the batch, and equals that of skyr_anf_step when skyr_set_tile
+ * gives the lattice the same tile.  A batch object owns only its job table,
+ * control blocks and graph; field, velocity and workspace memory stay with
+ * the caller and must stay valid while the field is in the batch.  A batch is
+ * used by one thread at a time.
  *   skyr_batch_create  max_jobs slots; work is enqueued on `stream`
  *   skyr_batch_add     a fresh flow (state as after skyr_anf_state_init, zero
  *                      velocity); runs until max|F| < flow->tol or
@@ -449,23 +453,30 @@ SKYR_API skyr_status skyr_batch_remove(skyr_batch* b, int32_t slot);
 SKYR_API int32_t skyr_batch_active(const skyr_batch* b);
 SKYR_API skyr_status skyr_batch_destroy(skyr_batch* b);
 
-/* Tile shapes of the fused sweep.  A few shapes (waves per block, lanes per
- * row, flux rows per thread) are compiled per precision; x is cut into slabs
- * of `xchunk` (>= 16) planes and one block marches one (y, z) tile of one
- * slab.  The choice is kept per (lattice dimensions, precision) for the whole
- * process and applies to every later sweep on such a lattice; results are
- * deterministic for a given choice.  Default (a lattice never set or tuned):
- * the shape whose padded (y, z) tiling costs least (flux positions of all
- * tiles, each priced by a per-shape factor measured at 256^3), and the even
- * split of x into the most slabs (of at least 16 planes, at most 24) whose
- * block count stays within 1024 (float) or 3072 (double) blocks, a split made
- * for batches; a lattice stepped on its own is usually faster after
- * skyr_autotune.  skyr_get_tile reports the setting in force, the
- * default included. */
+/* Tile shapes of the fused sweep.  A few shapes (interior waves, halo waves,
+ * halo positions per halo lane, output columns) are compiled per precision;
+ * skyr_tile_variant_info gives a shape's threads per block and its output
+ * rows and columns.  x is cut into slabs of `xchunk` (>= 16) planes and one
+ * block marches one (y, z) tile of one slab.  The choice is kept per (lattice
+ * dimensions, precision) for the whole process and applies to every later
+ * sweep on such a lattice; results are deterministic for a given choice.
+ * Default for a field flowing alone (a lattice never set or tuned): the shape
+ * and even split of x into 1..8 slabs of least estimated time, that is the
+ * rounds of the device its blocks take times the padded work of one block,
+ * each shape priced by a factor measured at 256^3.  Fields in batches have a
+ * tile setting of their own (skyr_set_batch_tile, skyr_batch_autotune) whose
+ * default is the precision's first shape (variant 0: the fields of one
+ * precision then share one launch per sweep slot) with x split evenly into the
+ * fewest slabs of at most 64 planes: in a batch the other fields fill the
+ * device.  The getters report the setting in force, the default included. */
 SKYR_API int32_t skyr_tile_variants(skyr_precision prec);
 SKYR_API skyr_status skyr_tile_variant_info(skyr_precision prec, int32_t variant, int32_t info[3]);
 SKYR_API skyr_status skyr_set_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant, int32_t xchunk);
 SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk);
+SKYR_API skyr_status skyr_set_batch_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant,
+                                         int32_t xchunk);
+SKYR_API skyr_status skyr_get_batch_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant,
+                                         int32_t* xchunk);
 
 /* Autotuner: time every compiled shape with the slab lengths that split the
  * interior x-extent evenly into 1..8 slabs (at least 16 planes each) on this
@@ -480,6 +491,25 @@ SKYR_API skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec,
 SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                                    const skyr_flow* flow, const void* phi, void* phi_alt, void* vel, void* work,
                                    void* stream, int32_t* variant, int32_t* xchunk, double* best_us);
+
+/* Batch autotuner: the slab length of fields on this lattice in batches.
+ * `copies` independent fields (arrays of `copies` device pointers: phi[i]
+ * initial data, phi_alt[i] and vel[i] field-sized, work[i] of
+ * skyr_workspace_bytes) run together in one batch for each even split of x
+ * into 1..8 slabs (at least 16 planes each), with the batch shape (variant 0,
+ * which keeps a precision's fields in one launch): four sweep slots, then
+ * three timed runs of six slots each; a candidate's time per slot is the
+ * median of its runs.  The fastest is kept with skyr_set_batch_tile -- the batch default
+ * unless the fastest beats it by 3% or more -- and returned (outputs nullable;
+ * best_us is its time per sweep slot of the whole batch, in microseconds).  The
+ * flows run with no tolerance and no step limit, so phi[i] and phi_alt[i] end
+ * with unspecified (advanced) fields and vel[i] zero: pass scratch copies.
+ * Give enough copies that their blocks fill the device several times over.
+ * Synchronises `stream`. */
+SKYR_API skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                         const skyr_flow* flow, int32_t copies, void* const* phi,
+                                         void* const* phi_alt, void* const* vel, void* const* work, void* stream,
+                                         int32_t* variant, int32_t* xchunk, double* best_us);
 
 /* Kernel timing for measurement tools.  skyr_timing_enable(1) resets and
  * starts recording a pair of HIP events around every sweep-kernel launch made

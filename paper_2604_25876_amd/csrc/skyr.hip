@@ -39,6 +39,14 @@ static skyr_status fail(skyr_status s, const std::string& msg)
             return fail(SKYR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));                   \
     } while (0)
 
+// the same, handing the failure to `on_fail` (a cleanup that returns the status it is given)
+#define SKYR_HIP_OR(call, on_fail)                                                                           \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            return on_fail(fail(SKYR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)));          \
+    } while (0)
+
 // ------------------------------------------------------------ tile choice
 // A tile shape is (interior waves, halo waves, halo positions per halo lane,
 // output columns); a tile has interior waves x 64 / columns rows.  A few shapes
@@ -90,7 +98,8 @@ struct TileKey {
     }
 };
 static std::mutex g_tile_mu;
-static std::map<TileKey, std::pair<int, int>> g_tiles;  // (variant, planes per slab)
+static std::map<TileKey, std::pair<int, int>> g_tiles;        // (variant, planes per slab)
+static std::map<TileKey, std::pair<int, int>> g_batch_tiles;  // the same, for fields in batches
 
 // Tiles of the (y, z) plane: rows from y = 2; columns from z = 0 (so that tile rows
 // start on 128-byte lines when the row length allows) unless starting at z = 2 saves a
@@ -172,6 +181,39 @@ static Launch plan(const skyr_lattice* lat, skyr_precision prec)
         }
     }
     if (xc == 0) default_tile(lat, prec, v, xc);
+    return plan_with(lat, prec, v, xc);
+}
+
+// Tile shape and slab length of a field in a batch on a lattice that no one has set or
+// tuned for batches.  The shape is the precision's first: fields of one precision then
+// share one launch per sweep slot (fields of other shapes run as concurrent launches,
+// which mix their blocks on the CUs so that a field's neighbouring tiles no longer march
+// together; each extra launch cost the 64-field mix a few percent).  The batch's other
+// fields fill the device, so the field need not: x is split evenly into the fewest slabs
+// of at most kBatchSlab planes, so that the last blocks of a launch end early.
+constexpr int kBatchShape = 0;
+constexpr int kBatchSlab = 64;
+static void batch_default_tile(const skyr_lattice* lat, skyr_precision prec, int& v_out, int& xc_out)
+{
+    const int nx = lat->n[0] - 4;
+    const int slabs = std::max(1, (nx + kBatchSlab - 1) / kBatchSlab);
+    (void)prec;
+    v_out = kBatchShape;
+    xc_out = std::max(std::min(kMinChunk, nx), (nx + slabs - 1) / slabs);
+}
+
+static Launch plan_batch(const skyr_lattice* lat, skyr_precision prec)
+{
+    int v = 0, xc = 0;
+    {
+        std::lock_guard<std::mutex> g(g_tile_mu);
+        auto it = g_batch_tiles.find(TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec});
+        if (it != g_batch_tiles.end()) {
+            v = it->second.first;
+            xc = it->second.second;
+        }
+    }
+    if (xc == 0) batch_default_tile(lat, prec, v, xc);
     return plan_with(lat, prec, v, xc);
 }
 
@@ -1531,6 +1573,27 @@ skyr_status skyr_get_tile(const skyr_lattice* lat, skyr_precision prec, int32_t*
     return SKYR_OK;
 }
 
+skyr_status skyr_set_batch_tile(const skyr_lattice* lat, skyr_precision prec, int32_t variant, int32_t xchunk)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (variant < 0 || variant >= shape_count(prec)) return fail(SKYR_E_INVAL, "no such tile variant");
+    if (xchunk < kMinChunk) return fail(SKYR_E_INVAL, "slabs must have at least 16 planes");
+    std::lock_guard<std::mutex> g(g_tile_mu);
+    g_batch_tiles[TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec}] = {variant, xchunk};
+    return SKYR_OK;
+}
+
+skyr_status skyr_get_batch_tile(const skyr_lattice* lat, skyr_precision prec, int32_t* variant, int32_t* xchunk)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    const Launch L = plan_batch(lat, prec);
+    if (variant) *variant = L.variant;
+    if (xchunk) *xchunk = L.xchunk;
+    return SKYR_OK;
+}
+
 skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model, const skyr_flow* flow,
                           const void* phi, void* phi_alt, void* vel, void* work, void* stream, int32_t* variant_out,
                           int32_t* xchunk_out, double* best_us_out)
@@ -1679,19 +1742,18 @@ struct skyr_batch {
     std::vector<Ctl> ctl;            // host mirror of d_ctl (valid after a run / poll)
     Ctl* d_ctl = nullptr;            // [max_jobs]
     SweepArgs* d_args = nullptr;     // [max_jobs]
-    int* d_first = nullptr;          // [max_jobs] first block of a job in its chain's grid
     int* d_count = nullptr;          // [max_jobs] blocks of a job
     // Jobs are grouped by (precision, tile shape): group g < F64 shape count is F64 shape g,
     // the rest F32 shape g - (F64 shape count); one kernel serves a group.  A group's jobs
-    // are split into one or more chains (balanced by blocks); a chain is one batched launch
-    // of its own jobs per sweep slot (the sweep takes each job's flow decision itself).
-    // Chains share no field, so the graph holds them as independent branches, where one
-    // chain's blocks fill the CUs another chain's last round leaves idle.
+    // form one chain: one batched launch of its jobs per sweep slot (the sweep takes each
+    // job's flow decision itself).  Chains share no field, so the graph holds them as
+    // independent branches, where one chain's blocks fill the CUs another chain's last
+    // blocks leave idle.
     static constexpr int kGroups = 16;
-    static constexpr int kChains = 2 * kGroups;
+    static constexpr int kChains = kGroups;
     int nchains = 0;
     int chain_group[kChains] = {};
-    int* d_map[kChains] = {};  // block -> job, per chain
+    int* d_map[kChains] = {};  // launch slots (job, block of the job) per chain
     int map_cap[kChains] = {};
     int grid[kChains] = {};
     int ext[kChains] = {};  // the highest kernel variant a job of the chain needs
@@ -1739,57 +1801,101 @@ static skyr_status upload_ints(const std::vector<int>& v, int*& d, int& cap)
     return SKYR_OK;
 }
 
-// rebuild the device job tables, chains and block maps from the host description
+// Sweep time of block `blk` of a job, in the units of a shape's cost factor: the planes
+// of its item (the march's four extra included) times the item's output columns.
+static double item_time(const Launch& L, int nx, int blk)
+{
+    const int tiles = L.tiles_y * L.tiles_z;
+    const int slab = blk / tiles;
+    const int planes = std::min(L.xchunk, nx - slab * L.xchunk);
+    return (double)(planes + 4) * L.shape.oy() * L.shape.oz() * L.shape.cost;
+}
+
+// The launch slots of one chain.  Blocks go to the XCDs in pieces of at most one XCD's
+// CUs from one job (a job's neighbouring tiles then march through the same planes on
+// one L2), the piece of most work first, each to the XCD with the least work so far;
+// on each XCD, the pieces with the longest blocks dispatch first.  Launch block p runs
+// on XCD p mod 8 as the (p / 8)-th block there; XCDs with fewer blocks are padded with
+// empty slots.
+static std::vector<int> chain_slots(const skyr_batch* b, const std::vector<int>& jobs, const std::vector<int>& count)
+{
+    constexpr int kXcds = 8, kPiece = kCUs / kXcds;
+    struct Piece {
+        int job, first, n;
+        double work, longest;
+    };
+    std::vector<Piece> pieces;
+    for (int j : jobs) {
+        const auto& J = b->jobs[j];
+        const int nx = J.lat.n[0] - 4;
+        for (int f = 0; f < count[j]; f += kPiece) {
+            Piece pc{j, f, std::min(kPiece, count[j] - f), 0.0, 0.0};
+            for (int k = f; k < f + pc.n; ++k) {
+                const double t = item_time(J.L, nx, k);
+                pc.work += t;
+                pc.longest = std::max(pc.longest, t);
+            }
+            pieces.push_back(pc);
+        }
+    }
+    std::stable_sort(pieces.begin(), pieces.end(), [](const Piece& x, const Piece& y) { return x.work > y.work; });
+    std::vector<const Piece*> on[kXcds];
+    double load[kXcds] = {};
+    for (const Piece& pc : pieces) {
+        const int x = (int)(std::min_element(load, load + kXcds) - load);
+        load[x] += pc.work;
+        on[x].push_back(&pc);
+    }
+    size_t longest = 0;
+    std::vector<int> list[kXcds];
+    for (int x = 0; x < kXcds; ++x) {
+        std::stable_sort(on[x].begin(), on[x].end(), [](const Piece* p, const Piece* q) { return p->longest > q->longest; });
+        for (const Piece* pc : on[x])
+            for (int k = pc->first; k < pc->first + pc->n; ++k) {
+                list[x].push_back(pc->job);
+                list[x].push_back(k);
+            }
+        longest = std::max(longest, list[x].size() / 2);
+    }
+    std::vector<int> slots(2 * kXcds * longest, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t k = 0; k < list[x].size() / 2; ++k) {
+            slots[2 * (k * kXcds + x)] = list[x][2 * k];
+            slots[2 * (k * kXcds + x) + 1] = list[x][2 * k + 1];
+        }
+    return slots;
+}
+
+// rebuild the device job tables, chains and launch slots from the host description
 static skyr_status batch_rebuild(skyr_batch* b)
 {
-    std::vector<int> first(b->max_jobs, 0), count(b->max_jobs, 0), of_group[skyr_batch::kGroups];
-    int groups = 0;
+    std::vector<int> count(b->max_jobs, 0), of_group[skyr_batch::kGroups];
     for (int j = 0; j < b->max_jobs; ++j) {
         const auto& J = b->jobs[j];
         if (!J.active) continue;
         count[j] = J.L.blocks();
-        auto& v = of_group[batch_group(J.prec, J.L.variant)];
-        groups += v.empty() ? 1 : 0;
-        v.push_back(j);
+        of_group[batch_group(J.prec, J.L.variant)].push_back(j);
     }
-    // chains per group: four branches shared out over the groups present, at most two per
-    // group (four concurrent chains of one kernel ran the 64-job mix 3% slower than one;
-    // two match it)
-    const int parts = std::min(2, std::max(1, 4 / std::max(groups, 1)));
-    std::vector<int> map[skyr_batch::kChains], list[skyr_batch::kChains];
+    // one chain per group: a group's jobs in one launch per sweep slot, their blocks spread
+    // over the XCDs by chain_slots (splitting a group into concurrent chains mixes their
+    // blocks on the CUs, and neighbouring tiles of a field no longer march together)
+    std::vector<int> list[skyr_batch::kChains];
     int nc = 0;
     for (int g = 0; g < skyr_batch::kGroups; ++g) {
-        auto& v = of_group[g];
-        if (v.empty()) continue;
-        const int np = std::min(parts, (int)v.size());
-        // largest jobs first, each to the chain with the fewest blocks so far
-        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return count[x] > count[y]; });
-        std::vector<long long> load(np, 0);
-        for (int j : v) {
-            const int c = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[c] += count[j];
-            list[nc + c].push_back(j);
-        }
-        for (int c = 0; c < np; ++c) {
-            b->chain_group[nc + c] = g;
-            // jobs of a chain in slot order, so that the block map does not depend on their sizes
-            std::sort(list[nc + c].begin(), list[nc + c].end());
-        }
-        nc += np;
+        if (of_group[g].empty()) continue;
+        list[nc] = of_group[g];
+        b->chain_group[nc] = g;
+        ++nc;
     }
     for (int c = 0; c < skyr_batch::kChains; ++c) {
         b->ext[c] = EXT_NONE;
-        for (int j : list[c]) {
-            b->ext[c] = std::max(b->ext[c], ext_level(b->args[j]));
-            first[j] = (int)map[c].size();
-            map[c].insert(map[c].end(), count[j], j);
-        }
-        skyr_status rc = upload_ints(map[c], b->d_map[c], b->map_cap[c]);
+        for (int j : list[c]) b->ext[c] = std::max(b->ext[c], ext_level(b->args[j]));
+        const std::vector<int> slots = chain_slots(b, list[c], count);
+        skyr_status rc = upload_ints(slots, b->d_map[c], b->map_cap[c]);
         if (rc != SKYR_OK) return rc;
-        b->grid[c] = (int)map[c].size();
+        b->grid[c] = (int)slots.size() / 2;
     }
     b->nchains = nc;
-    SKYR_HIP(hipMemcpy(b->d_first, first.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_count, count.data(), sizeof(int) * b->max_jobs, hipMemcpyHostToDevice));
     SKYR_HIP(hipMemcpy(b->d_args, b->args.data(), sizeof(SweepArgs) * b->max_jobs, hipMemcpyHostToDevice));
     b->dirty = false;
@@ -1797,7 +1903,7 @@ static skyr_status batch_rebuild(skyr_batch* b)
     return SKYR_OK;
 }
 
-// launch parameters of chain c's batched sweep; argv (four entries) receives the
+// launch parameters of chain c's batched sweep; argv (three entries) receives the
 // addresses of its arguments, which live in the batch object
 static hipKernelNodeParams chain_params(skyr_batch* b, int c, void** argv)
 {
@@ -1808,8 +1914,7 @@ static hipKernelNodeParams chain_params(skyr_batch* b, int c, void** argv)
                                   threads);
     argv[0] = &b->d_args;
     argv[1] = &b->d_map[c];
-    argv[2] = &b->d_first;
-    argv[3] = &b->d_count;
+    argv[2] = &b->d_count;
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(fn);
     p.gridDim = dim3(b->grid[c]);
@@ -1827,7 +1932,7 @@ static hipKernelNodeParams chain_params(skyr_batch* b, int c, void** argv)
 static skyr_status batch_graph(skyr_batch* b, int sweeps)
 {
     const int nc = b->nchains;
-    void* argv[skyr_batch::kChains][4];
+    void* argv[skyr_batch::kChains][3];
     hipKernelNodeParams prm[skyr_batch::kChains];
     bool same = b->exec && b->graph_sweeps == sweeps && b->graph_chains == nc;
     for (int c = 0; c < nc; ++c) {
@@ -1887,14 +1992,12 @@ skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
     auto cleanup = [&](hipError_t e) {
         (void)hipFree(b->d_ctl);
         (void)hipFree(b->d_args);
-        (void)hipFree(b->d_first);
         (void)hipFree(b->d_count);
         delete b;
         return fail(SKYR_E_DEVICE, std::string("skyr_batch_create: ") + hipGetErrorString(e));
     };
     hipError_t e = hipMalloc((void**)&b->d_ctl, sizeof(Ctl) * max_jobs);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_args, sizeof(SweepArgs) * max_jobs);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_first, sizeof(int) * max_jobs);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_count, sizeof(int) * max_jobs);
     if (e == hipSuccess) e = hipMemcpy(b->d_ctl, b->ctl.data(), sizeof(Ctl) * max_jobs, hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(e);
@@ -1904,19 +2007,15 @@ skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
     return SKYR_OK;
 }
 
-skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
-                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, void* work, int32_t* slot)
+}  // extern "C"
+
+namespace skyr {
+
+// skyr_batch_add after its argument checks, with the field's launch plan given
+static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
+                                    const skyr_model* model, const skyr_flow* flow, void* phi, void* phi_alt,
+                                    void* vel, void* work, const Launch& L, int32_t* slot)
 {
-    if (!b) return fail(SKYR_E_INVAL, "batch is null");
-    skyr_status rc = check_common(lat, prec, model, phi, work);
-    if (rc != SKYR_OK) return rc;
-    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
-    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
-    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
-    if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
-        return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
-    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
-    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     int j = -1;
     for (int k = 0; k < b->max_jobs; ++k)
         if (!b->jobs[k].active) {
@@ -1924,8 +2023,6 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
             break;
         }
     if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
-    // tile shape and slab length of the lattice (the autotuner's choice if it ran for it)
-    const Launch L = plan(lat, prec);
     SweepArgs a = make_args(lat, L, model, flow->dt);
     a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
@@ -1971,6 +2068,27 @@ skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precisio
     b->dirty = true;
     if (slot) *slot = j;
     return SKYR_OK;
+}
+
+}  // namespace skyr
+
+extern "C" {
+
+skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, void* work, int32_t* slot)
+{
+    if (!b) return fail(SKYR_E_INVAL, "batch is null");
+    skyr_status rc = check_common(lat, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
+    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
+        return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
+    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
+    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    // tile shape and slab length of the lattice's fields in batches
+    return skyr::batch_add_launch(b, lat, prec, model, flow, phi, phi_alt, vel, work, skyr::plan_batch(lat, prec), slot);
 }
 
 skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
@@ -2079,11 +2197,112 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
     batch_release_graph(b);
     (void)hipFree(b->d_ctl);
     (void)hipFree(b->d_args);
-    (void)hipFree(b->d_first);
     (void)hipFree(b->d_count);
     for (int c = 0; c < skyr_batch::kChains; ++c) (void)hipFree(b->d_map[c]);
     delete b;
     return SKYR_OK;
+}
+
+// The batch autotuner: every candidate slab length (the even splits of x into 1 ..
+// kMaxSlabs slabs of at least kMinChunk planes, with the batch shape, which keeps the
+// fields of one precision in one launch) is given to all the copies in one batch, which
+// runs kWarm sweep slots and then kReps timed runs of kSweeps slots; a candidate's time is
+// the median of its runs per slot.  The fastest is kept unless it beats the batch default
+// by less than kAutotuneMargin.
+skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                const skyr_flow* flow, int32_t copies, void* const* phi, void* const* phi_alt,
+                                void* const* vel, void* const* work, void* stream, int32_t* variant_out,
+                                int32_t* xchunk_out, double* best_us_out)
+{
+    if (copies < 1 || !phi || !phi_alt || !vel || !work) return fail(SKYR_E_INVAL, "copies >= 1 and buffer arrays required");
+    if (!flow) return fail(SKYR_E_INVAL, "flow must be non-null");
+    for (int i = 0; i < copies; ++i) {
+        skyr_status rc = check_common(lat, prec, model, phi[i], work[i]);
+        if (rc != SKYR_OK) return rc;
+        if (!phi_alt[i] || !vel[i]) return fail(SKYR_E_INVAL, "phi_alt and vel must be non-null");
+        if (phi[i] == phi_alt[i] || phi[i] == vel[i] || phi_alt[i] == vel[i])
+            return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    }
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
+    hipStream_t s = (hipStream_t)stream;
+    // the timed flows never stop: no tolerance, no step limit
+    skyr_flow fl = *flow;
+    fl.tol = 0.0;
+    fl.max_steps = INT64_MAX / 2;
+    constexpr int kWarm = 4, kSweeps = 6, kReps = 3;
+    skyr_batch* b = nullptr;
+    skyr_status rc = skyr_batch_create(copies, stream, &b);
+    if (rc != SKYR_OK) return rc;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto done = [&](skyr_status r) {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        (void)skyr_batch_destroy(b);
+        return r;
+    };
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        return done(fail(SKYR_E_DEVICE, "batch autotune: event creation failed"));
+    struct Cand {
+        int v, xc;
+        double us;
+    };
+    std::vector<Cand> cands;
+    const int nx = lat->n[0] - 4;
+    {
+        int prev = -1;
+        for (int sl = 1; sl <= kMaxSlabs; ++sl) {
+            const int xc = std::max(std::min(kMinChunk, nx), (nx + sl - 1) / sl);
+            if (xc == prev) continue;
+            prev = xc;
+            cands.push_back({kBatchShape, xc, INFINITY});
+        }
+    }
+    int dv = 0, dx = 0;
+    batch_default_tile(lat, prec, dv, dx);
+    size_t di = cands.size();
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (cands[i].v == dv && cands[i].xc == dx) di = i;
+    for (Cand& cd : cands) {
+        const Launch L = plan_with(lat, prec, cd.v, cd.xc);
+        for (int i = 0; i < copies; ++i) {
+            if (b->jobs[i].active && (rc = skyr_batch_remove(b, i)) != SKYR_OK) return done(rc);
+            SKYR_HIP_OR(fill(vel[i], 4 * sites(lat), prec, 0.0, s), done);
+            if ((rc = batch_add_launch(b, lat, prec, model, &fl, phi[i], phi_alt[i], vel[i], work[i], L, nullptr)) !=
+                SKYR_OK)
+                return done(rc);
+        }
+        if ((rc = skyr_batch_run(b, kWarm)) != SKYR_OK) return done(rc);
+        double t[kReps];
+        for (int r = 0; r < kReps; ++r) {
+            SKYR_HIP_OR(hipEventRecord(ev[0], s), done);
+            if ((rc = skyr_batch_run(b, kSweeps)) != SKYR_OK) return done(rc);
+            SKYR_HIP_OR(hipEventRecord(ev[1], s), done);
+            SKYR_HIP_OR(hipEventSynchronize(ev[1]), done);
+            float ms = 0.0f;
+            SKYR_HIP_OR(hipEventElapsedTime(&ms, ev[0], ev[1]), done);
+            t[r] = 1e3 * ms / kSweeps;
+        }
+        std::sort(t, t + kReps);
+        cd.us = t[kReps / 2];
+    }
+    size_t pick = 0;
+    for (size_t i = 1; i < cands.size(); ++i)
+        if (cands[i].us < cands[pick].us) pick = i;
+    if (di < cands.size() && !(cands[pick].us < kAutotuneMargin * cands[di].us)) pick = di;
+    for (int i = 0; i < copies; ++i)
+        if (b->jobs[i].active && (rc = skyr_batch_remove(b, i)) != SKYR_OK) return done(rc);
+    for (int i = 0; i < copies; ++i) SKYR_HIP_OR(fill(vel[i], 4 * sites(lat), prec, 0.0, s), done);
+    SKYR_HIP_OR(hipStreamSynchronize(s), done);
+    {
+        std::lock_guard<std::mutex> g(g_tile_mu);
+        g_batch_tiles[TileKey{lat->n[0], lat->n[1], lat->n[2], (int)prec}] = {cands[pick].v, cands[pick].xc};
+    }
+    if (variant_out) *variant_out = cands[pick].v;
+    if (xchunk_out) *xchunk_out = cands[pick].xc;
+    if (best_us_out) *best_us_out = cands[pick].us;
+    return done(SKYR_OK);
 }
 
 void skyr_timing_enable(int32_t on)

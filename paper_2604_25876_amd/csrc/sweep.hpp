@@ -1216,20 +1216,21 @@ __global__ __launch_bounds__(G::THREADS) void sweep_kernel(SweepArgs a)
     sweep_block<T, G, MODE, false, EXT>(a, xcd_logical_block(blockIdx.x, nb), nb, smem);
 }
 
-// Many fields in one launch: block i (after the XCD remap) belongs to field
-// job_of_block[i] and is its block (i - first_block[job]); every field's blocks
-// and partial sums are exactly those of a launch of that field alone.
+// Many fields in one launch: launch block p sweeps block slot[p].y of field slot[p].x
+// (no field when slot[p].x < 0: a padding block that ends at once).  The host lays the
+// slots out for the round-robin dispatch of blocks over the XCDs (block p runs on XCD
+// p mod 8); every field's blocks and partial sums are exactly those of a launch of that
+// field alone.
 template <typename T, class G, int EXT>
 __global__ __launch_bounds__(G::THREADS) void batch_sweep_kernel(const SweepArgs* __restrict__ jobs,
-                                                                 const int* __restrict__ job_of_block,
-                                                                 const int* __restrict__ first_block,
+                                                                 const int2* __restrict__ slot,
                                                                  const int* __restrict__ blocks_of_job)
 {
     __shared__ SweepSmem<T, G> smem;
-    const int i = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int j = job_of_block[i];
-    const SweepArgs a = jobs[j];
-    sweep_block<T, G, MODE_STEP, true, EXT>(a, i - first_block[j], blocks_of_job[j], smem);
+    const int2 e = slot[blockIdx.x];
+    if (e.x < 0) return;
+    const SweepArgs a = jobs[e.x];
+    sweep_block<T, G, MODE_STEP, true, EXT>(a, e.y, blocks_of_job[e.x], smem);
 }
 
 }  // namespace skyr

@@ -178,6 +178,14 @@ _SIGNATURES = {
     "skyr_autotune": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "skyr_set_batch_tile": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.c_int32, ctypes.c_int32]),
+    "skyr_get_batch_tile": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_batch_autotune": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                           ctypes.POINTER(Flow), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_void_p), _P, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "skyr_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)]),
     "skyr_batch_add": (ctypes.c_int, [_P, ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                       ctypes.POINTER(Flow), _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
@@ -521,7 +529,7 @@ def timing_read() -> tuple[float, int]:
 
 # ------------------------------------------------------------------ tiles
 def tile_variants(prec: int) -> list[tuple[int, int, int]]:
-    """Compiled sweep shapes (waves per block, lanes per row, flux rows per thread)."""
+    """Compiled sweep shapes: (threads per block, output rows, output columns) of each."""
     out = []
     for v in range(lib().skyr_tile_variants(prec)):
         info = (ctypes.c_int32 * 3)()
@@ -538,6 +546,50 @@ def get_tile(lat: Lattice, prec: int) -> tuple[int, int]:
     v, x = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().skyr_get_tile(ctypes.byref(lat), prec, ctypes.byref(v), ctypes.byref(x)))
     return int(v.value), int(x.value)
+
+
+def set_batch_tile(lat: Lattice, prec: int, variant: int, xchunk: int) -> None:
+    """The tile of this lattice's fields in batches."""
+    _check(lib().skyr_set_batch_tile(ctypes.byref(lat), prec, int(variant), int(xchunk)))
+
+
+def get_batch_tile(lat: Lattice, prec: int) -> tuple[int, int]:
+    v, x = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().skyr_get_batch_tile(ctypes.byref(lat), prec, ctypes.byref(v), ctypes.byref(x)))
+    return int(v.value), int(x.value)
+
+
+def batch_copies(lat: Lattice, prec: int, fill: int = 512, most: int = 64) -> int:
+    """Fields for skyr_batch_autotune: enough that the candidate with the fewest blocks
+    (one slab of the largest tile) still has `fill` blocks, 2 .. `most`."""
+    ny, nz = lat.shape[1] - 4, lat.shape[2] - 4
+    fewest = min(-(-ny // oy) * -(-nz // oz) for _, oy, oz in tile_variants(prec))
+    return max(2, min(most, -(-fill // max(fewest, 1))))
+
+
+def batch_autotune(lat: Lattice, prec: int, model: Model, flow: Flow, phi0, copies: int | None = None,
+                   stream=None):
+    """Time every shape / slab split for this lattice's fields in a batch of `copies`
+    copies of phi0 (default batch_copies) and keep the fastest as its batch tile.
+    Returns (variant, planes per slab, microseconds per sweep slot of the batch).
+    The copies are allocated here and freed on return; phi0 is not changed."""
+    import torch
+    n = copies or batch_copies(lat, prec)
+    dev = phi0.device
+    phis = [phi0.clone() for _ in range(n)]
+    alts = [torch.empty_like(phi0) for _ in range(n)]
+    vels = [torch.zeros_like(phi0) for _ in range(n)]
+    works = [new_workspace(lat, prec, dev) for _ in range(n)]
+    shape, dt = (4,) + lat.shape, field_dtype(prec)
+    arr = lambda ts, f: (ctypes.c_void_p * n)(*[f(t).value for t in ts])
+    v, x, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().skyr_batch_autotune(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow), n,
+                                     arr(phis, lambda t: _dev_ptr(t, dt, shape)),
+                                     arr(alts, lambda t: _dev_ptr(t, dt, shape)),
+                                     arr(vels, lambda t: _dev_ptr(t, dt, shape)),
+                                     arr(works, lambda t: _work_ptr(t, lat, prec)), _stream(stream),
+                                     ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
+    return int(v.value), int(x.value), float(us.value)
 
 
 def autotune(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work, stream=None):

@@ -255,3 +255,32 @@ def test_default_tile_choice(n, prec):
     """skyr_get_tile on a lattice never set or tuned (host logic only)."""
     lat = skyr.Lattice.cube(n, 0.1)
     assert skyr.get_tile(lat, prec) == _default_tile(n, prec)
+
+
+def _batch_default_tile(n, prec):
+    """The batch default tile rule, restated: the precision's first shape, x split
+    evenly into the fewest slabs of at most 64 planes (at least 16 planes each)."""
+    import math
+    i = n - 4
+    slabs = max(1, math.ceil(i / 64))
+    return 0, max(min(16, i), math.ceil(i / slabs))
+
+
+@pytest.mark.parametrize("n", [9, 24, 48, 64, 66, 96, 128, 150, 192, 256, 400])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_default_tile_choice(n, prec):
+    """skyr_get_batch_tile on a lattice never set or tuned for batches (host logic only),
+    and a batch setting that changes neither the single-field setting nor the reverse."""
+    lat = skyr.Lattice.cube(n, 0.1)
+    want = _batch_default_tile(n, prec)
+    assert skyr.get_batch_tile(lat, prec) == want
+    if n == 150:
+        solo = skyr.get_tile(lat, prec)
+        skyr.set_batch_tile(lat, prec, 1, 20)
+        assert skyr.get_batch_tile(lat, prec) == (1, 20) and skyr.get_tile(lat, prec) == solo
+        skyr.set_tile(lat, prec, 2, 30)
+        assert skyr.get_batch_tile(lat, prec) == (1, 20) and skyr.get_tile(lat, prec) == (2, 30)
+        with pytest.raises(skyr.SkyrError):
+            skyr.set_batch_tile(lat, prec, 3, 20)
+        with pytest.raises(skyr.SkyrError):
+            skyr.set_batch_tile(lat, prec, 0, 15)

@@ -80,34 +80,66 @@ def test_batch_equals_single_field_entry_point(skyr):
     d = MIX[2]
     res = _run_batch(skyr, [d])[0]
     lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
-    st = skyr.anf_state()
-    skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
+    # the single-field flow on the tile the lattice's fields get in batches
+    solo = skyr.get_tile(lat, prec)
+    skyr.set_tile(lat, prec, *skyr.get_batch_tile(lat, prec))
+    try:
+        st = skyr.anf_state()
+        skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
+    finally:
+        skyr.set_tile(lat, prec, *solo)
     assert st.steps == res[2] and st.arrests == res[3]
     assert np.array_equal(phi.cpu().numpy(), res[0])
 
 
 def test_batch_groups_jobs_by_tuned_tile_shape(skyr):
-    """Lattices whose tile shape was set differently (as the autotuner would,
+    """Lattices whose batch tile was set differently (as the batch autotuner would,
     per lattice and precision) run in one batch, one launch per shape group;
     each result equals the single-field entry point's with the same setting."""
     jobs = [job(30, 0.2, 1.0, 0.02, "f32", 2, 21, flow="power"), job(34, 0.2, 1.0, 0.02, "f32", 3, 22, flow="power"),
             job(26, 0.25, 1.0, 0.025, "f64", 2, 23), job(38, 0.2, 0.0, 0.02, "f64", 1, 24)]
+    precs = [skyr.F32_BULK, skyr.F32_BULK, skyr.F64, skyr.F64]
     lat_of = lambda d: skyr.Lattice.cube(d["n"], d["h"])
-    saved = [(d, prec, skyr.get_tile(lat_of(d), prec)) for d in jobs for prec in (skyr.F64, skyr.F32_BULK)]
+    saved = [(d, prec, skyr.get_tile(lat_of(d), prec), skyr.get_batch_tile(lat_of(d), prec))
+             for d, prec in zip(jobs, precs)]
     try:
-        skyr.set_tile(lat_of(jobs[1]), skyr.F32_BULK, 2, 16)
-        skyr.set_tile(lat_of(jobs[0]), skyr.F32_BULK, 1, 26)
-        skyr.set_tile(lat_of(jobs[3]), skyr.F64, 1, 17)
+        skyr.set_batch_tile(lat_of(jobs[1]), skyr.F32_BULK, 2, 16)
+        skyr.set_batch_tile(lat_of(jobs[0]), skyr.F32_BULK, 1, 26)
+        skyr.set_batch_tile(lat_of(jobs[3]), skyr.F64, 1, 17)
         mix = _run_batch(skyr, jobs)
-        for j, d in enumerate(jobs):
+        for j, (d, prec) in enumerate(zip(jobs, precs)):
             lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+            skyr.set_tile(lat, prec, *skyr.get_batch_tile(lat, prec))
             st = skyr.anf_state()
             skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
             assert st.steps == mix[j][2] and st.arrests == mix[j][3], j
             assert np.array_equal(phi.cpu().numpy(), mix[j][0]), f"job {j}"
     finally:
-        for d, prec, (v, x) in saved:
-            skyr.set_tile(lat_of(d), prec, v, x)
+        for d, prec, solo, batch in saved:
+            skyr.set_tile(lat_of(d), prec, *solo)
+            skyr.set_batch_tile(lat_of(d), prec, *batch)
+
+
+def test_batch_autotune_keeps_a_measured_tile(skyr):
+    """The batch autotuner times every candidate slab length on copies of a field in one batch,
+    keeps one of them as the lattice's batch tile (leaving its single-field tile and
+    the field it was given alone), and a batch on that tile still equals the field
+    flowing alone."""
+    d = job(40, 0.2, 1.0, 0.02, "f32", 2, 31, flow="power", steps=120)
+    lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+    before = phi.clone()
+    saved, solo = skyr.get_batch_tile(lat, prec), skyr.get_tile(lat, prec)
+    try:
+        v, xc, us = skyr.batch_autotune(lat, prec, skyr.Model(d["m"]), flow, phi, copies=4)
+        assert (v, xc) == skyr.get_batch_tile(lat, prec) and skyr.get_tile(lat, prec) == solo
+        assert v == 0 and xc in (36, 18, 16)
+        assert math.isfinite(us) and us > 0
+        assert torch.equal(phi, before)
+        mix = _run_batch(skyr, [d, MIX[0]])
+        alone = _run_batch(skyr, [d])[0]
+        assert mix[0][2] == alone[2] and np.array_equal(mix[0][0], alone[0])
+    finally:
+        skyr.set_batch_tile(lat, prec, *saved)
 
 
 def test_batch_join_while_running(skyr):
@@ -164,8 +196,13 @@ def test_served_requests_with_extended_models(skyr):
         d = r.desc
         lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
         model = skyr.Model(d["m"], d.get("m_y", 0.0), d.get("m_z", 0.0), d.get("m_w", 0.0), d.get("c6", 0.0))
-        st = skyr.anf_state()
-        skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, d["steps"], work)
+        solo = skyr.get_tile(lat, prec)
+        skyr.set_tile(lat, prec, *skyr.get_batch_tile(lat, prec))
+        try:
+            st = skyr.anf_state()
+            skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st, d["steps"], work)
+        finally:
+            skyr.set_tile(lat, prec, *solo)
         assert r.state["steps"] == st.steps and r.state["arrests"] == st.arrests, r.rid
         assert np.array_equal(r.result["field"].cpu().numpy(), phi.cpu().numpy()), r.rid
         assert r.result["E6"] > 0 if d.get("c6") else r.result["E6"] == 0.0
