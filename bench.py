@@ -328,20 +328,29 @@ def tune_batch_tiles(skyr, torch, jobs):
 def batch_throughput(skyr, torch, jobs, sweeps=64):
     """The same jobs stepped `sweeps` times (a) together in one batch (one
     launch per precision and tile shape and sweep slot, replayed from a captured
-    graph; the batch tiles set by the batch autotuner first) and (b) one at a
-    time through skyr_anf_step; site-updates/s of each."""
+    graph; the fields in the padded rows of batch fields; the batch tiles set by
+    the batch autotuner first) and (b) one at a time through skyr_anf_step;
+    site-updates/s of each."""
     tiles = tune_batch_tiles(skyr, torch, jobs)
     bufs = [_job_buffers(skyr, torch, d) for d in jobs]
     with skyr.Batch(len(jobs)) as b:
-        slots = [b.add(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, work)
-                 for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs)]
+        slots = []
+        for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs):
+            # the fields in the padded rows of batch fields
+            layout = skyr.batch_layout(lat, prec)
+            p = skyr.to_padded(phi, layout)
+            slots.append(b.add_padded(lat, prec, skyr.Model(d["m"]), flow, p, torch.zeros_like(p),
+                                      torch.zeros_like(p), work, layout))
         b.run(sweeps)  # warm-up: the graph of `sweeps` slots is captured here
         steps0 = [b.poll(s).steps for s in slots]
+        sweeps0 = [b.poll(s).sweeps for s in slots]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.run(sweeps)
         t_batch = time.perf_counter() - t0
         upd_b = sum((b.poll(s).steps - s0) * (d["n"] - 4) ** 3 for s, s0, d in zip(slots, steps0, jobs))
+        bytes_b = sum((b.poll(s).sweeps - s0) * (d["n"] - 4) ** 3 * BYTES_PER_SITE[d["precision"]]
+                      for s, s0, d in zip(slots, sweeps0, jobs))
     bufs = [_job_buffers(skyr, torch, d) for d in jobs]
     for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs):
         skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, skyr.anf_state(), 8, work)
@@ -355,7 +364,14 @@ def batch_throughput(skyr, torch, jobs, sweeps=64):
     t_seq = time.perf_counter() - t0
     return {"jobs": len(jobs), "sweeps": sweeps, "batched_site_updates_per_s": upd_b / t_batch,
             "sequential_site_updates_per_s": steps_s / t_seq, "batched_s": t_batch, "sequential_s": t_seq,
-            "speedup": (upd_b / t_batch) / (steps_s / t_seq), "batch_tiles": tiles}
+            "speedup": (upd_b / t_batch) / (steps_s / t_seq), "batch_tiles": tiles,
+            "roofline": hbm_roofline(bytes_b / t_batch / 1e9)}
+
+
+def hbm_roofline(gbs):
+    """Algorithmic bytes per second of a batched or served run (every sweep: read phi and
+    v, write phi' and v' at each interior site) against the HBM peak."""
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
 # steps to convergence of a typical request of the served stream (median of a
@@ -391,7 +407,8 @@ def served_stream(skyr, torch, count=128, cap=20000, rate=None, throughput=None,
     rep = srv.serve(reqs)
     be.close()
     rep.update({"rate_per_s": rate, "capacity_est_jobs_per_s": capacity, "step_cap": cap,
-                "tol": "1e-4 (FP64, energy arrest rule); max(1e-4, 2 x FP32 force floor) (FP32-bulk, power rule)"})
+                "tol": "1e-4 (FP64, energy arrest rule); max(1e-4, 2 x FP32 force floor) (FP32-bulk, power rule)",
+                "roofline": hbm_roofline(rep["sweep_GBs"])})
     return rep
 
 

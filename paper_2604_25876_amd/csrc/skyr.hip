@@ -1734,6 +1734,7 @@ struct skyr_batch {
         Launch L{};
         void* phi = nullptr;
         void* phi_alt = nullptr;
+        long long array_sites = 0;  // sites of the stored arrays (the padded rows included)
     };
     int max_jobs = 0;
     hipStream_t stream = nullptr;    // caller's stream (work is launched here)
@@ -2011,10 +2012,30 @@ skyr_status skyr_batch_create(int32_t max_jobs, void* stream, skyr_batch** out)
 
 namespace skyr {
 
-// skyr_batch_add after its argument checks, with the field's launch plan given
+// the argument checks of skyr_batch_add
+static skyr_status batch_add_checks(const skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
+                                    const skyr_model* model, const skyr_flow* flow, const void* phi,
+                                    const void* phi_alt, const void* vel, void* work)
+{
+    if (!b) return fail(SKYR_E_INVAL, "batch is null");
+    skyr_status rc = check_common(lat, prec, model, phi, work);
+    if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
+    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
+    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
+    if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
+        return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
+    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
+    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
+    return SKYR_OK;
+}
+
+// skyr_batch_add after its argument checks, with the field's launch plan given; pitch > 0:
+// the arrays hold rows of `pitch` elements with the lattice's z = 0 at element `lead`
 static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
                                     const skyr_model* model, const skyr_flow* flow, void* phi, void* phi_alt,
-                                    void* vel, void* work, const Launch& L, int32_t* slot)
+                                    void* vel, void* work, const Launch& L, int32_t* slot, int lead = 0,
+                                    int pitch = 0)
 {
     int j = -1;
     for (int k = 0; k < b->max_jobs; ++k)
@@ -2024,12 +2045,22 @@ static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr
         }
     if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
     SweepArgs a = make_args(lat, L, model, flow->dt);
+    if (pitch > 0) {
+        // padded rows: the same tiles over the same lattice sites, addressed in the wider rows
+        a.n2 = pitch;
+        a.ilo[2] += lead;
+        a.ihi[2] += lead;
+        a.olo[2] += lead;
+        a.ohi[2] += lead;
+        a.zstart += lead;
+    }
     a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
     a.phi1 = phi_alt;
     a.vel = vel;
     a.partials = (double*)((char*)work + CTL_BYTES + OBS_BYTES);
     a.ctl = b->d_ctl + j;
+    const long long array_sites = pitch > 0 ? (long long)lat->n[0] * lat->n[1] * pitch : sites(lat);
     Ctl h{};
     h.target = flow->max_steps;
     h.renorm64_every = prec == SKYR_F32_BULK ? flow->renorm64_every : 0;
@@ -2044,7 +2075,10 @@ static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr
     h.status = h.done ? 2 : 0;
     hipStream_t s = b->stream;
     SKYR_HIP(hipMemcpyAsync(b->d_ctl + j, &h, sizeof h, hipMemcpyHostToDevice, s));
-    {
+    if (pitch > 0) {
+        // the frozen layers and the padding of phi in phi_alt: the whole arrays
+        SKYR_HIP(hipMemcpyAsync(phi_alt, phi, 4 * array_sites * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
+    } else {
         const long long N3 = sites(lat);
         const int blocks = (int)std::min<long long>((N3 + 255) / 256, 8192);
         if (prec == SKYR_F64)
@@ -2063,6 +2097,7 @@ static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr
     J.L = L;
     J.phi = phi;
     J.phi_alt = phi_alt;
+    J.array_sites = array_sites;
     b->args[j] = a;
     b->ctl[j] = h;
     b->dirty = true;
@@ -2077,18 +2112,36 @@ extern "C" {
 skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel, void* work, int32_t* slot)
 {
-    if (!b) return fail(SKYR_E_INVAL, "batch is null");
-    skyr_status rc = check_common(lat, prec, model, phi, work);
+    skyr_status rc = skyr::batch_add_checks(b, lat, prec, model, flow, phi, phi_alt, vel, work);
     if (rc != SKYR_OK) return rc;
-    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
-    if (!flow || !phi_alt || !vel) return fail(SKYR_E_INVAL, "flow, phi_alt and vel must be non-null");
-    if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
-    if (!(flow->tol >= 0.0) || flow->max_steps < 0 || flow->renorm64_every < 0)
-        return fail(SKYR_E_INVAL, "tol, max_steps and renorm64_every must be >= 0");
-    if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");
-    if (phi == phi_alt || phi == vel || phi_alt == vel) return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     // tile shape and slab length of the lattice's fields in batches
     return skyr::batch_add_launch(b, lat, prec, model, flow, phi, phi_alt, vel, work, skyr::plan_batch(lat, prec), slot);
+}
+
+skyr_status skyr_batch_layout(const skyr_lattice* lat, skyr_precision prec, int32_t* lead, int32_t* pitch)
+{
+    skyr_status st = check_lattice(lat, prec);
+    if (st != SKYR_OK) return st;
+    if (!lead || !pitch) return fail(SKYR_E_INVAL, "lead and pitch must be non-null");
+    // the first tile column of the lattice's batch tile on a 128-byte line
+    const int line = 128 / (int)elem_bytes(prec);
+    const Launch L = plan_batch(lat, prec);
+    *lead = (line - L.zstart % line) % line;
+    *pitch = (*lead + lat->n[2] + line - 1) / line * line;
+    return SKYR_OK;
+}
+
+skyr_status skyr_batch_add_padded(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
+                                  const skyr_model* model, const skyr_flow* flow, void* phi, void* phi_alt, void* vel,
+                                  void* work, int32_t lead, int32_t pitch, int32_t* slot)
+{
+    skyr_status rc = skyr::batch_add_checks(b, lat, prec, model, flow, phi, phi_alt, vel, work);
+    if (rc != SKYR_OK) return rc;
+    if (lead < 0 || pitch < (long long)lead + lat->n[2]) return fail(SKYR_E_INVAL, "need lead >= 0 and pitch >= lead + n2");
+    if ((long long)lat->n[0] * lat->n[1] * pitch >= (1LL << 31) / 4)
+        return fail(SKYR_E_INVAL, "padded arrays too large for 32-bit component offsets");
+    return skyr::batch_add_launch(b, lat, prec, model, flow, phi, phi_alt, vel, work, skyr::plan_batch(lat, prec), slot,
+                                  lead, pitch);
 }
 
 skyr_status skyr_batch_run(skyr_batch* b, int32_t sweeps)
@@ -2141,7 +2194,7 @@ static skyr_status batch_settle(skyr_batch* b, int j)
     }
     if (h.cur == 1) {
         const auto& J = b->jobs[j];
-        SKYR_HIP(hipMemcpyAsync(J.phi, J.phi_alt, 4 * sites(&J.lat) * elem_bytes(J.prec), hipMemcpyDeviceToDevice,
+        SKYR_HIP(hipMemcpyAsync(J.phi, J.phi_alt, 4 * J.array_sites * elem_bytes(J.prec), hipMemcpyDeviceToDevice,
                                 b->stream));
         h.cur = 0;
         SKYR_HIP(hipMemcpyAsync(&b->d_ctl[j].cur, &h.cur, sizeof h.cur, hipMemcpyHostToDevice, b->stream));
@@ -2211,11 +2264,14 @@ skyr_status skyr_batch_destroy(skyr_batch* b)
 // by less than kAutotuneMargin.
 skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                                 const skyr_flow* flow, int32_t copies, void* const* phi, void* const* phi_alt,
-                                void* const* vel, void* const* work, void* stream, int32_t* variant_out,
-                                int32_t* xchunk_out, double* best_us_out)
+                                void* const* vel, void* const* work, int32_t lead, int32_t pitch, void* stream,
+                                int32_t* variant_out, int32_t* xchunk_out, double* best_us_out)
 {
     if (copies < 1 || !phi || !phi_alt || !vel || !work) return fail(SKYR_E_INVAL, "copies >= 1 and buffer arrays required");
     if (!flow) return fail(SKYR_E_INVAL, "flow must be non-null");
+    if (pitch != 0 && (lead < 0 || pitch < (long long)lead + lat->n[2] ||
+                       (long long)lat->n[0] * lat->n[1] * pitch >= (1LL << 31) / 4))
+        return fail(SKYR_E_INVAL, "pitch 0 (dense fields), or lead >= 0 and pitch >= lead + n2 within 32-bit offsets");
     for (int i = 0; i < copies; ++i) {
         skyr_status rc = check_common(lat, prec, model, phi[i], work[i]);
         if (rc != SKYR_OK) return rc;
@@ -2264,13 +2320,14 @@ skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, co
     size_t di = cands.size();
     for (size_t i = 0; i < cands.size(); ++i)
         if (cands[i].v == dv && cands[i].xc == dx) di = i;
+    const long long array_sites = pitch > 0 ? (long long)lat->n[0] * lat->n[1] * pitch : sites(lat);
     for (Cand& cd : cands) {
         const Launch L = plan_with(lat, prec, cd.v, cd.xc);
         for (int i = 0; i < copies; ++i) {
             if (b->jobs[i].active && (rc = skyr_batch_remove(b, i)) != SKYR_OK) return done(rc);
-            SKYR_HIP_OR(fill(vel[i], 4 * sites(lat), prec, 0.0, s), done);
-            if ((rc = batch_add_launch(b, lat, prec, model, &fl, phi[i], phi_alt[i], vel[i], work[i], L, nullptr)) !=
-                SKYR_OK)
+            SKYR_HIP_OR(fill(vel[i], 4 * array_sites, prec, 0.0, s), done);
+            if ((rc = batch_add_launch(b, lat, prec, model, &fl, phi[i], phi_alt[i], vel[i], work[i], L, nullptr, lead,
+                                       pitch)) != SKYR_OK)
                 return done(rc);
         }
         if ((rc = skyr_batch_run(b, kWarm)) != SKYR_OK) return done(rc);
@@ -2293,7 +2350,7 @@ skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, co
     if (di < cands.size() && !(cands[pick].us < kAutotuneMargin * cands[di].us)) pick = di;
     for (int i = 0; i < copies; ++i)
         if (b->jobs[i].active && (rc = skyr_batch_remove(b, i)) != SKYR_OK) return done(rc);
-    for (int i = 0; i < copies; ++i) SKYR_HIP_OR(fill(vel[i], 4 * sites(lat), prec, 0.0, s), done);
+    for (int i = 0; i < copies; ++i) SKYR_HIP_OR(fill(vel[i], 4 * array_sites, prec, 0.0, s), done);
     SKYR_HIP_OR(hipStreamSynchronize(s), done);
     {
         std::lock_guard<std::mutex> g(g_tile_mu);

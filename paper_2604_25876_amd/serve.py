@@ -80,23 +80,35 @@ class GpuBackend:
         lat = s.Lattice.cube(n, desc["h"])
         prec = self._prec(desc)
         elem = 4 if prec == s.F32_BULK else 8
-        return 3 * 4 * n ** 3 * elem + s.workspace_bytes(lat, prec)
+        _, pitch = s.batch_layout(lat, prec)
+        return 3 * 4 * n * n * pitch * elem + s.workspace_bytes(lat, prec)
 
     def start(self, desc) -> int:
+        """The request's fields in the padded-row layout of batch fields (the initial data
+        made dense, then copied in), and its flow added to the batch."""
         s = self.skyr
         n, h = desc["n"], desc["h"]
         prec = self._prec(desc)
         lat = s.Lattice.cube(n, h)
-        phi = s.new_field(lat, prec, self.device)
+        dense = s.new_field(lat, prec, self.device)
         spec, keep = s.spec_from_description(desc["init"])
-        s.init_field(lat, prec, spec, phi)
-        alt, vel = s.new_field(lat, prec, self.device), s.new_field(lat, prec, self.device)
+        s.init_field(lat, prec, spec, dense)
+        layout = s.batch_layout(lat, prec)
+        phi = s.to_padded(dense, layout)
+        del dense
+        alt, vel = self.torch.zeros_like(phi), self.torch.zeros_like(phi)
         work = s.new_workspace(lat, prec, self.device)
         flow = s.Flow(desc["dt"], desc["tol"], int(desc["steps"]), int(desc.get("renorm64_every", 16)),
                       s.flow_mode(desc.get("flow", "energy")))
-        slot = self.batch.add(lat, prec, self._model(desc), flow, phi, alt, vel, work)
-        self.bufs[slot] = (lat, prec, desc, phi, alt, vel, work)
+        slot = self.batch.add_padded(lat, prec, self._model(desc), flow, phi, alt, vel, work, layout)
+        self.bufs[slot] = (lat, prec, desc, phi, alt, vel, work, layout)
         return slot
+
+    def site(self, slot: int, A: int, x: int, y: int, z: int):
+        """The stored element of component A at lattice site (x, y, z) of a slot's field
+        (a view, for checks and tests)."""
+        lat, prec, desc, phi, alt, vel, work, (lead, pitch) = self.bufs[slot]
+        return phi[A, x, y, lead + z]
 
     def run(self, sweeps: int) -> None:
         self.batch.run(sweeps)
@@ -109,11 +121,12 @@ class GpuBackend:
 
     def finish(self, slot: int, keep_field: bool = False) -> dict:
         s = self.skyr
-        lat, prec, desc, phi, alt, vel, work = self.bufs.pop(slot)
+        lat, prec, desc, phi, alt, vel, work, layout = self.bufs.pop(slot)
         self.batch.remove(slot)
-        out = s.observables(lat, prec, self._model(desc), phi, work)
+        field = s.from_padded(phi, layout, lat.shape[2])
+        out = s.observables(lat, prec, self._model(desc), field, work)
         if keep_field:
-            out["field"] = phi
+            out["field"] = field
         return out
 
     def close(self) -> None:
@@ -138,6 +151,9 @@ class Server:
         self.t0 = None
         self.ticks = 0
         self.site_updates = 0
+        # algorithmic HBM bytes of the sweeps run (read phi and v, write phi' and v' at every
+        # interior site: 64 B in single, 128 B in double precision), redo sweeps included
+        self.sweep_bytes = 0
         self.progress = progress  # called with the server after each finished request
 
     def now(self) -> float:
@@ -165,14 +181,17 @@ class Server:
     def tick(self) -> None:
         self._admit()
         if self.active:
-            before = {s: r.state.get("steps", 0) for s, r in self.active.items()}
+            before = {s: (r.state.get("steps", 0), r.state.get("sweeps", r.state.get("steps", 0)))
+                      for s, r in self.active.items()}
             self.backend.run(self.sweeps_per_tick)
             t = self.now()
             for slot, req in list(self.active.items()):
                 st = self.backend.poll(slot)
                 req.state = st
                 n = req.desc["n"] - 4
-                self.site_updates += (st["steps"] - before[slot]) * n ** 3
+                self.site_updates += (st["steps"] - before[slot][0]) * n ** 3
+                site_bytes = 128 if req.desc.get("precision") == "f64" else 64
+                self.sweep_bytes += (st.get("sweeps", st["steps"]) - before[slot][1]) * n ** 3 * site_bytes
                 if st["done"]:
                     req.result = self.backend.finish(slot, self.keep_fields)
                     req.finished = t
@@ -210,6 +229,7 @@ class Server:
             "wall_s": wall,
             "jobs_per_s": len(self.done) / wall if wall and wall > 0 else math.nan,
             "site_updates_per_s": self.site_updates / wall if wall and wall > 0 else math.nan,
+            "sweep_GBs": self.sweep_bytes / wall / 1e9 if wall and wall > 0 else math.nan,
             "latency_p50_s": percentile(lat, 50), "latency_p99_s": percentile(lat, 99),
             "service_p50_s": percentile(svc, 50), "service_p99_s": percentile(svc, 99),
             "converged_latency_p50_s": percentile(conv, 50), "converged_latency_p99_s": percentile(conv, 99),

@@ -184,11 +184,17 @@ _SIGNATURES = {
     "skyr_batch_autotune": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                            ctypes.POINTER(Flow), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
-                                           ctypes.POINTER(ctypes.c_void_p), _P, ctypes.POINTER(ctypes.c_int32),
-                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+                                           ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32, _P,
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double)]),
     "skyr_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)]),
     "skyr_batch_add": (ctypes.c_int, [_P, ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                       ctypes.POINTER(Flow), _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_batch_layout": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "skyr_batch_add_padded": (ctypes.c_int, [_P, ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                             ctypes.POINTER(Flow), _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "skyr_batch_run": (ctypes.c_int, [_P, ctypes.c_int32]),
     "skyr_batch_poll": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(AnfState)]),
     "skyr_batch_remove": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -568,27 +574,30 @@ def batch_copies(lat: Lattice, prec: int, fill: int = 512, most: int = 64) -> in
 
 
 def batch_autotune(lat: Lattice, prec: int, model: Model, flow: Flow, phi0, copies: int | None = None,
-                   stream=None):
-    """Time every shape / slab split for this lattice's fields in a batch of `copies`
-    copies of phi0 (default batch_copies) and keep the fastest as its batch tile.
-    Returns (variant, planes per slab, microseconds per sweep slot of the batch).
-    The copies are allocated here and freed on return; phi0 is not changed."""
+                   padded: bool = True, stream=None):
+    """Time every slab split for this lattice's fields in a batch of `copies` copies of
+    the dense field phi0 (default batch_copies), stored in the padded rows of
+    batch_layout (or densely), and keep the fastest as its batch tile.  Returns
+    (variant, planes per slab, microseconds per sweep slot of the batch).  The copies
+    are allocated here and freed on return; phi0 is not changed."""
     import torch
     n = copies or batch_copies(lat, prec)
     dev = phi0.device
-    phis = [phi0.clone() for _ in range(n)]
-    alts = [torch.empty_like(phi0) for _ in range(n)]
-    vels = [torch.zeros_like(phi0) for _ in range(n)]
+    layout = batch_layout(lat, prec) if padded else (0, 0)
+    first = to_padded(phi0, layout) if padded else phi0
+    phis = [first.clone() for _ in range(n)]
+    alts = [torch.zeros_like(first) for _ in range(n)]
+    vels = [torch.zeros_like(first) for _ in range(n)]
     works = [new_workspace(lat, prec, dev) for _ in range(n)]
-    shape, dt = (4,) + lat.shape, field_dtype(prec)
+    shape, dt = tuple(first.shape), field_dtype(prec)
     arr = lambda ts, f: (ctypes.c_void_p * n)(*[f(t).value for t in ts])
     v, x, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(lib().skyr_batch_autotune(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow), n,
                                      arr(phis, lambda t: _dev_ptr(t, dt, shape)),
                                      arr(alts, lambda t: _dev_ptr(t, dt, shape)),
                                      arr(vels, lambda t: _dev_ptr(t, dt, shape)),
-                                     arr(works, lambda t: _work_ptr(t, lat, prec)), _stream(stream),
-                                     ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
+                                     arr(works, lambda t: _work_ptr(t, lat, prec)), layout[0], layout[1],
+                                     _stream(stream), ctypes.byref(v), ctypes.byref(x), ctypes.byref(us)))
     return int(v.value), int(x.value), float(us.value)
 
 
@@ -635,6 +644,28 @@ def autotune_cached(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_
 
 
 # ---------------------------------------------------------------- batches
+def batch_layout(lat: Lattice, prec: int) -> tuple[int, int]:
+    """(lead, pitch): the padded-row layout of batch fields on this lattice."""
+    lead, pitch = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().skyr_batch_layout(ctypes.byref(lat), prec, ctypes.byref(lead), ctypes.byref(pitch)))
+    return int(lead.value), int(pitch.value)
+
+
+def to_padded(t, layout: tuple[int, int]):
+    """A dense (4, n0, n1, n2) field copied into zeroed padded rows (4, n0, n1, pitch)."""
+    import torch
+    lead, pitch = layout
+    out = torch.zeros(t.shape[:3] + (pitch,), dtype=t.dtype, device=t.device)
+    out[..., lead:lead + t.shape[3]] = t
+    return out
+
+
+def from_padded(t, layout: tuple[int, int], n2: int):
+    """The dense (4, n0, n1, n2) field of a padded one."""
+    lead, _ = layout
+    return t[..., lead:lead + n2].contiguous()
+
+
 class Batch:
     """Owner of a skyr_batch (many flows advanced by shared launches).  Field,
     velocity and workspace tensors belong to the caller; the batch keeps a
@@ -655,6 +686,20 @@ class Batch:
         _check(lib().skyr_batch_add(self._h, ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                     _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
                                     _dev_ptr(vel, dt, shape), _work_ptr(work, lat, prec), ctypes.byref(slot)))
+        self._tensors[int(slot.value)] = (phi, phi_alt, vel, work)
+        return int(slot.value)
+
+    def add_padded(self, lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work,
+                   layout: tuple[int, int]) -> int:
+        """add() for fields stored with padded rows (batch_layout, to_padded)."""
+        lead, pitch = (int(v) for v in layout)
+        shape = (4,) + lat.shape[:2] + (pitch,)
+        dt = field_dtype(prec)
+        slot = ctypes.c_int32()
+        _check(lib().skyr_batch_add_padded(self._h, ctypes.byref(lat), prec, ctypes.byref(model),
+                                           ctypes.byref(flow), _dev_ptr(phi, dt, shape),
+                                           _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
+                                           _work_ptr(work, lat, prec), lead, pitch, ctypes.byref(slot)))
         self._tensors[int(slot.value)] = (phi, phi_alt, vel, work)
         return int(slot.value)
 

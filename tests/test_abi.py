@@ -284,3 +284,21 @@ def test_batch_default_tile_choice(n, prec):
             skyr.set_batch_tile(lat, prec, 3, 20)
         with pytest.raises(skyr.SkyrError):
             skyr.set_batch_tile(lat, prec, 0, 15)
+
+
+@pytest.mark.parametrize("n", [9, 24, 48, 64, 66, 98, 100, 128, 150, 190])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_layout(n, prec):
+    """skyr_batch_layout restated (host logic only): the first tile column of the batch
+    tile (z = 0, or z = 2 where that saves a tile) on a 128-byte line, rows of whole
+    lines."""
+    import math
+    line = 16 if prec == skyr.F64 else 32
+    oz = 16 if prec == skyr.F64 else 32  # the batch shape's columns
+    aligned, inner = (n - 3) // oz + 1, math.ceil((n - 4) / oz)
+    zstart = 0 if aligned <= inner else 2
+    lead = (line - zstart % line) % line
+    pitch = math.ceil((lead + n) / line) * line
+    lat = skyr.Lattice((ctypes.c_int32 * 3)(n, n + 1, n), 0, 0.1)
+    assert skyr.batch_layout(lat, prec) == (lead, pitch)
+    assert (lead + zstart) % line == 0 and pitch % line == 0 and pitch >= lead + n

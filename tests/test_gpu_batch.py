@@ -142,6 +142,68 @@ def test_batch_autotune_keeps_a_measured_tile(skyr):
         skyr.set_batch_tile(lat, prec, *saved)
 
 
+def test_batch_splits_large_fields_over_xcds(skyr):
+    """Fields with more blocks than one XCD's CUs are laid out in several pieces (and the
+    XCDs padded with empty slots); each field still ends bitwise as alone, and as the
+    single-field flow on the same tile."""
+    jobs = [job(100, 0.15, 1.0, 0.015, "f32", 3, 41, flow="power", steps=60),
+            job(84, 0.18, 1.0, 0.018, "f64", 2, 42, steps=60),
+            job(24, 0.25, 1.0, 0.025, "f64", 1, 43, steps=60), job(30, 0.2, 0.0, 0.02, "f32", 2, 44, steps=60)]
+    mix = _run_batch(skyr, jobs)
+    for j, d in enumerate(jobs):
+        alone = _run_batch(skyr, [d])[0]
+        assert mix[j][2] == alone[2] and np.array_equal(mix[j][0], alone[0]), f"job {j}"
+    d = jobs[0]
+    lat, prec, phi, alt, vel, work, flow = _setup(skyr, d)
+    v, xc = skyr.get_batch_tile(lat, prec)
+    blocks = math.ceil((d["n"] - 4) / 16) * math.ceil((d["n"] - 4) / 32) * math.ceil((d["n"] - 4) / xc)
+    assert blocks > 32
+    solo = skyr.get_tile(lat, prec)
+    skyr.set_tile(lat, prec, v, xc)
+    try:
+        st = skyr.anf_state()
+        skyr.anf_step(lat, prec, skyr.Model(d["m"]), flow, phi, alt, vel, st, d["steps"], work)
+    finally:
+        skyr.set_tile(lat, prec, *solo)
+    assert st.steps == mix[0][2] and np.array_equal(phi.cpu().numpy(), mix[0][0])
+
+
+def test_padded_batch_fields_equal_dense(skyr):
+    """Fields in padded rows (skyr_batch_layout, both lead = 0 and a lead that puts z = 2 on a
+    line) end bitwise as the same fields stored densely, in one mixed batch, and the
+    padding is never written; bad layouts are refused."""
+    jobs = [job(40, 0.2, 1.0, 0.02, "f32", 2, 51, flow="power", steps=80),
+            job(36, 0.2, 0.0, 0.02, "f32", 1, 52, steps=80),
+            job(26, 0.25, 1.0, 0.025, "f64", 2, 53, steps=80), job(20, 0.3, 1.0, 0.03, "f64", 1, 54, steps=80)]
+    dense = _run_batch(skyr, jobs)
+    bufs = [_setup(skyr, d) for d in jobs]
+    layouts = [skyr.batch_layout(b[0], b[1]) for b in bufs]
+    assert {lead for lead, _ in layouts} == {0, 30, 14}
+    with skyr.Batch(8) as bt:
+        slots = []
+        for d, (lat, prec, phi, alt, vel, work, flow), lay in zip(jobs, bufs, layouts):
+            p = skyr.to_padded(phi, lay)
+            a, v = torch.zeros_like(p), torch.zeros_like(p)
+            slots.append((bt.add_padded(lat, prec, skyr.Model(d["m"]), flow, p, a, v, work, lay), p, v, lat, lay))
+        for _ in range(40):
+            bt.run(16)
+            if all(bt.poll(sl).converged or bt.poll(sl).steps >= d["steps"] for (sl, *_), d in zip(slots, jobs)):
+                break
+        for j, ((sl, p, v, lat, (lead, pitch)), d) in enumerate(zip(slots, jobs)):
+            st = bt.poll(sl)
+            assert st.steps == dense[j][2] and st.arrests == dense[j][3], j
+            assert np.array_equal(skyr.from_padded(p, (lead, pitch), lat.shape[2]).cpu().numpy(), dense[j][0]), j
+            assert np.array_equal(skyr.from_padded(v, (lead, pitch), lat.shape[2]).cpu().numpy(), dense[j][1]), j
+            n2 = lat.shape[2]
+            assert not p[..., :lead].any() and not p[..., lead + n2:].any(), f"padding of field {j} written"
+        lat, prec, phi, alt, vel, work, flow = bufs[1]
+        lead, pitch = layouts[1]
+        for bad in ((lead, lead + lat.shape[2] - 1), (-1, pitch)):
+            p = torch.zeros((4,) + lat.shape[:2] + (bad[1],), dtype=phi.dtype, device=DEV)
+            with pytest.raises(skyr.SkyrError):
+                bt.add_padded(lat, prec, skyr.Model(1.0), flow, p, torch.zeros_like(p), torch.zeros_like(p), work, bad)
+
+
 def test_batch_join_while_running(skyr):
     """A field added after others have run for a while ends bitwise equal to its
     run alone (continuous batching)."""

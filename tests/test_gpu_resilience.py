@@ -91,7 +91,7 @@ def test_nonfinite_request_stops_alone_in_the_server(skyr):
         def start(self, desc):
             slot = super().start(desc)
             if desc.get("plant_nan"):
-                self.bufs[slot][3][2, 12, 12, 12] = float("inf")
+                self.site(slot, 2, 12, 12, 12).fill_(float("inf"))
             return slot
 
     reqs = [dict(JOBS[0]), dict(JOBS[1], plant_nan=True), dict(JOBS[2])]

@@ -104,3 +104,17 @@ def test_latencies_and_percentiles():
     a, b = srv.done
     assert a.admitted <= b.admitted and b.latency >= b.service > 0
     assert rep["latency_p99_s"] >= rep["latency_p50_s"] > 0
+
+
+def test_site_updates_and_sweep_bytes_are_counted_per_job():
+    """The report's throughput counts every job's accepted steps over its interior sites,
+    and its algorithmic bytes every sweep at 64 B (single) or 128 B (double) per interior
+    site; the mock's sweeps are all accepted steps."""
+    be = MockBackend(2)
+    srv = Server(be, max_jobs=2, hbm_budget=10 ** 9, sweeps_per_tick=4, clock=FakeClock())
+    reqs = [make("a", 10, 8), make("b", 14, 12)]
+    reqs[1].desc["precision"] = "f64"
+    rep = srv.serve(reqs)
+    assert srv.site_updates == 8 * 6 ** 3 + 12 * 10 ** 3
+    assert srv.sweep_bytes == 8 * 6 ** 3 * 64 + 12 * 10 ** 3 * 128
+    assert rep["sweep_GBs"] == pytest.approx(srv.sweep_bytes / rep["wall_s"] / 1e9)
