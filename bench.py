@@ -368,6 +368,27 @@ def batch_throughput(skyr, torch, jobs, sweeps=64):
             "roofline": hbm_roofline(bytes_b / t_batch / 1e9)}
 
 
+def copy_bandwidth(torch, gib=1, reps=5):
+    """Attainable HBM bandwidth on this device: a device-to-device copy of `gib` GiB (read
+    plus write, the sweep's own 1:1 mix), timed with events on the current stream; the
+    median of `reps` copies after two untimed ones, in GB/s."""
+    src = torch.ones(gib * 2 ** 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * gib * 2 ** 30 / sorted(ts)[reps // 2] / 1e9
+
+
 def hbm_roofline(gbs):
     """Algorithmic bytes per second of a batched or served run (every sweep: read phi and
     v, write phi' and v' at each interior site) against the HBM peak."""
@@ -544,6 +565,8 @@ def main():
     r32 = run_flow(skyr, torch, W, "f32", args.steps, args.warmup, tiles["f32"])
     print(f"# f32-bulk: {r32}", file=sys.stderr, flush=True)
     r64 = run_flow(skyr, torch, W, "f64", args.steps, args.warmup, tiles["f64"])
+    copy_gbs = copy_bandwidth(torch)
+    print(f"# attainable (copy) bandwidth: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     print(f"# f64: {r64}", file=sys.stderr, flush=True)
     # the kernel variants with the program's other potentials, and with the sextic term too (Sec. 7.7), FP32-bulk
     pot_model = (W["m"], 0.5, 0.5, 0.5)
@@ -616,7 +639,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": r32["traffic"],
                      "kernel": "sweep_kernel<float> (step mode)",
-                     "kernel_avg_us": r32["sweep_kernel_avg_us"], "bytes_per_launch": r32["bytes_per_launch"]},
+                     "kernel_avg_us": r32["sweep_kernel_avg_us"], "bytes_per_launch": r32["bytes_per_launch"],
+                     "attainable": {"GBs": copy_gbs, "frac": r32["achieved_GBs"] / copy_gbs,
+                                    "f64_frac": r64["achieved_GBs"] / copy_gbs,
+                                    "probe": "device-to-device copy of 1 GiB (read + write), median of 5"}},
         "cpu_baseline": cpu,
         "batched_64_jobs": batch,
         "served": serve,
