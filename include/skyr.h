@@ -450,16 +450,19 @@ SKYR_API skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr
 
 /* Padded rows for batch fields.  A field whose rows are not whole 128-byte
  * lines (n2 x element size) has its tiles' rows straddle lines, which costs
- * the sweep up to a quarter of its speed.  skyr_batch_layout gives a layout
- * of phi, phi_alt and vel in which the first tile column of the lattice's
+ * the sweep up to a quarter of its speed; and the four component arrays of a
+ * field are four separate memory streams.  skyr_batch_layout gives a layout of
+ * phi, phi_alt and vel in which the four components of a lattice row follow
+ * each other, each padded so that the first tile column of the lattice's
  * batch tile starts a line: component A, site (x, y, z) at element
- * ((A n0 + x) n1 + y) pitch + lead + z, with lead < 128 bytes and pitch the
- * least whole number of lines >= lead + n2.  skyr_batch_add_padded takes
- * fields in any such layout (lead >= 0, pitch >= lead + n2; the elements
- * outside [lead, lead + n2) of a row must be finite, zero for instance, and
- * are never written); it is skyr_batch_add otherwise, and a field's results
- * are bitwise those of the same field stored densely.  The other entry points
- * take dense fields only. */
+ * ((x n1 + y) 4 + A) pitch + lead + z, with lead < 128 bytes and pitch the
+ * least whole number of lines >= lead + n2 (a tensor of shape
+ * (n0, n1, 4, pitch)).  skyr_batch_add_padded takes fields in any such layout
+ * (lead >= 0, pitch >= lead + n2, 4 n0 n1 pitch elements within 4 GiB; the
+ * elements outside [lead, lead + n2) of a row must be finite, zero for
+ * instance, and are never written); it is skyr_batch_add otherwise, and a
+ * field's results are bitwise those of the same field stored densely.  The
+ * other entry points take dense fields only. */
 SKYR_API skyr_status skyr_batch_layout(const skyr_lattice* lat, skyr_precision prec, int32_t* lead, int32_t* pitch);
 SKYR_API skyr_status skyr_batch_add_padded(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
                                            const skyr_model* model, const skyr_flow* flow, void* phi,
@@ -513,8 +516,9 @@ SKYR_API skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec,
 /* Batch autotuner: the slab length of fields on this lattice in batches.
  * `copies` independent fields (arrays of `copies` device pointers: phi[i]
  * initial data, phi_alt[i] and vel[i] field-sized, work[i] of
- * skyr_workspace_bytes; dense when pitch = 0, else in the padded rows
- * (lead, pitch) of skyr_batch_add_padded, the padding zero) run together in
+ * skyr_workspace_bytes; dense when pitch = 0, else in the padded,
+ * row-interleaved layout (lead, pitch) of skyr_batch_add_padded, the padding
+ * zero) run together in
  * one batch for each even split of x
  * into 1..8 slabs (at least 16 planes each), with the batch shape (variant 0,
  * which keeps a precision's fields in one launch): four sweep slots, then

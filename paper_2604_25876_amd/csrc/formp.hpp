@@ -458,6 +458,8 @@ void formp_kernel(SweepArgs a)
     cm.n0 = a.n0;
     cm.n1 = a.n1;
     cm.n2 = a.n2;
+    cm.zlo = a.zlo;
+    cm.zhi = a.zhi;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         cm.ilo[d] = a.ilo[d];

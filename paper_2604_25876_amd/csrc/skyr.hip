@@ -598,6 +598,9 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_
     a.n0 = lat->n[0];
     a.n1 = lat->n[1];
     a.n2 = lat->n[2];
+    a.cstride = sites(lat);
+    a.zlo = 0;
+    a.zhi = lat->n[2] - 1;
     for (int d = 0; d < 3; ++d) {  // a whole lattice: I and the output region are its interior
         a.ilo[d] = a.olo[d] = 2;
         a.ihi[d] = a.ohi[d] = lat->n[d] - 3;
@@ -1480,6 +1483,9 @@ skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const s
     a.n0 = g.P[0];
     a.n1 = g.P[1];
     a.n2 = g.P[2];
+    a.cstride = g.sites();
+    a.zlo = 0;
+    a.zhi = g.P[2] - 1;
     for (int d = 0; d < 3; ++d) {
         a.ilo[d] = g.ilo[d];
         a.ihi[d] = g.ihi[d];
@@ -2046,8 +2052,13 @@ static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr
     if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
     SweepArgs a = make_args(lat, L, model, flow->dt);
     if (pitch > 0) {
-        // padded rows: the same tiles over the same lattice sites, addressed in the wider rows
-        a.n2 = pitch;
+        // padded rows with the four components of a row one after the other: the same tiles
+        // over the same lattice sites, each component addressed within its quarter of a row
+        // four pitches long
+        a.n2 = 4 * pitch;
+        a.cstride = pitch;
+        a.zlo = lead;  // columns beyond the lattice read its frozen end columns, as in a dense row
+        a.zhi = lead + lat->n[2] - 1;
         a.ilo[2] += lead;
         a.ihi[2] += lead;
         a.olo[2] += lead;
@@ -2138,8 +2149,8 @@ skyr_status skyr_batch_add_padded(skyr_batch* b, const skyr_lattice* lat, skyr_p
     skyr_status rc = skyr::batch_add_checks(b, lat, prec, model, flow, phi, phi_alt, vel, work);
     if (rc != SKYR_OK) return rc;
     if (lead < 0 || pitch < (long long)lead + lat->n[2]) return fail(SKYR_E_INVAL, "need lead >= 0 and pitch >= lead + n2");
-    if ((long long)lat->n[0] * lat->n[1] * pitch >= (1LL << 31) / 4)
-        return fail(SKYR_E_INVAL, "padded arrays too large for 32-bit component offsets");
+    if (4LL * lat->n[0] * lat->n[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32))
+        return fail(SKYR_E_INVAL, "padded arrays too large for 32-bit offsets");
     return skyr::batch_add_launch(b, lat, prec, model, flow, phi, phi_alt, vel, work, skyr::plan_batch(lat, prec), slot,
                                   lead, pitch);
 }
@@ -2269,9 +2280,6 @@ skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, co
 {
     if (copies < 1 || !phi || !phi_alt || !vel || !work) return fail(SKYR_E_INVAL, "copies >= 1 and buffer arrays required");
     if (!flow) return fail(SKYR_E_INVAL, "flow must be non-null");
-    if (pitch != 0 && (lead < 0 || pitch < (long long)lead + lat->n[2] ||
-                       (long long)lat->n[0] * lat->n[1] * pitch >= (1LL << 31) / 4))
-        return fail(SKYR_E_INVAL, "pitch 0 (dense fields), or lead >= 0 and pitch >= lead + n2 within 32-bit offsets");
     for (int i = 0; i < copies; ++i) {
         skyr_status rc = check_common(lat, prec, model, phi[i], work[i]);
         if (rc != SKYR_OK) return rc;
@@ -2279,6 +2287,9 @@ skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, co
         if (phi[i] == phi_alt[i] || phi[i] == vel[i] || phi_alt[i] == vel[i])
             return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     }
+    if (pitch != 0 && (lead < 0 || pitch < (long long)lead + lat->n[2] ||
+                       4LL * lat->n[0] * lat->n[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32)))
+        return fail(SKYR_E_INVAL, "pitch 0 (dense fields), or lead >= 0 and pitch >= lead + n2 within 32-bit offsets");
     if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");

@@ -94,6 +94,11 @@ struct SweepArgs {
     double* partials;  // [nblocks][NPART]
     Ctl* ctl;          // MODE_STEP: control block
     int n0, n1, n2;        // extent of the stored array (the whole lattice, or a padded block)
+    // elements from one component of the field to the next: n0 n1 n2 for component-major
+    // arrays; the row length when the components of a row follow each other (the row of
+    // n2 elements then holding all four, each in its own quarter)
+    long long cstride;
+    int zlo, zhi;          // the columns of a row a load may touch: z is clamped into [zlo, zhi]
     // In array coordinates: I, the sites the energy sums over and the flux lives on (the
     // lattice's interior: [2, n-3] per axis for a whole lattice), and the output region, the
     // sites this launch updates (a box within I; all of I for a whole lattice).
@@ -384,6 +389,7 @@ template <typename T, bool FROM_TABLE> struct SweepCommon {
     gptr<T> vel[4];
     gptr<T> gout[4];
     int n0, n1, n2;
+    int zlo, zhi;        // the columns of a row a load may touch
     int ilo[3], ihi[3];  // I in array coordinates
     int olo1, olo2, ohi1, ohi2;  // the output region in y and z
     unsigned plane_b;  // bytes per x-plane of one component
@@ -398,7 +404,7 @@ template <typename T, bool FROM_TABLE> struct SweepCommon {
     }
     __device__ __forceinline__ unsigned site_off(int y, int z) const
     {
-        return (unsigned)(clampi(y, 0, n1 - 1) * n2 + clampi(z, 0, n2 - 1)) * (unsigned)sizeof(T);
+        return (unsigned)(clampi(y, 0, n1 - 1) * n2 + clampi(z, zlo, zhi)) * (unsigned)sizeof(T);
     }
 };
 
@@ -1108,6 +1114,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     cm.n0 = a.n0;
     cm.n1 = a.n1;
     cm.n2 = a.n2;
+    cm.zlo = a.zlo;
+    cm.zhi = a.zhi;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         cm.ilo[d] = a.ilo[d];
@@ -1118,7 +1126,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int b, int nb, S
     cm.ohi1 = a.ohi[1];
     cm.ohi2 = a.ohi[2];
     cm.plane_b = (unsigned)(a.n1 * a.n2) * (unsigned)sizeof(T);
-    const long long N3 = (long long)a.n0 * a.n1 * a.n2;
+    const long long N3 = a.cstride;
     {
         const T* pin = (const T*)(MODE == MODE_STEP && cur ? (const void*)a.phi1 : a.phi0);
         T* pout = (T*)(MODE == MODE_STEP ? (cur ? (void*)a.phi0 : a.phi1) : nullptr);

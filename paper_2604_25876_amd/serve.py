@@ -108,7 +108,7 @@ class GpuBackend:
         """The stored element of component A at lattice site (x, y, z) of a slot's field
         (a view, for checks and tests)."""
         lat, prec, desc, phi, alt, vel, work, (lead, pitch) = self.bufs[slot]
-        return phi[A, x, y, lead + z]
+        return phi[x, y, A, lead + z]
 
     def run(self, sweeps: int) -> None:
         self.batch.run(sweeps)

@@ -652,18 +652,19 @@ def batch_layout(lat: Lattice, prec: int) -> tuple[int, int]:
 
 
 def to_padded(t, layout: tuple[int, int]):
-    """A dense (4, n0, n1, n2) field copied into zeroed padded rows (4, n0, n1, pitch)."""
+    """A dense (4, n0, n1, n2) field copied into the zeroed, row-interleaved padded layout
+    of batch fields, (n0, n1, 4, pitch) with z = 0 at element lead of a row."""
     import torch
     lead, pitch = layout
-    out = torch.zeros(t.shape[:3] + (pitch,), dtype=t.dtype, device=t.device)
-    out[..., lead:lead + t.shape[3]] = t
+    out = torch.zeros(t.shape[1:3] + (4, pitch), dtype=t.dtype, device=t.device)
+    out[..., lead:lead + t.shape[3]] = t.permute(1, 2, 0, 3)
     return out
 
 
 def from_padded(t, layout: tuple[int, int], n2: int):
     """The dense (4, n0, n1, n2) field of a padded one."""
     lead, _ = layout
-    return t[..., lead:lead + n2].contiguous()
+    return t[..., lead:lead + n2].permute(2, 0, 1, 3).contiguous()
 
 
 class Batch:
@@ -693,7 +694,7 @@ class Batch:
                    layout: tuple[int, int]) -> int:
         """add() for fields stored with padded rows (batch_layout, to_padded)."""
         lead, pitch = (int(v) for v in layout)
-        shape = (4,) + lat.shape[:2] + (pitch,)
+        shape = lat.shape[:2] + (4, pitch)
         dt = field_dtype(prec)
         slot = ctypes.c_int32()
         _check(lib().skyr_batch_add_padded(self._h, ctypes.byref(lat), prec, ctypes.byref(model),

@@ -199,7 +199,7 @@ def test_padded_batch_fields_equal_dense(skyr):
         lat, prec, phi, alt, vel, work, flow = bufs[1]
         lead, pitch = layouts[1]
         for bad in ((lead, lead + lat.shape[2] - 1), (-1, pitch)):
-            p = torch.zeros((4,) + lat.shape[:2] + (bad[1],), dtype=phi.dtype, device=DEV)
+            p = torch.zeros(lat.shape[:2] + (4, bad[1]), dtype=phi.dtype, device=DEV)
             with pytest.raises(skyr.SkyrError):
                 bt.add_padded(lat, prec, skyr.Model(1.0), flow, p, torch.zeros_like(p), torch.zeros_like(p), work, bad)
 
