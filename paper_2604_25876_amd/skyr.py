@@ -692,7 +692,8 @@ class Batch:
 
     def add_padded(self, lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, work,
                    layout: tuple[int, int]) -> int:
-        """add() for fields stored with padded rows (batch_layout, to_padded)."""
+        """add() for fields in the padded, row-interleaved layout of batch fields (batch_layout,
+        to_padded): tensors of shape (n0, n1, 4, pitch)."""
         lead, pitch = (int(v) for v in layout)
         shape = lat.shape[:2] + (4, pitch)
         dt = field_dtype(prec)
