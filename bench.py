@@ -395,23 +395,24 @@ def hbm_roofline(gbs):
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
-# steps to convergence of a typical request of the served stream (median of a
-# measured sample of its first jobs), used only to set the arrival rate
-SERVE_STEPS_EST = 9000
+# mean accepted steps of a request of the served stream (measured over its first 128
+# requests: 13,460, the requests stopped at the step cap included), used only to set the
+# arrival rate
+SERVE_STEPS_EST = 13500
 
 
-def served_stream(skyr, torch, count=128, cap=20000, rate=None, throughput=None, sweeps_per_tick=32):
+def served_stream(skyr, torch, count=128, cap=20000, rate=None, bandwidth=None, sweeps_per_tick=32):
     """The served workload (Poisson arrivals, jobs of mixed size and precision).
-    The arrival rate is 1.2 x the estimated service capacity: batched
-    site-updates/s over the mean work of a request (SERVE_STEPS_EST steps of
-    its interior sites), unless given."""
+    The arrival rate is 1.2 x the estimated service capacity, unless given: the batched
+    algorithmic bandwidth (bytes/s) over the mean bytes of a request, SERVE_STEPS_EST
+    sweeps of its interior sites at 64 B (FP32-bulk) or 128 B (FP64) each."""
     from paper_2604_25876_amd.serve import GpuBackend, Request, Server
     from skyr_inputs import served_stream as stream
     probe = stream(5, count, 1.0)
-    mean_sites = sum((d["n"] - 4) ** 3 for d in probe) / len(probe)
+    mean_bytes = sum((d["n"] - 4) ** 3 * BYTES_PER_SITE[d["precision"]] for d in probe) / len(probe)
     capacity = None
     if rate is None:
-        capacity = (throughput or 2e10) / (mean_sites * SERVE_STEPS_EST)
+        capacity = (bandwidth or 3e12) / (mean_bytes * SERVE_STEPS_EST)
         rate = 1.2 * capacity
     reqs = []
     for i, d in enumerate(stream(5, count, rate)):
@@ -551,7 +552,7 @@ def main():
     if args.served_only:
         from skyr_inputs import batch_jobs
         batch = batch_throughput(skyr, torch, batch_jobs(4, 64))
-        serve = served_stream(skyr, torch, count=args.serve_jobs, throughput=batch["batched_site_updates_per_s"])
+        serve = served_stream(skyr, torch, count=args.serve_jobs, bandwidth=batch["roofline"]["achieved"] * 1e9)
         print(json.dumps({"batched_64_jobs": batch, "served": serve}), flush=True)
         return
     if args.sweep_tiles:
@@ -590,7 +591,7 @@ def main():
         from skyr_inputs import batch_jobs
         batch = batch_throughput(skyr, torch, batch_jobs(4, 64))
         print(f"# batch: {batch}", file=sys.stderr, flush=True)
-        serve = served_stream(skyr, torch, count=args.serve_jobs, throughput=batch["batched_site_updates_per_s"])
+        serve = served_stream(skyr, torch, count=args.serve_jobs, bandwidth=batch["roofline"]["achieved"] * 1e9)
         print(f"# serve: {serve}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
