@@ -138,6 +138,10 @@ def test_batch_autotune_keeps_a_measured_tile(skyr):
         mix = _run_batch(skyr, [d, MIX[0]])
         alone = _run_batch(skyr, [d])[0]
         assert mix[0][2] == alone[2] and np.array_equal(mix[0][0], alone[0])
+        # the same on densely stored copies
+        v2, xc2, us2 = skyr.batch_autotune(lat, prec, skyr.Model(d["m"]), flow, phi, copies=3, padded=False)
+        assert v2 == 0 and xc2 in (36, 18, 16) and math.isfinite(us2) and us2 > 0
+        assert torch.equal(phi, before)
     finally:
         skyr.set_batch_tile(lat, prec, *saved)
 
@@ -170,8 +174,8 @@ def test_batch_splits_large_fields_over_xcds(skyr):
 
 def test_padded_batch_fields_equal_dense(skyr):
     """Fields in padded rows (skyr_batch_layout, both lead = 0 and a lead that puts z = 2 on a
-    line) end bitwise as the same fields stored densely, in one mixed batch, and the
-    padding is never written; bad layouts are refused."""
+    line) end bitwise as the same fields stored densely, in one mixed batch that also holds
+    a densely stored field, and the padding is never written; bad layouts are refused."""
     jobs = [job(40, 0.2, 1.0, 0.02, "f32", 2, 51, flow="power", steps=80),
             job(36, 0.2, 0.0, 0.02, "f32", 1, 52, steps=80),
             job(26, 0.25, 1.0, 0.025, "f64", 2, 53, steps=80), job(20, 0.3, 1.0, 0.03, "f64", 1, 54, steps=80)]
@@ -179,16 +183,24 @@ def test_padded_batch_fields_equal_dense(skyr):
     bufs = [_setup(skyr, d) for d in jobs]
     layouts = [skyr.batch_layout(b[0], b[1]) for b in bufs]
     assert {lead for lead, _ in layouts} == {0, 30, 14}
+    dense_mate = job(28, 0.2, 1.0, 0.02, "f32", 2, 55, flow="power", steps=80)
+    mate_alone = _run_batch(skyr, [dense_mate])[0]
     with skyr.Batch(8) as bt:
         slots = []
         for d, (lat, prec, phi, alt, vel, work, flow), lay in zip(jobs, bufs, layouts):
             p = skyr.to_padded(phi, lay)
             a, v = torch.zeros_like(p), torch.zeros_like(p)
             slots.append((bt.add_padded(lat, prec, skyr.Model(d["m"]), flow, p, a, v, work, lay), p, v, lat, lay))
+        # a densely stored field in the same batch
+        mlat, mprec, mphi, malt, mvel, mwork, mflow = _setup(skyr, dense_mate)
+        mslot = bt.add(mlat, mprec, skyr.Model(dense_mate["m"]), mflow, mphi, malt, mvel, mwork)
         for _ in range(40):
             bt.run(16)
-            if all(bt.poll(sl).converged or bt.poll(sl).steps >= d["steps"] for (sl, *_), d in zip(slots, jobs)):
+            if all(bt.poll(sl).converged or bt.poll(sl).steps >= d["steps"] for (sl, *_), d in zip(slots, jobs)) \
+                    and (bt.poll(mslot).converged or bt.poll(mslot).steps >= dense_mate["steps"]):
                 break
+        st = bt.poll(mslot)
+        assert st.steps == mate_alone[2] and np.array_equal(mphi.cpu().numpy(), mate_alone[0])
         for j, ((sl, p, v, lat, (lead, pitch)), d) in enumerate(zip(slots, jobs)):
             st = bt.poll(sl)
             assert st.steps == dense[j][2] and st.arrests == dense[j][3], j
