@@ -194,6 +194,40 @@ def hedgehog_40_smoke(skyr, torch):
             "E_start": E0, "E_end": obs["E"], "B_end": obs["B"], "max_force_end": obs["max_force"], "wall_s": wall}
 
 
+def paper_size_layouts(skyr, torch, prec_name, steps=200, warmup=20):
+    """The paper's own workload size (the O_h B = 4 cube on 151^3 at h = 0.107, dt = 0.1 h),
+    whose 151-site rows are not whole 128-byte lines: the flow (tolerance 0, default tiles)
+    on the dense field and on its padded, row-interleaved copy; site-updates/s of each."""
+    from skyr_inputs import CUBE_B4_128
+    prec = skyr.F32_BULK if prec_name == "f32" else skyr.F64
+    n, h = 151, 0.107
+    lat = skyr.Lattice.cube(n, h)
+    spec, keep = skyr.spec_from_description(CUBE_B4_128["init"])
+    dev = torch.device("cuda:0")
+    phi = skyr.new_field(lat, prec, dev)
+    skyr.init_field(lat, prec, spec, phi)
+    layout = skyr.batch_layout(lat, prec)
+    pphi = skyr.to_padded(phi, layout)
+    work = skyr.new_workspace(lat, prec, dev)
+    model = skyr.Model(1.0)
+    flow = skyr.Flow(0.1 * h, 0.0, 10 ** 12, 16, skyr.flow_mode("power" if prec_name == "f32" else "energy"))
+    out = {"workload": "cube-b4 at 151^3, h = 0.107", "layout": {"lead": layout[0], "pitch": layout[1]}}
+    for name, f, run in (("dense", phi, skyr.anf_step), ("padded", pphi, skyr.anf_step_padded)):
+        alt, vel = torch.zeros_like(f), torch.zeros_like(f)
+        extra = (layout,) if name == "padded" else ()
+        st = skyr.anf_state()
+        run(lat, prec, model, flow, f, alt, vel, st, warmup, work, *extra)
+        torch.cuda.synchronize()
+        s0 = st.steps
+        t0 = time.perf_counter()
+        run(lat, prec, model, flow, f, alt, vel, st, steps, work, *extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"site_updates_per_s": (st.steps - s0) * (n - 4) ** 3 / t, "ms_per_step": 1e3 * t / (st.steps - s0)}
+    out["speedup"] = out["padded"]["site_updates_per_s"] / out["dense"]["site_updates_per_s"]
+    return out
+
+
 def block_share(skyr, torch, w, prec_name, reps=50):
     """One device's share of the workload's lattice split 2 x 2 x 2: the step sweep over the
     128^3 block at (128, 0, 128), its four-deep shell written from a separate buffer (what
@@ -586,6 +620,8 @@ def main():
     print(f"# hedgehog-40 as specified: {c1}", file=sys.stderr, flush=True)
     share = {p: block_share(skyr, torch, W, p) for p in ("f32", "f64")}
     print(f"# one device's block of a 2x2x2 split: {share}", file=sys.stderr, flush=True)
+    paper151 = {p: paper_size_layouts(skyr, torch, p) for p in ("f32", "f64")}
+    print(f"# paper-size lattice, dense vs padded rows: {paper151}", file=sys.stderr, flush=True)
     batch = serve = None
     if not args.no_batch:
         from skyr_inputs import batch_jobs
@@ -635,6 +671,7 @@ def main():
         "moments": moments,
         "hedgehog_40_as_specified": c1,
         "block_128_of_256": share,
+        "paper_size_151": paper151,
         "sweeps": r32["sweeps"],
         "arrests": r32["arrests"],
         "roofline": {"bound": "hbm", "achieved": r32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -288,6 +288,20 @@ SKYR_API skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec,
                           const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
                           int64_t nsteps, void* work, void* stream);
 
+/* skyr_anf_step for fields stored in padded rows with the four components of a
+ * row one after the other (the layout of skyr_batch_add_padded: component A,
+ * site (x, y, z) at element ((x n1 + y) 4 + A) pitch + lead + z; lead >= 0,
+ * pitch >= lead + n2, the elements outside [lead, lead + n2) of a row finite
+ * and never written; skyr_batch_layout gives lead and pitch that put the
+ * first tile column on a 128-byte line).  phi, phi_alt and vel all take that
+ * layout; the exact-gradient form only.  Results are bitwise those of
+ * skyr_anf_step on the same field stored densely; on a lattice whose rows are
+ * not whole 128-byte lines the sweep runs faster. */
+SKYR_API skyr_status skyr_anf_step_padded(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                          const skyr_flow* flow, void* phi, void* phi_alt, void* vel,
+                                          skyr_anf_state* st, int64_t nsteps, void* work, int32_t lead,
+                                          int32_t pitch, void* stream);
+
 /* For callers that cannot allocate device memory (tight serving loops, harnesses
  * that forbid hipMalloc / hipFree, callers without a workspace of their own):
  * skyr_anf_step with the same arguments except `work`.  The control block and
@@ -461,8 +475,9 @@ SKYR_API skyr_status skyr_batch_add(skyr_batch* b, const skyr_lattice* lat, skyr
  * (lead >= 0, pitch >= lead + n2, 4 n0 n1 pitch elements within 4 GiB; the
  * elements outside [lead, lead + n2) of a row must be finite, zero for
  * instance, and are never written); it is skyr_batch_add otherwise, and a
- * field's results are bitwise those of the same field stored densely.  The
- * other entry points take dense fields only. */
+ * field's results are bitwise those of the same field stored densely.
+ * skyr_anf_step_padded is the single-field flow on such fields; the other
+ * entry points take dense fields only. */
 SKYR_API skyr_status skyr_batch_layout(const skyr_lattice* lat, skyr_precision prec, int32_t* lead, int32_t* pitch);
 SKYR_API skyr_status skyr_batch_add_padded(skyr_batch* b, const skyr_lattice* lat, skyr_precision prec,
                                            const skyr_model* model, const skyr_flow* flow, void* phi,

@@ -619,6 +619,32 @@ static SweepArgs make_args(const skyr_lattice* lat, const Launch& L, const skyr_
     return a;
 }
 
+// Sweep arguments for fields in padded rows of `pitch` elements with the four components of
+// a row one after the other and the lattice's z = 0 at element `lead`: the same tiles over
+// the same lattice sites, each component addressed within its quarter of a row four
+// pitches long; lanes beyond the lattice read its frozen end columns, as in a dense row.
+static void use_padded_rows(SweepArgs& a, const skyr_lattice* lat, int lead, int pitch)
+{
+    a.n2 = 4 * pitch;
+    a.cstride = pitch;
+    a.zlo = lead;
+    a.zhi = lead + lat->n[2] - 1;
+    a.ilo[2] += lead;
+    a.ihi[2] += lead;
+    a.olo[2] += lead;
+    a.ohi[2] += lead;
+    a.zstart += lead;
+}
+
+// the layout checks of a padded field: lead >= 0, pitch >= lead + n2, offsets within 32 bits
+static skyr_status check_padded_rows(const skyr_lattice* lat, skyr_precision prec, int lead, int pitch)
+{
+    if (lead < 0 || pitch < (long long)lead + lat->n[2]) return fail(SKYR_E_INVAL, "need lead >= 0 and pitch >= lead + n2");
+    if (4LL * lat->n[0] * lat->n[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32))
+        return fail(SKYR_E_INVAL, "padded arrays too large for 32-bit offsets");
+    return SKYR_OK;
+}
+
 static hipError_t fill(void* p, long long n, skyr_precision prec, double v, hipStream_t s)
 {
     const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
@@ -1113,7 +1139,8 @@ static skyr_status flow_graph_launch(const void* fn, int grid, int threads, cons
 // groups of sweeps from a cached graph (exact form, timing off)
 static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
                            const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
-                           int64_t nsteps, void* work, hipStream_t s, bool timed, bool graphs)
+                           int64_t nsteps, void* work, hipStream_t s, bool timed, bool graphs, int lead = 0,
+                           int pitch = 0)
 {
     const int64_t target = std::min<int64_t>(st->steps + nsteps, flow->max_steps);
     if (st->converged || target <= st->steps) return SKYR_OK;
@@ -1123,6 +1150,8 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     char* w = (char*)work;
     Ctl* ctl = (Ctl*)w;
     SweepArgs a = make_args(lat, L, model, flow->dt);
+    if (pitch > 0) use_padded_rows(a, lat, lead, pitch);
+    const long long array_sites = pitch > 0 ? (long long)lat->n[0] * lat->n[1] * pitch : sites(lat);
     a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
     a.phi1 = phi_alt;
@@ -1147,8 +1176,10 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
     h.tol = flow->tol;
     h.h3 = lat->h * lat->h * lat->h;
     SKYR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
-    // the frozen layers of phi_alt must match those of phi
-    {
+    // the frozen layers of phi_alt must match those of phi (padded rows: the whole arrays)
+    if (pitch > 0) {
+        SKYR_HIP(hipMemcpyAsync(phi_alt, phi, 4 * array_sites * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
+    } else {
         const long long N3 = sites(lat);
         const int blocks = (int)std::min<long long>((N3 + 255) / 256, 8192);
         if (prec == SKYR_F64)
@@ -1199,7 +1230,7 @@ static skyr_status anf_run(const skyr_lattice* lat, skyr_precision prec, const s
         SKYR_HIP(hipStreamSynchronize(s));
     }
     if (h.cur == 1) {
-        SKYR_HIP(hipMemcpyAsync(phi, phi_alt, 4 * sites(lat) * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
+        SKYR_HIP(hipMemcpyAsync(phi, phi_alt, 4 * array_sites * elem_bytes(prec), hipMemcpyDeviceToDevice, s));
         SKYR_HIP(hipStreamSynchronize(s));
     }
     st->steps = h.steps;
@@ -1255,6 +1286,19 @@ skyr_status skyr_anf_step(const skyr_lattice* lat, skyr_precision prec, const sk
     const skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work);
     if (rc != SKYR_OK) return rc;
     return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true, true);
+}
+
+skyr_status skyr_anf_step_padded(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
+                                 const skyr_flow* flow, void* phi, void* phi_alt, void* vel, skyr_anf_state* st,
+                                 int64_t nsteps, void* work, int32_t lead, int32_t pitch, void* stream)
+{
+    skyr_status rc = check_flow(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work);
+    if (rc != SKYR_OK) return rc;
+    if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "padded fields run the exact-gradient sweep only");
+    rc = check_padded_rows(lat, prec, lead, pitch);
+    if (rc != SKYR_OK) return rc;
+    return anf_run(lat, prec, model, flow, phi, phi_alt, vel, st, nsteps, work, (hipStream_t)stream, true, true, lead,
+                   pitch);
 }
 
 skyr_status skyr_anf_step_noalloc(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,
@@ -2051,20 +2095,7 @@ static skyr_status batch_add_launch(skyr_batch* b, const skyr_lattice* lat, skyr
         }
     if (j < 0) return fail(SKYR_E_BUSY, "every batch slot is in use");
     SweepArgs a = make_args(lat, L, model, flow->dt);
-    if (pitch > 0) {
-        // padded rows with the four components of a row one after the other: the same tiles
-        // over the same lattice sites, each component addressed within its quarter of a row
-        // four pitches long
-        a.n2 = 4 * pitch;
-        a.cstride = pitch;
-        a.zlo = lead;  // columns beyond the lattice read its frozen end columns, as in a dense row
-        a.zhi = lead + lat->n[2] - 1;
-        a.ilo[2] += lead;
-        a.ihi[2] += lead;
-        a.olo[2] += lead;
-        a.ohi[2] += lead;
-        a.zstart += lead;
-    }
+    if (pitch > 0) use_padded_rows(a, lat, lead, pitch);
     a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
     a.phi0 = phi;
     a.phi1 = phi_alt;
@@ -2148,9 +2179,8 @@ skyr_status skyr_batch_add_padded(skyr_batch* b, const skyr_lattice* lat, skyr_p
 {
     skyr_status rc = skyr::batch_add_checks(b, lat, prec, model, flow, phi, phi_alt, vel, work);
     if (rc != SKYR_OK) return rc;
-    if (lead < 0 || pitch < (long long)lead + lat->n[2]) return fail(SKYR_E_INVAL, "need lead >= 0 and pitch >= lead + n2");
-    if (4LL * lat->n[0] * lat->n[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32))
-        return fail(SKYR_E_INVAL, "padded arrays too large for 32-bit offsets");
+    rc = skyr::check_padded_rows(lat, prec, lead, pitch);
+    if (rc != SKYR_OK) return rc;
     return skyr::batch_add_launch(b, lat, prec, model, flow, phi, phi_alt, vel, work, skyr::plan_batch(lat, prec), slot,
                                   lead, pitch);
 }
@@ -2287,9 +2317,10 @@ skyr_status skyr_batch_autotune(const skyr_lattice* lat, skyr_precision prec, co
         if (phi[i] == phi_alt[i] || phi[i] == vel[i] || phi_alt[i] == vel[i])
             return fail(SKYR_E_INVAL, "phi, phi_alt and vel must differ");
     }
-    if (pitch != 0 && (lead < 0 || pitch < (long long)lead + lat->n[2] ||
-                       4LL * lat->n[0] * lat->n[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32)))
-        return fail(SKYR_E_INVAL, "pitch 0 (dense fields), or lead >= 0 and pitch >= lead + n2 within 32-bit offsets");
+    if (pitch != 0) {
+        skyr_status prc = check_padded_rows(lat, prec, lead, pitch);
+        if (prc != SKYR_OK) return prc;
+    }
     if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "batches run the exact-gradient sweep only");
     if (!(flow->dt > 0.0) || !std::isfinite(flow->dt)) return fail(SKYR_E_INVAL, "dt must be positive");
     if (flow->mode < SKYR_ARREST_ENERGY || flow->mode > SKYR_GRADIENT_FLOW) return fail(SKYR_E_INVAL, "unknown flow mode");

@@ -152,6 +152,9 @@ _SIGNATURES = {
     "skyr_anf_step": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                      ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState), ctypes.c_int64, _P,
                                      _P]),
+    "skyr_anf_step_padded": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
+                                            ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState),
+                                            ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P]),
     "skyr_anf_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.c_int, ctypes.POINTER(Model),
                                              ctypes.POINTER(Flow), _P, _P, _P, ctypes.POINTER(AnfState),
                                              ctypes.c_int64, _P]),
@@ -369,6 +372,20 @@ def anf_step(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, ve
     _check(lib().skyr_anf_step(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
                                _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape), _dev_ptr(vel, dt, shape),
                                ctypes.byref(state), int(nsteps), _work_ptr(work, lat, prec), _stream(stream)))
+    return state
+
+
+def anf_step_padded(lat: Lattice, prec: int, model: Model, flow: Flow, phi, phi_alt, vel, state: AnfState,
+                    nsteps: int, work, layout: tuple[int, int], stream=None) -> AnfState:
+    """skyr_anf_step on fields in the padded, row-interleaved layout (n0, n1, 4, pitch) of
+    batch_layout / to_padded."""
+    lead, pitch = (int(v) for v in layout)
+    shape = lat.shape[:2] + (4, pitch)
+    dt = field_dtype(prec)
+    _check(lib().skyr_anf_step_padded(ctypes.byref(lat), prec, ctypes.byref(model), ctypes.byref(flow),
+                                      _dev_ptr(phi, dt, shape), _dev_ptr(phi_alt, dt, shape),
+                                      _dev_ptr(vel, dt, shape), ctypes.byref(state), int(nsteps),
+                                      _work_ptr(work, lat, prec), lead, pitch, _stream(stream)))
     return state
 
 

@@ -149,3 +149,41 @@ def test_arrested_flow_with_sextic_matches_oracle(skyr):
     assert st.arrests == rst.arrests
     assert np.abs(phi - ref).max() < 1e-10
     assert np.abs(vel - rvel).max() < 1e-9
+
+
+@pytest.mark.parametrize("prec,rule,shape,tol", [(1, "power", (36, 33, 36), 0.0), (0, "energy", (26, 30, 26), 0.0),
+                                                 (1, "power", (40, 40, 40), 2e-2), (0, "energy", (22, 24, 20), 0.0)],
+                         ids=["f32-lead30", "f64-lead0", "f32-converging", "f64-lead14"])
+def test_padded_flow_equals_dense(skyr, prec, rule, shape, tol):
+    """skyr_anf_step_padded on the padded, row-interleaved copy of a field ends bitwise as
+    skyr_anf_step on the dense field, over several calls (graph replays, arrests, and, with a
+    tolerance, the stop with its restore sweep), and never writes the padding."""
+    h = 0.2
+    lat = _lat(skyr, shape, h)
+    spec, keep = skyr.spec_from_description({"kind": "hedgehog", "prof_lambda": 0.8})
+    phi = skyr.new_field(lat, prec, DEV)
+    skyr.init_field(lat, prec, spec, phi)
+    layout = skyr.batch_layout(lat, prec)
+    lead, pitch = layout
+    pphi = skyr.to_padded(phi, layout)
+    palt, pvel = torch.zeros_like(pphi), torch.zeros_like(pphi)
+    alt, vel = skyr.new_field(lat, prec, DEV), skyr.new_field(lat, prec, DEV)
+    work = skyr.new_workspace(lat, prec, DEV)
+    flow = skyr.Flow(0.04, tol, 10 ** 6, 4, skyr.flow_mode(rule))
+    model = skyr.Model(1.0, 0.0, 0.0, 0.0, 0.0)
+    st_d, st_p = skyr.anf_state(), skyr.anf_state()
+    for nsteps in (7, 150, 90):
+        skyr.anf_step(lat, prec, model, flow, phi, alt, vel, st_d, nsteps, work)
+        skyr.anf_step_padded(lat, prec, model, flow, pphi, palt, pvel, st_p, nsteps, work, layout)
+        assert bytes(st_d) == bytes(st_p), nsteps
+    assert st_d.arrests > 0
+    if tol > 0:
+        assert st_d.converged
+    n2 = lat.shape[2]
+    assert torch.equal(skyr.from_padded(pphi, layout, n2), phi)
+    assert torch.equal(skyr.from_padded(pvel, layout, n2), vel)
+    assert not pphi[..., :lead].any() and not pphi[..., lead + n2:].any()
+    short = torch.zeros(lat.shape[:2] + (4, lead + n2 - 1), dtype=phi.dtype, device=DEV)
+    with pytest.raises(skyr.SkyrError):
+        skyr.anf_step_padded(lat, prec, model, flow, short, torch.zeros_like(short), torch.zeros_like(short),
+                             skyr.anf_state(), 1, work, (lead, lead + n2 - 1))
