@@ -517,10 +517,11 @@ SKYR_API skyr_status skyr_get_batch_tile(const skyr_lattice* lat, skyr_precision
 /* Autotuner: time every compiled shape with the slab lengths that split the
  * interior x-extent evenly into 1..8 slabs (at least 16 planes each) on this
  * lattice (flow sweeps, phi read, phi_alt and vel written; a candidate's time
- * is the median of five sweeps, and the four fastest and the default choice are
- * timed three more times, interleaved, keeping their best median), keep the
- * fastest with skyr_set_tile -- the default choice unless the fastest beats it
- * by 3% or more, about the spread of such timings between runs -- and return it
+ * is the median of five sweeps; the four fastest and the default choice are
+ * then timed in three more interleaved rounds, and a finalist's time is the
+ * median of its rounds), keep the fastest finalist with skyr_set_tile -- the
+ * default choice unless the fastest beats it by 3% or more, about the spread
+ * of such timings between runs -- and return it
  * (outputs nullable; best_us is its sweep time in microseconds).  phi is
  * unchanged; phi_alt is scratch and vel is zero on return.  Synchronises
  * `stream`. */

@@ -1680,6 +1680,7 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     struct Cand {
         int v, xc;
         double us;
+        std::vector<double> rounds;  // the medians of the interleaved rounds
     };
     std::vector<Cand> cands;
     // slab lengths: the even splits of the interior x-extent into s = 1, 2, ... slabs
@@ -1692,10 +1693,10 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
             const int xc = std::max(std::min(kMinChunk, nx), (nx + sl - 1) / sl);
             if (xc == prev) continue;
             prev = xc;
-            cands.push_back({v, xc, INFINITY});
+            cands.push_back({v, xc, INFINITY, {}});
         }
     }
-    auto time_one = [&](Cand& cd, int warm) -> hipError_t {
+    auto time_one = [&](Cand& cd, int warm, bool round) -> hipError_t {
         const Launch L = plan_with(lat, prec, cd.v, cd.xc);
         SweepArgs a = make_args(lat, L, model, flow->dt);
         a.gradient_flow = flow->mode == SKYR_GRADIENT_FLOW;
@@ -1720,15 +1721,18 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
         }
         if (e == hipSuccess) {
             std::sort(t, t + kReps);
-            cd.us = std::min(cd.us, t[kReps / 2]);
+            if (round)
+                cd.rounds.push_back(t[kReps / 2]);
+            else
+                cd.us = std::min(cd.us, t[kReps / 2]);
         }
         return e;
     };
     // the first candidate also warms the device clocks up before anything is compared
-    hipError_t e = cands.empty() ? hipSuccess : time_one(cands[0], 24);
-    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) e = time_one(cands[i], 1);
-    // the closest candidates and the default choice are timed again, interleaved, and keep
-    // their best median
+    hipError_t e = cands.empty() ? hipSuccess : time_one(cands[0], 24, false);
+    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) e = time_one(cands[i], 1, false);
+    // the closest candidates and the default choice are timed again in interleaved rounds;
+    // a finalist's time is the median of its rounds (a single lucky round does not decide)
     int dv = 0, dx = 0;
     default_tile(lat, prec, dv, dx);
     size_t di = cands.size();
@@ -1740,7 +1744,13 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     order.resize(std::min<size_t>(4, order.size()));
     if (di < cands.size() && std::find(order.begin(), order.end(), di) == order.end()) order.push_back(di);
     for (int round = 0; round < 3 && e == hipSuccess; ++round)
-        for (size_t i = 0; i < order.size() && e == hipSuccess; ++i) e = time_one(cands[order[i]], 1);
+        for (size_t i = 0; i < order.size() && e == hipSuccess; ++i) e = time_one(cands[order[i]], 1, true);
+    for (size_t i : order) {
+        auto& r = cands[i].rounds;
+        if (r.empty()) continue;
+        std::sort(r.begin(), r.end());
+        cands[i].us = r[r.size() / 2];
+    }
     if (e != hipSuccess) {
         cleanup();
         return fail(SKYR_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
@@ -1749,9 +1759,10 @@ skyr_status skyr_autotune(const skyr_lattice* lat, skyr_precision prec, const sk
     // close shapes (a few percent between runs): then the default stays
     double best = INFINITY;
     int bv = dv, bx = dx;
-    if (!cands.empty()) {
-        size_t pick = 0;
-        for (size_t i = 1; i < cands.size(); ++i)
+    if (!order.empty()) {
+        // among the finalists (timed in every round)
+        size_t pick = order[0];
+        for (size_t i : order)
             if (cands[i].us < cands[pick].us) pick = i;
         if (di < cands.size() && !(cands[pick].us < kAutotuneMargin * cands[di].us)) pick = di;
         best = cands[pick].us;
