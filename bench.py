@@ -554,6 +554,8 @@ def main():
                     help="run only the batched and served workloads and print the served record (profiling runs)")
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="print the sweep time of every compiled tile shape and x-chunk, then exit")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="run 24 sweep slots of the 64-job batch (for counter runs of the batched kernel) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="instead of the flow, copy a 1 GiB device buffer 5 times (reference for the HBM "
                          "byte counters: 1 GiB read + 1 GiB written per copy)")
@@ -563,6 +565,28 @@ def main():
     args = ap.parse_args()
     tiles = {p: (tuple(int(t) for t in v.split(":")) if v else None)
              for p, v in (("f32", args.tile_f32), ("f64", args.tile_f64))}
+    if args.batch_probe:
+        # the 64-job mix on padded, row-interleaved fields with the default batch tiles: 24
+        # sweep slots, for counter runs of the batched kernel
+        import torch
+        from paper_2604_25876_amd import skyr
+        from skyr_inputs import batch_jobs
+        skyr.lib()
+        jobs = batch_jobs(4, 64)
+        bufs = [_job_buffers(skyr, torch, d) for d in jobs]
+        with skyr.Batch(len(jobs)) as b:
+            for d, (lat, prec, phi, alt, vel, work, flow) in zip(jobs, bufs):
+                layout = skyr.batch_layout(lat, prec)
+                p = skyr.to_padded(phi, layout)
+                b.add_padded(lat, prec, skyr.Model(d["m"]), flow, p, torch.zeros_like(p), torch.zeros_like(p), work,
+                             layout)
+            for _ in range(3):
+                b.run(8)
+        tiles = {n: skyr.get_batch_tile(skyr.Lattice.cube(n, 0.15), skyr.F32_BULK) for n in (48, 64, 96, 128)}
+        print(json.dumps({"batch_probe_slots": 24, "algorithmic_bytes_per_slot":
+                          sum((d["n"] - 4) ** 3 * BYTES_PER_SITE[d["precision"]] for d in jobs),
+                          "tiles": {str(k): v for k, v in tiles.items()}}))
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda:0")
