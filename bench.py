@@ -247,22 +247,29 @@ def block_share(skyr, torch, w, prec_name, reps=50):
     own = torch.zeros(padded.shape[1:], dtype=torch.bool, device=dev)
     own[4:-4, 4:-4, 4:-4] = True
     shell = padded[:, ~own].contiguous()
-    out, vel = torch.zeros_like(padded), torch.zeros_like(padded)
     work = skyr.new_block_workspace(blk, prec, dev)
-    for _ in range(3):
-        skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, padded, shell, out, vel=vel, work=work,
-                         dt=w["dt"], want_sums=False)
-    torch.cuda.synchronize()
-    skyr.timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, padded, shell, out, vel=vel, work=work,
-                         dt=w["dt"], want_sums=False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms, cnt = skyr.timing_read()
-    skyr.timing_enable(False)
-    us = 1e3 * ms / max(cnt, 1)
+
+    def timed(phi, layout):
+        out, vel = torch.zeros_like(phi), torch.zeros_like(phi)
+        for _ in range(3):
+            skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, phi, shell, out, vel=vel, work=work,
+                             dt=w["dt"], want_sums=False, layout=layout)
+        torch.cuda.synchronize()
+        skyr.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            skyr.block_sweep(blk, prec, skyr.Model(w["m"]), skyr.BLOCK_STEP, phi, shell, out, vel=vel, work=work,
+                             dt=w["dt"], want_sums=False, layout=layout)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, cnt = skyr.timing_read()
+        skyr.timing_enable(False)
+        return 1e3 * ms / max(cnt, 1), 1e6 * wall / reps
+
+    us, call_us = timed(padded, None)
+    # the same block in padded, row-interleaved rows (skyr_block_sweep_padded)
+    layout = skyr.block_layout(blk, prec)
+    us_p, call_us_p = timed(skyr.to_padded(padded, layout), layout)
     # the block's own sites in I, per axis the overlap of [origin, origin + extent) with [2, n - 2)
     sites = 1
     for o, e in zip(origin, extent):
@@ -270,7 +277,9 @@ def block_share(skyr, torch, w, prec_name, reps=50):
     eb = 4 if prec_name == "f32" else 8
     return {"block": {"origin": list(origin), "extent": list(extent)}, "interior_sites": sites,
             "sweep_kernel_avg_us": us, "achieved_GBs": 16 * eb * sites / us / 1e3,
-            "call_us": 1e6 * wall / reps, "site_updates_per_s": sites / (us / 1e6)}
+            "call_us": call_us, "site_updates_per_s": sites / (us / 1e6),
+            "padded_rows": {"layout": {"lead": layout[0], "pitch": layout[1]}, "sweep_kernel_avg_us": us_p,
+                            "call_us": call_us_p, "site_updates_per_s": sites / (us_p / 1e6)}}
 
 
 def time_moments(skyr, torch, w, prec_name, reps=5):

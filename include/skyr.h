@@ -386,6 +386,24 @@ SKYR_API skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec
                                       void* phi, const void* shell, void* out, void* vel, skyr_block_sums* sums,
                                       void* work, void* stream);
 
+/* The block sweep on block fields stored in padded rows with the four components
+ * of a row one after the other: component A at padded site (x, y, z) (the
+ * indices of skyr_block_sites' box, P0 x P1 x P2) at element
+ * ((x P1 + y) 4 + A) pitch + lead + z, with lead >= 0 and pitch >= lead + P2
+ * (4 P0 P1 pitch elements within 4 GiB).  phi, out and vel take that layout;
+ * the shell buffer is as for skyr_block_sweep.  The elements outside
+ * [lead, lead + P2) of a row must be finite (zero, for instance) and are never
+ * written.  Results are bitwise those of skyr_block_sweep.  skyr_block_layout
+ * gives a lead and pitch that put the first tile column of the block's sweep on
+ * a 128-byte line, rows of whole lines (the padded rows of P2 = extent + 8
+ * elements otherwise straddle lines). */
+SKYR_API skyr_status skyr_block_sweep_padded(const skyr_block* blk, skyr_precision prec, const skyr_model* model,
+                                             int32_t mode, int32_t projected, double dt, int32_t redo,
+                                             int32_t renorm64, void* phi, const void* shell, void* out, void* vel,
+                                             skyr_block_sums* sums, void* work, int32_t lead, int32_t pitch,
+                                             void* stream);
+SKYR_API skyr_status skyr_block_layout(const skyr_block* blk, skyr_precision prec, int32_t* lead, int32_t* pitch);
+
 /* Energy parts, baryon number, virial and largest projected force of phi
  * (Sec. 2.1 eq. B0_components, Sec. 5.6 eq. Virial).  Synchronises `stream`. */
 SKYR_API skyr_status skyr_observables(const skyr_lattice* lat, skyr_precision prec, const skyr_model* model,

@@ -1404,10 +1404,17 @@ __device__ __forceinline__ long long shell_rank(int x, int y, int z, int P1, int
 // shell buffer.  Pass 1 (after pass 0): shell sites outside the lattice from the nearest
 // lattice site, which pass 0 or the own box has filled.
 template <typename T>
-__global__ void block_shell_kernel(T* __restrict__ phi, const T* __restrict__ shell, BlockGeo g, int pass)
+__global__ void block_shell_kernel(T* __restrict__ phi, const T* __restrict__ shell, BlockGeo g, int pass, int lead,
+                                   int pitch)
 {
     const long long N = g.sites(), S = g.shell();
     const int P1 = g.P[1], P2 = g.P[2];
+    // the stored element of component A at padded site (x, y, z): component-major arrays, or
+    // (pitch > 0) rows of `pitch` elements holding the four components one after the other
+    const auto at = [&](int A, int x, int y, int z) -> long long {
+        return pitch > 0 ? ((long long)((long long)x * P1 + y) * 4 + A) * pitch + lead + z
+                         : (long long)A * N + ((long long)x * P1 + y) * P2 + z;
+    };
     for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < N; s += (long long)gridDim.x * blockDim.x) {
         const int z = (int)(s % P2), y = (int)((s / P2) % P1), x = (int)(s / ((long long)P1 * P2));
         const int p[3] = {x, y, z};
@@ -1422,10 +1429,9 @@ __global__ void block_shell_kernel(T* __restrict__ phi, const T* __restrict__ sh
         if (own) continue;
         if (pass == 0 && inside) {
             const long long r = shell_rank(x, y, z, P1, P2, g.e[0], g.e[1], g.e[2]);
-            for (int A = 0; A < 4; ++A) phi[A * N + s] = shell[A * S + r];
+            for (int A = 0; A < 4; ++A) phi[at(A, x, y, z)] = shell[A * S + r];
         } else if (pass == 1 && !inside) {
-            const long long t = ((long long)q[0] * P1 + q[1]) * P2 + q[2];
-            for (int A = 0; A < 4; ++A) phi[A * N + s] = phi[A * N + t];
+            for (int A = 0; A < 4; ++A) phi[at(A, x, y, z)] = phi[at(A, q[0], q[1], q[2])];
         }
     }
 }
@@ -1487,13 +1493,26 @@ size_t skyr_block_workspace_bytes(const skyr_block* blk, skyr_precision prec)
     return block_work_bytes(g, prec);
 }
 
-skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const skyr_model* model, int32_t mode,
-                             int32_t projected, double dt, int32_t redo, int32_t renorm64, void* phi,
-                             const void* shell, void* out, void* vel, skyr_block_sums* sums, void* work, void* stream)
+}  // extern "C"
+
+namespace skyr {
+
+// skyr_block_sweep and skyr_block_sweep_padded (pitch > 0: the stored arrays hold rows of
+// `pitch` elements with the four components of a row one after the other, the padded
+// index z of a row at element lead + z)
+static skyr_status block_sweep_impl(const skyr_block* blk, skyr_precision prec, const skyr_model* model, int32_t mode,
+                                    int32_t projected, double dt, int32_t redo, int32_t renorm64, void* phi,
+                                    const void* shell, void* out, void* vel, skyr_block_sums* sums, void* work,
+                                    void* stream, int lead, int pitch)
 {
     BlockGeo g;
     skyr_status rc = block_geo(blk, g);
     if (rc != SKYR_OK) return rc;
+    if (pitch > 0) {
+        if (lead < 0 || pitch < (long long)lead + g.P[2]) return fail(SKYR_E_INVAL, "need lead >= 0 and pitch >= lead + P2");
+        if (4LL * g.P[0] * g.P[1] * pitch * (long long)elem_bytes(prec) >= (1LL << 32))
+            return fail(SKYR_E_INVAL, "padded block arrays too large for 32-bit offsets");
+    }
     rc = check_common(&blk->lattice, prec, model, phi, work);
     if (rc != SKYR_OK) return rc;
     if (model->form != SKYR_FORM_EXACT) return fail(SKYR_E_INVAL, "block sweeps use the exact-gradient form");
@@ -1514,10 +1533,10 @@ skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const s
         for (int pass = 0; pass < 2; ++pass) {
             if (prec == SKYR_F64)
                 hipLaunchKernelGGL(block_shell_kernel<double>, dim3(blocks), dim3(256), 0, s, (double*)phi,
-                                   (const double*)shell, g, pass);
+                                   (const double*)shell, g, pass, lead, pitch);
             else
                 hipLaunchKernelGGL(block_shell_kernel<float>, dim3(blocks), dim3(256), 0, s, (float*)phi,
-                                   (const float*)shell, g, pass);
+                                   (const float*)shell, g, pass, lead, pitch);
             SKYR_HIP(hipGetLastError());
         }
     }
@@ -1540,6 +1559,18 @@ skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const s
     a.tiles_y = L.tiles_y;
     a.zstart = L.zstart;
     a.xchunk = L.xchunk;
+    if (pitch > 0) {
+        // the same tiles over the same padded sites, each component within its quarter of a row
+        a.n2 = 4 * pitch;
+        a.cstride = pitch;
+        a.zlo = lead;
+        a.zhi = lead + g.P[2] - 1;
+        a.ilo[2] += lead;
+        a.ihi[2] += lead;
+        a.olo[2] += lead;
+        a.ohi[2] += lead;
+        a.zstart += lead;
+    }
     a.h = blk->lattice.h;
     a.m = model->m;
     a.m_y = model->m_y;
@@ -1582,6 +1613,43 @@ skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const s
         sums->power = o[5];
         sums->max_force = o[6];
     }
+    return SKYR_OK;
+}
+
+}  // namespace skyr
+
+extern "C" {
+
+skyr_status skyr_block_sweep(const skyr_block* blk, skyr_precision prec, const skyr_model* model, int32_t mode,
+                             int32_t projected, double dt, int32_t redo, int32_t renorm64, void* phi,
+                             const void* shell, void* out, void* vel, skyr_block_sums* sums, void* work, void* stream)
+{
+    return skyr::block_sweep_impl(blk, prec, model, mode, projected, dt, redo, renorm64, phi, shell, out, vel, sums,
+                                  work, stream, 0, 0);
+}
+
+skyr_status skyr_block_sweep_padded(const skyr_block* blk, skyr_precision prec, const skyr_model* model, int32_t mode,
+                                    int32_t projected, double dt, int32_t redo, int32_t renorm64, void* phi,
+                                    const void* shell, void* out, void* vel, skyr_block_sums* sums, void* work,
+                                    int32_t lead, int32_t pitch, void* stream)
+{
+    if (pitch <= 0) return fail(SKYR_E_INVAL, "pitch must be positive");
+    return skyr::block_sweep_impl(blk, prec, model, mode, projected, dt, redo, renorm64, phi, shell, out, vel, sums,
+                                  work, stream, lead, pitch);
+}
+
+skyr_status skyr_block_layout(const skyr_block* blk, skyr_precision prec, int32_t* lead, int32_t* pitch)
+{
+    BlockGeo g;
+    skyr_status rc = block_geo(blk, g);
+    if (rc != SKYR_OK) return rc;
+    if (prec != SKYR_F64 && prec != SKYR_F32_BULK) return fail(SKYR_E_INVAL, "unknown precision");
+    if (!lead || !pitch) return fail(SKYR_E_INVAL, "lead and pitch must be non-null");
+    // the first tile column of the block's sweep on a 128-byte line
+    const int line = 128 / (int)elem_bytes(prec);
+    const int zstart = g.empty ? 0 : plan_block(g, prec).zstart;
+    *lead = (line - zstart % line) % line;
+    *pitch = (*lead + g.P[2] + line - 1) / line * line;
     return SKYR_OK;
 }
 

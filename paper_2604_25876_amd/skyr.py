@@ -209,6 +209,12 @@ _SIGNATURES = {
     "skyr_block_sweep": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.POINTER(Model), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P, _P,
                                         _P, ctypes.POINTER(BlockSums), _P, _P]),
+    "skyr_block_sweep_padded": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.POINTER(Model),
+                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                               ctypes.c_int32, _P, _P, _P, _P, ctypes.POINTER(BlockSums), _P,
+                                               ctypes.c_int32, ctypes.c_int32, _P]),
+    "skyr_block_layout": (ctypes.c_int, [ctypes.POINTER(Block), ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]),
     "skyr_timing_enable": (None, [ctypes.c_int32]),
     "skyr_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -425,21 +431,32 @@ def new_block_workspace(blk: Block, prec: int, device="cuda"):
 
 def block_sweep(blk: Block, prec: int, model: Model, mode: int, phi, shell, out, vel=None, work=None,
                 projected: bool = False, dt: float = 0.0, redo: bool = False, renorm64: bool = False,
-                want_sums: bool = True, stream=None):
+                want_sums: bool = True, stream=None, layout: tuple[int, int] | None = None):
     """skyr_block_sweep: one sweep over a block's own interior sites (gradient or one
     kick-drift step) with its shell written from `shell`; returns the block's sums
-    (a dict) when want_sums, else None."""
-    shape = (4,) + blk.padded_shape
+    (a dict) when want_sums, else None.  With a layout (block_layout), phi, out and vel
+    are in the padded, row-interleaved layout (P0, P1, 4, pitch) of skyr_block_sweep_padded."""
+    shape = (4,) + blk.padded_shape if layout is None else blk.padded_shape[:2] + (4, int(layout[1]))
     dt_ = field_dtype(prec)
     if work is None or not work.is_cuda or work.numel() * work.element_size() < block_workspace_bytes(blk, prec):
         raise ValueError("a device workspace of block_workspace_bytes(blk, prec) bytes is required")
     sums = BlockSums()
-    _check(lib().skyr_block_sweep(ctypes.byref(blk), prec, ctypes.byref(model), int(mode), int(bool(projected)),
-                                  float(dt), int(bool(redo)), int(bool(renorm64)), _dev_ptr(phi, dt_, shape),
-                                  _dev_ptr(shell, dt_, (4, block_shell_sites(blk))), _dev_ptr(out, dt_, shape),
-                                  _dev_ptr(vel, dt_, shape), ctypes.byref(sums) if want_sums else None,
-                                  ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+    args = (ctypes.byref(blk), prec, ctypes.byref(model), int(mode), int(bool(projected)), float(dt),
+            int(bool(redo)), int(bool(renorm64)), _dev_ptr(phi, dt_, shape),
+            _dev_ptr(shell, dt_, (4, block_shell_sites(blk))), _dev_ptr(out, dt_, shape), _dev_ptr(vel, dt_, shape),
+            ctypes.byref(sums) if want_sums else None, ctypes.c_void_p(work.data_ptr()))
+    if layout is None:
+        _check(lib().skyr_block_sweep(*args, _stream(stream)))
+    else:
+        _check(lib().skyr_block_sweep_padded(*args, int(layout[0]), int(layout[1]), _stream(stream)))
     return sums.as_dict() if want_sums else None
+
+
+def block_layout(blk: Block, prec: int) -> tuple[int, int]:
+    """(lead, pitch): the padded, row-interleaved layout of block fields for skyr_block_sweep_padded."""
+    lead, pitch = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().skyr_block_layout(ctypes.byref(blk), prec, ctypes.byref(lead), ctypes.byref(pitch)))
+    return int(lead.value), int(pitch.value)
 
 
 def observables(lat: Lattice, prec: int, model: Model, phi, work, stream=None) -> dict:

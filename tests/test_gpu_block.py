@@ -266,3 +266,55 @@ def test_block_arguments_are_checked(skyr):
                          torch.zeros((4, skyr.block_shell_sites(corner)), dtype=torch.float64, device=DEV),
                          skyr.new_block_field(corner, 0, DEV), work=skyr.new_block_workspace(corner, 0, DEV))
     assert s["E"] == 0.0 and s["max_force"] == 0.0
+
+
+def _same(a, b):
+    """equal element by element, NaN where the other is NaN"""
+    return bool(((a == b) | (a.isnan() & b.isnan())).all())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mode", ["gradient", "step"])
+def test_block_sweep_padded_equals_dense(skyr, prec, mode):
+    """skyr_block_sweep_padded on the padded, row-interleaved copies of a block's buffers
+    (skyr_block_layout) writes what skyr_block_sweep writes, bit for bit, NaN where it
+    writes nothing, the same sums, and never the padding; for every block of a split."""
+    shape, cuts, h, dt = (37, 41, 45), ([17], [23], [20]), 0.21, 0.03
+    phi_full = random_unit_field(shape, 43, 0.4)
+    rng = np.random.default_rng(6)
+    vel_full = 0.3 * rng.standard_normal(phi_full.shape)
+    vel_full -= (vel_full * phi_full).sum(axis=0) * phi_full
+    if prec == 1:
+        phi_full = phi_full.astype(np.float32).astype(np.float64)
+        vel_full = vel_full.astype(np.float32).astype(np.float64)
+    lat = _lat(skyr, shape, h)
+    mdl = skyr.Model(*ALL)
+    step = mode == "step"
+    leads = set()
+    for ox, ex in _pieces(shape[0], cuts[0]):
+        for oy, ey in _pieces(shape[1], cuts[1]):
+            for oz, ez in _pieces(shape[2], cuts[2]):
+                B = Padded(shape, (ox, oy, oz), (ex, ey, ez))
+                blk = skyr.Block.of(lat, (ox, oy, oz), (ex, ey, ez))
+                bw = skyr.new_block_workspace(blk, prec, DEV)
+                layout = skyr.block_layout(blk, prec)
+                lead, pitch = layout
+                leads.add(lead)
+                phi, shell, out, vel = _block_inputs(skyr, B, phi_full, prec, vel_full if step else None)
+                pphi, pout = skyr.to_padded(phi, layout), skyr.to_padded(out, layout)
+                pvel = skyr.to_padded(vel, layout) if step else None
+                kw = dict(vel=vel, dt=dt) if step else dict(projected=True)
+                sd = skyr.block_sweep(blk, prec, mdl, skyr.BLOCK_STEP if step else skyr.BLOCK_GRADIENT, phi, shell, out,
+                                      work=bw, **kw)
+                kw = dict(vel=pvel, dt=dt) if step else dict(projected=True)
+                sp = skyr.block_sweep(blk, prec, mdl, skyr.BLOCK_STEP if step else skyr.BLOCK_GRADIENT, pphi, shell,
+                                      pout, work=bw, layout=layout, **kw)
+                assert sd == sp
+                P2 = blk.padded_shape[2]
+                assert _same(skyr.from_padded(pout, layout, P2), out)
+                assert _same(skyr.from_padded(pphi, layout, P2), phi)
+                if step:
+                    assert _same(skyr.from_padded(pvel, layout, P2), vel)
+                for t in (pphi, pout) + ((pvel,) if step else ()):
+                    assert not t[..., :lead].any() and not t[..., lead + P2:].any()
+    assert len(leads) >= 1
